@@ -1,0 +1,143 @@
+"""CPU model of the GPU schedule (test code only, not the oracle).
+
+The GPU library reaches the oracle's result in a different order:
+* blocked rounds over k-blocks of size BS (the paper's Section on data
+  locality: diagonal block, then its row and column, then the rest);
+* phase 2 written as a min-plus product against the already closed
+  diagonal block instead of an in-place k-sequential sweep;
+* phase 3 as a min-plus product of the column and row panels;
+* int32 sums formed by plain wrapping-free addition, with every value that
+  ends at or above 2^29 mapped back to INF afterwards.
+
+These tests check, on small graphs, that each of those choices gives
+exactly the oracle's distances and canonical predecessors, for many block
+sizes, ragged n and shuffled tile orders."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+import synth
+
+INF32 = pins.INF32
+NONE = np.iinfo(np.int32).max
+
+
+def lexmin_update(D, P, S, C, sat_inf):
+    """D,P <- lexmin((D,P), (S,C)); C is ignored where S is 'infinite'."""
+    better = (S < D) | ((S == D) & ~sat_inf & (C < P))
+    D[better] = S[better]
+    P[better] = C[better]
+
+
+def add_sat(a, b, saturating):
+    s = a.astype(np.int64) + b.astype(np.int64)
+    if saturating:
+        s = np.where((a == INF32) | (b == INF32), INF32, s)
+    return s
+
+
+def product_update(D, P, A, B, PB, saturating):
+    """D,P <- lexmin(D,P, min_k (A[:,k] + B[k,:], PB[k,:]))."""
+    for k in range(A.shape[1]):
+        S = add_sat(A[:, k:k + 1], B[k:k + 1, :], saturating)
+        C = np.broadcast_to(PB[k:k + 1, :], S.shape)
+        inf = S >= INF32 if saturating else S >= (1 << 29)
+        lexmin_update(D, P, S, C, inf)
+
+
+def close_tile(D, P, saturating):
+    """Sequential FW on a square tile, in place (phase 1)."""
+    m = D.shape[0]
+    for k in range(m):
+        a = D[:, k:k + 1].copy()
+        b = D[k:k + 1, :].copy()
+        pb = P[k:k + 1, :].copy()
+        S = add_sat(a, b, saturating)
+        inf = S >= INF32 if saturating else S >= (1 << 29)
+        lexmin_update(D, P, S, np.broadcast_to(pb, S.shape), inf)
+
+
+def blocked(W, bs, rng, saturating=True, phase2_product=True):
+    n = W.shape[0]
+    D = W.astype(np.int64)
+    P = np.where((W != INF32) & ~np.eye(n, dtype=bool),
+                 np.arange(n)[:, None], NONE).astype(np.int64)
+    R = (n + bs - 1) // bs
+    blk = [slice(r * bs, min(n, (r + 1) * bs)) for r in range(R)]
+    for r in range(R):
+        K = blk[r]
+        close_tile(D[K, K], P[K, K], saturating)
+        others = [q for q in range(R) if q != r]
+        rng.shuffle(others)
+        for q in others:
+            J = blk[q]
+            if phase2_product:
+                Bold, PBold = D[K, J].copy(), P[K, J].copy()
+                product_update(D[K, J], P[K, J], D[K, K], Bold, PBold, saturating)
+                Aold = D[J, K].copy()
+                product_update(D[J, K], P[J, K], Aold, D[K, K], P[K, K], saturating)
+            else:  # the paper's in-place k-sequential block update
+                for k in range(K.stop - K.start):
+                    kk = K.start + k
+                    S = add_sat(D[K, kk:kk + 1], D[kk:kk + 1, J], saturating)
+                    C = np.broadcast_to(P[kk:kk + 1, J], S.shape).copy()
+                    inf = S >= INF32 if saturating else S >= (1 << 29)
+                    lexmin_update(D[K, J], P[K, J], S, C, inf)
+                for k in range(K.stop - K.start):
+                    kk = K.start + k
+                    S = add_sat(D[J, kk:kk + 1], D[kk:kk + 1, K], saturating)
+                    C = np.broadcast_to(P[kk:kk + 1, K], S.shape).copy()
+                    inf = S >= INF32 if saturating else S >= (1 << 29)
+                    lexmin_update(D[J, K], P[J, K], S, C, inf)
+        tiles = [(a, b) for a in others for b in others]
+        rng.shuffle(tiles)
+        for a, b in tiles:
+            I, J = blk[a], blk[b]
+            product_update(D[I, J], P[I, J], D[I, K], D[K, J], P[K, J], saturating)
+    if not saturating:
+        D = np.where(D >= (1 << 29), INF32, D)
+    P = np.where((P == NONE) | (D == INF32) | np.eye(n, dtype=bool), -1, P)
+    return D.astype(np.int32), P.astype(np.int32)
+
+
+@pytest.mark.parametrize("n,bs", [(1, 4), (2, 1), (7, 3), (23, 5), (40, 8), (41, 16), (37, 37), (50, 64)])
+@pytest.mark.parametrize("kind", ["dense", "sparse", "potential", "ties"])
+def test_blocked_matches_oracle(orc, n, bs, kind):
+    rng = np.random.default_rng(n * 131 + bs)
+    if kind == "dense":
+        W = pins.random_graph(rng, n, 0.5, 1, 1000)
+    elif kind == "sparse":
+        W = pins.random_graph(rng, n, 0.06, 1, 1000)
+    elif kind == "ties":
+        W = pins.random_graph(rng, n, 0.3, 1, 2)
+    else:
+        W = synth.potential_int32(n, p=0.15, seed=n + bs)
+    D0, P0, st = orc.fw(W, pred=True)
+    assert st == oracle.OK
+    for sat in (True, False):
+        D, P = blocked(W, bs, rng, saturating=sat)
+        assert np.array_equal(D, D0)
+        assert np.array_equal(P, P0)
+
+
+@pytest.mark.parametrize("n,bs", [(30, 7), (33, 8)])
+def test_paper_phase2_equals_product_phase2(orc, n, bs):
+    rng = np.random.default_rng(9)
+    W = pins.random_graph(rng, n, 0.2, 1, 5)
+    D1, P1 = blocked(W, bs, rng, phase2_product=True)
+    D2, P2 = blocked(W, bs, rng, phase2_product=False)
+    assert np.array_equal(D1, D2) and np.array_equal(P1, P2)
+    D0, P0, _ = orc.fw(W, pred=True)
+    assert np.array_equal(D1, D0) and np.array_equal(P1, P0)
+
+
+def test_plain_add_threshold_large_potential(orc):
+    """Negative weights, plain addition plus the 2^29 threshold == saturating."""
+    n = 120
+    W = synth.potential_int32(n, p=0.012, seed=5)
+    D0, _, _ = orc.fw(W)
+    rng = np.random.default_rng(0)
+    D, _ = blocked(W, 32, rng, saturating=False)
+    assert np.array_equal(D, D0)
+    assert (D0 == INF32).any()
