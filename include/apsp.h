@@ -1,0 +1,220 @@
+/*
+ * apsp.h — all-pairs shortest paths by blocked Floyd–Warshall on AMD
+ * Instinct MI355X (gfx950).  C ABI of libapsp.so.
+ *
+ * The method (Rucci, De Giusti, Naiouf, "Blocked All-Pairs Shortest Paths
+ * Algorithm on Intel Xeon Phi KNL Processor: A Case Study"):
+ *   - Section "Floyd-Warshall Algorithm": the input is an N x N matrix D
+ *     holding the direct distance between every pair of nodes; after N
+ *     iterations (iteration k relaxes every pair through node k) D holds the
+ *     shortest distances, and a second matrix P is produced when paths must
+ *     be reconstructed.
+ *   - Section "Data Locality": D is split into BS x BS blocks and processed
+ *     in R = N/BS rounds; each round first closes the diagonal block, then
+ *     the rest of its block row and block column, then every other block.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *   Layout     dist is row-major n x n, contiguous (leading dimension n).
+ *              It is read as the weight matrix and overwritten in place by
+ *              the distance matrix.  pred (optional) is row-major n x n
+ *              int32, output only.
+ *   Weights    int32: "no edge" is APSP_INF_INT32; float32: +inf.  The
+ *              diagonal must be 0.  int32 weights must satisfy
+ *              |w| <= apsp_weight_bound(n) so that no path length gets near
+ *              the sentinel.  float32 weights must not be NaN or -inf.
+ *   Output     dist(i,j) is the least total weight over all i->j paths,
+ *              APSP_INF_INT32 / +inf when j is unreachable from i.
+ *              pred(i,j) is the vertex just before j on a shortest i->j
+ *              path; when several shortest paths end differently, the
+ *              smallest such vertex.  pred(i,i) = pred(i,j unreachable) =
+ *              APSP_NO_PRED.  (The paper's P records the last intermediate
+ *              node added, which depends on the evaluation order; this
+ *              canonical form does not, so blocked and unblocked schedules
+ *              agree exactly.)
+ *   Arithmetic int32 results are exact.  float32 results are exact when the
+ *              weights are integers (every partial sum is then an integer
+ *              well below 2^24); otherwise sums are rounded to float32 in
+ *              the blocked order, within a relative 1e-6 of the exact value
+ *              for short-hop paths.
+ *   Memory     Pointers named dist/pred/packed_* are DEVICE pointers owned by
+ *              the caller.  The library may allocate internal device
+ *              workspace (kept per device and reused; released by
+ *              apsp_release_workspace).
+ *   Streams    apsp_solve* and apsp_batch_plan_execute enqueue work on the
+ *              given hipStream_t (NULL = the legacy default stream) and
+ *              return without waiting.  Argument errors are detected on the
+ *              host before anything is enqueued.  Data-dependent outcomes
+ *              (invalid weights, negative cycles) are written, when asked
+ *              for, to a device status word (apsp_options_t.d_status).
+ *   Errors     Functions never abort and never throw across the ABI.
+ *              APSP_ERROR_HIP means a HIP runtime call failed; its code is
+ *              available from apsp_last_hip_error() on the calling thread.
+ *   Threads    apsp_solve* may be called concurrently from several threads
+ *              on different streams.  Server calls are thread-safe.
+ */
+#ifndef APSP_H
+#define APSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define APSP_INF_INT32 1073741823 /* INT32_MAX / 2 : no edge / unreachable (int32) */
+#define APSP_NO_PRED (-1)
+
+typedef enum { APSP_INT32 = 0, APSP_FLOAT32 = 1 } apsp_dtype_t;
+
+typedef enum {
+    APSP_SUCCESS = 0,
+    APSP_ERROR_INVALID_ARGUMENT = 1, /* bad pointer, size, dtype or option (host check) */
+    APSP_ERROR_INVALID_VALUE = 2,    /* weights violate the preconditions above */
+    APSP_ERROR_NEGATIVE_CYCLE = 3,   /* a cycle of negative total weight exists */
+    APSP_ERROR_OUT_OF_MEMORY = 4,    /* device/host allocation or HBM budget */
+    APSP_ERROR_HIP = 5,              /* a HIP runtime call failed */
+    APSP_ERROR_QUEUE_FULL = 6,       /* server: admission queue is full */
+    APSP_ERROR_NOT_READY = 7,        /* server: request still running */
+    APSP_ERROR_CANCELLED = 8,        /* server: request cancelled or server destroyed */
+    APSP_ERROR_TIMEOUT = 9,          /* server: wait timed out */
+    APSP_ERROR_UNKNOWN_TICKET = 10   /* server: no such (unreleased) request */
+} apsp_status_t;
+
+/* Short human-readable name of a status code (static storage). */
+const char *apsp_status_string(apsp_status_t status);
+
+/* hipError_t of the last failed HIP call made by the library on this thread. */
+int apsp_last_hip_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int apsp_version(void);
+
+/* Largest |w| accepted for int32 weights at size n: floor((2^28-1)/(n-1)).
+ * Keeps every path length within +-2^28 and every intermediate sum of the
+ * kernels free of overflow. */
+int64_t apsp_weight_bound(int64_t n);
+
+/* ------------------------------------------------------------------ single
+ *
+ * apsp_solve: one graph, blocked Floyd–Warshall (the paper's Sections
+ * "Floyd-Warshall Algorithm" and "Data Locality"), three phases per round:
+ *   phase 1  close the BS x BS diagonal block (k sequential, one workgroup)
+ *   phase 2  update the block row and block column against it
+ *   phase 3  min-plus update of every remaining block from its row's and
+ *            column's panel blocks.
+ *   dist   device, n*n elements of dtype, in place (weights in, distances out)
+ *   pred   device, n*n int32 or NULL (no predecessors)
+ *   n      number of vertices, 0 <= n <= 65536 (0 is a no-op)
+ * Returns APSP_SUCCESS once the work is enqueued.
+ */
+apsp_status_t apsp_solve(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype,
+                         hipStream_t stream);
+
+typedef struct {
+    int32_t validate;      /* nonzero: check the weight preconditions on the device first;
+                              on failure the solve is skipped and d_status gets
+                              APSP_ERROR_INVALID_VALUE (dist/pred unchanged) */
+    int32_t block_size;    /* 0 = automatic; else 64, 128 or 256 (256: distances only) */
+    int32_t use_graph;     /* nonzero: capture the round sequence once per shape into a
+                              hipGraph and replay it (fewer launches for small n) */
+    int32_t reserved;
+    int32_t *d_status;     /* device int32 or NULL: receives APSP_SUCCESS,
+                              APSP_ERROR_INVALID_VALUE or APSP_ERROR_NEGATIVE_CYCLE */
+} apsp_options_t;
+
+/* apsp_solve with options (NULL options = defaults = apsp_solve). */
+apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype,
+                            hipStream_t stream, const apsp_options_t *options);
+
+/* Release the calling device's internal workspace and cached graphs.
+ * Must not overlap with solves in flight on that device. */
+apsp_status_t apsp_release_workspace(void);
+
+/* ----------------------------------------------------------------- batched
+ *
+ * Many independent graphs of uneven size, solved by one persistent fused
+ * launch that runs all three phases of every graph (each workgroup pulls
+ * graphs, largest first, from a device work counter).
+ *
+ *   ns          host, batch sizes, 1 <= ns[b] <= 1024
+ *   offsets     host, element offset of graph b in the packed buffers;
+ *               offsets[b] % 4 == 0 and graphs must not overlap
+ *   packed_dist device, graph b occupies [offsets[b], offsets[b] + ns[b]^2),
+ *               row-major with leading dimension ns[b]; in place
+ *   packed_pred device int32, same offsets, or NULL (plan made without pred)
+ * A plan holds the device copy of the metadata and the tuned tile choice;
+ * it may be executed any number of times (also under stream capture) and
+ * must outlive the work it enqueued.
+ */
+typedef struct apsp_batch_plan apsp_batch_plan_t;
+
+apsp_status_t apsp_batch_plan_create(const int32_t *ns, const int64_t *offsets, int32_t batch,
+                                     apsp_dtype_t dtype, int32_t want_pred,
+                                     apsp_batch_plan_t **out_plan);
+apsp_status_t apsp_batch_plan_execute(const apsp_batch_plan_t *plan, void *packed_dist,
+                                      int32_t *packed_pred, hipStream_t stream);
+apsp_status_t apsp_batch_plan_destroy(apsp_batch_plan_t *plan);
+
+/* create + execute; the plan is released once the stream reaches it. */
+apsp_status_t apsp_solve_batched(void *packed_dist, int32_t *packed_pred, const int32_t *ns,
+                                 const int64_t *offsets, int32_t batch, apsp_dtype_t dtype,
+                                 hipStream_t stream);
+
+/* ------------------------------------------------------------------ server
+ *
+ * A request loop on one GPU: requests (host weight matrices) are copied
+ * into library-owned device slots when the HBM budget and the in-flight
+ * limit allow, solved with their work overlapping other requests' work on
+ * the device (small graphs are coalesced into batched launches), and their
+ * distance/predecessor matrices stay resident until released.
+ */
+typedef struct apsp_server apsp_server_t;
+
+typedef struct {
+    int64_t hbm_budget_bytes; /* device bytes the server may hold (0 = 1/2 of free memory) */
+    int32_t max_inflight;     /* requests resident at once (0 = 64) */
+    int32_t n_streams;        /* HIP streams used for large requests (0 = 4) */
+    int32_t max_queue;        /* pending requests before submit fails (0 = 4096) */
+    int32_t batch_max_n;      /* requests with n <= this are coalesced (0 = 512) */
+} apsp_server_config_t;
+
+typedef struct {
+    const void *weights; /* host, n*n elements of dtype, row-major; copied during submit */
+    int64_t n;
+    apsp_dtype_t dtype;
+    int32_t want_pred;
+} apsp_request_t;
+
+typedef struct {
+    int64_t submitted, completed, failed, cancelled;
+    int64_t queued, inflight;
+    int64_t bytes_in_use;
+    double p50_latency_ms, p99_latency_ms; /* submit -> result ready, completed requests */
+    double solves_per_s;                   /* completed / (last completion - first submit) */
+} apsp_server_stats_t;
+
+apsp_status_t apsp_server_create(const apsp_server_config_t *config, apsp_server_t **out);
+apsp_status_t apsp_server_submit(apsp_server_t *server, const apsp_request_t *request,
+                                 uint64_t *ticket);
+apsp_status_t apsp_server_poll(apsp_server_t *server, uint64_t ticket);
+apsp_status_t apsp_server_wait(apsp_server_t *server, uint64_t ticket, int64_t timeout_us);
+/* Device pointers of a finished request's resident results (valid until release). */
+apsp_status_t apsp_server_result(apsp_server_t *server, uint64_t ticket, const void **d_dist,
+                                 const int32_t **d_pred);
+/* Copy a finished request's results to host memory (h_pred may be NULL). */
+apsp_status_t apsp_server_copy_result(apsp_server_t *server, uint64_t ticket, void *h_dist,
+                                      int32_t *h_pred);
+apsp_status_t apsp_server_release(apsp_server_t *server, uint64_t ticket);
+apsp_status_t apsp_server_stats(apsp_server_t *server, apsp_server_stats_t *stats);
+/* Cancels pending and running requests (their tickets report CANCELLED) and frees all. */
+apsp_status_t apsp_server_destroy(apsp_server_t *server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APSP_H */

@@ -1,0 +1,163 @@
+"""MI355X-native blocked Floyd–Warshall all-pairs shortest paths.
+
+Thin ctypes binding over ``libapsp.so`` (C ABI declared in
+``include/apsp.h``).  Every step of a solve runs in the library's HIP
+kernels; this module only turns torch tensors into device pointers and the
+current torch stream into a ``hipStream_t``.  There is no fallback: if the
+library is missing, ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG_DIR, "libapsp.so")
+
+INF_INT32 = 1073741823
+NO_PRED = -1
+INT32, FLOAT32 = 0, 1
+
+STATUS = {
+    0: "SUCCESS", 1: "INVALID_ARGUMENT", 2: "INVALID_VALUE", 3: "NEGATIVE_CYCLE",
+    4: "OUT_OF_MEMORY", 5: "HIP", 6: "QUEUE_FULL", 7: "NOT_READY", 8: "CANCELLED",
+    9: "TIMEOUT", 10: "UNKNOWN_TICKET",
+}
+SUCCESS, INVALID_ARGUMENT, INVALID_VALUE, NEGATIVE_CYCLE, OUT_OF_MEMORY, HIP_ERROR, \
+    QUEUE_FULL, NOT_READY, CANCELLED, TIMEOUT, UNKNOWN_TICKET = range(11)
+
+
+class APSPError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        msg = f"{where}: {STATUS.get(status, status)}"
+        if status == HIP_ERROR and _lib is not None:
+            msg += f" (hipError {_lib.apsp_last_hip_error()})"
+        super().__init__(msg)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("validate", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("d_status", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libapsp.so (built by ``python -m paper_1811_01201_amd._build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1811_01201_amd._build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+        L.apsp_solve.argtypes = [vp, vp, i64, c_int, vp]
+        L.apsp_solve.restype = c_int
+        L.apsp_solve_ex.argtypes = [vp, vp, i64, c_int, vp, ctypes.POINTER(Options)]
+        L.apsp_solve_ex.restype = c_int
+        L.apsp_status_string.argtypes = [c_int]
+        L.apsp_status_string.restype = ctypes.c_char_p
+        L.apsp_last_hip_error.restype = c_int
+        L.apsp_version.restype = c_int
+        L.apsp_weight_bound.argtypes = [i64]
+        L.apsp_weight_bound.restype = i64
+        L.apsp_release_workspace.restype = c_int
+        _bind_optional(L)
+        _lib = L
+    return _lib
+
+
+def _bind_optional(L):
+    """Signatures of the batched and server entry points."""
+    vp, i64, i32, c_int, u64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                                ctypes.c_uint64)
+    table = {
+        "apsp_batch_plan_create": ([vp, vp, i32, c_int, i32, ctypes.POINTER(vp)], c_int),
+        "apsp_batch_plan_execute": ([vp, vp, vp, vp], c_int),
+        "apsp_batch_plan_destroy": ([vp], c_int),
+        "apsp_solve_batched": ([vp, vp, vp, vp, i32, c_int, vp], c_int),
+        "apsp_server_create": ([vp, ctypes.POINTER(vp)], c_int),
+        "apsp_server_submit": ([vp, vp, ctypes.POINTER(u64)], c_int),
+        "apsp_server_poll": ([vp, u64], c_int),
+        "apsp_server_wait": ([vp, u64, i64], c_int),
+        "apsp_server_result": ([vp, u64, ctypes.POINTER(vp), ctypes.POINTER(vp)], c_int),
+        "apsp_server_copy_result": ([vp, u64, vp, vp], c_int),
+        "apsp_server_release": ([vp, u64], c_int),
+        "apsp_server_stats": ([vp, vp], c_int),
+        "apsp_server_destroy": ([vp], c_int),
+    }
+    for name, (args, res) in table.items():
+        f = getattr(L, name, None)
+        if f is not None:
+            f.argtypes = args
+            f.restype = res
+
+
+def status_string(st: int) -> str:
+    return lib().apsp_status_string(st).decode()
+
+
+def weight_bound(n: int) -> int:
+    return int(lib().apsp_weight_bound(n))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.int32:
+        return INT32
+    if t.dtype == torch.float32:
+        return FLOAT32
+    raise TypeError(f"dist must be int32 or float32, got {t.dtype}")
+
+
+def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, status=None,
+          stream=None, check=True) -> int:
+    """Solve APSP in place on a square device tensor.
+
+    dist   : torch.Tensor [n, n] int32/float32 on the GPU, contiguous (weights in,
+             distances out).
+    pred   : optional torch.Tensor [n, n] int32 on the same device (output).
+    status : optional torch.Tensor [1] int32 on the device, receives the
+             data-dependent status (required with validate=True).
+    Returns the host status of the enqueue (raises APSPError unless check=False).
+    """
+    assert dist.dim() == 2 and dist.shape[0] == dist.shape[1], "dist must be square"
+    assert dist.is_cuda and dist.is_contiguous()
+    n = dist.shape[0]
+    pp = None
+    if pred is not None:
+        import torch
+        assert pred.dtype == torch.int32 and pred.is_cuda and pred.is_contiguous()
+        assert tuple(pred.shape) == (n, n)
+        pp = pred.data_ptr()
+    opt = Options(int(validate), int(block_size), int(use_graph), 0,
+                  status.data_ptr() if status is not None else None)
+    st = lib().apsp_solve_ex(dist.data_ptr(), pp, n, _dtype_code(dist), _stream_ptr(stream),
+                             ctypes.byref(opt))
+    if check and st != SUCCESS:
+        raise APSPError(st, "apsp_solve_ex")
+    return st
+
+
+def solve_raw(dist_ptr, pred_ptr, n, dtype_code, stream_ptr, options: Options | None = None) -> int:
+    """Direct call with raw integers (used by the ABI tests)."""
+    L = lib()
+    if options is None:
+        return L.apsp_solve(dist_ptr, pred_ptr, n, dtype_code, stream_ptr)
+    return L.apsp_solve_ex(dist_ptr, pred_ptr, n, dtype_code, stream_ptr, ctypes.byref(options))
+
+
+def release_workspace() -> None:
+    st = lib().apsp_release_workspace()
+    if st != SUCCESS:
+        raise APSPError(st, "apsp_release_workspace")

@@ -1,0 +1,267 @@
+// Internal definitions shared by the libapsp translation units (never
+// installed; the public interface is include/apsp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "apsp.h"
+
+namespace apsp {
+
+constexpr int32_t kInf32 = APSP_INF_INT32;
+// int32 results at or above this are "unreachable" once a solve is done:
+// reachable distances stay within +-2^28 (weight bound), while any sum that
+// involved the INF sentinel stays above INF - 2 * 2^28 > 2^29.
+constexpr int32_t kFakeThreshold = 1 << 29;
+constexpr int kMaxN = 65536;
+
+// ---------------------------------------------------------------------------
+// Arithmetic policies.  Each supplies the element type T, the number of
+// elements per 16-byte vector (VW), the path-sum operator and the minimum,
+// and strip(): the transform applied to a left operand (a D(i,k) value)
+// before it is added to a right operand (a D(k,j) value).
+//
+// Key mode carries distance and predecessor together in one double:
+//   key = d * 2^S + p,   0 <= p < 2^S (p = 2^S - 1 means "none"),
+// an exact integer (|key| < 2^53), +inf when unreachable.  Then
+//   strip(key_ik) + key_kj = (d_ik + d_kj) * 2^S + p_kj
+// is the key of the concatenated path (its last hop is the k->j path's),
+// and min over keys is the lexicographic (distance, predecessor) minimum,
+// i.e. exactly the canonical predecessor rule.
+// ---------------------------------------------------------------------------
+// relax2(c, a0, b0, a1, b1) = min(c, a0 + b0, a1 + b1): two k-steps of one
+// element.  For 32-bit types the three-input minimum is written as one
+// v_min3 instruction; left to itself the compiler re-associates chains of
+// these minima into 3 two/three-input minima per 4 updates instead of 2.
+struct ArI32 {
+    using T = int32_t;
+    static constexpr int VW = 4;
+    // clamp-saturating add: never wraps, even with negative cycles
+    __device__ __forceinline__ T add(T a, T b) const { return __builtin_elementwise_add_sat(a, b); }
+    __device__ __forceinline__ T mn(T a, T b) const { return a < b ? a : b; }
+    __device__ __forceinline__ T strip(T a) const { return a; }
+    __device__ __forceinline__ T relax2(T c, T a0, T b0, T a1, T b1) const {
+        const T s0 = add(a0, b0), s1 = add(a1, b1);
+        T r;
+        asm("v_min3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(c), "v"(s0), "v"(s1));
+        return r;
+    }
+    // one step, kept as its own instruction (no fusion across steps)
+    __device__ __forceinline__ T relax1(T c, T a, T b) const {
+        T r = mn(c, add(a, b));
+        asm("" : "+v"(r));  // materialise this step's value: no fusion across steps
+        return r;
+    }
+};
+
+struct ArF32 {
+    using T = float;
+    static constexpr int VW = 4;
+    __device__ __forceinline__ T add(T a, T b) const { return a + b; }
+    __device__ __forceinline__ T mn(T a, T b) const { return __builtin_fminf(a, b); }
+    __device__ __forceinline__ T strip(T a) const { return a; }
+    __device__ __forceinline__ T relax2(T c, T a0, T b0, T a1, T b1) const {
+        const T s0 = a0 + b0, s1 = a1 + b1;
+        T r;
+        asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(c), "v"(s0), "v"(s1));
+        return r;
+    }
+    __device__ __forceinline__ T relax1(T c, T a, T b) const {
+        T r = mn(c, add(a, b));
+        asm("" : "+v"(r));  // materialise this step's value: no fusion across steps
+        return r;
+    }
+};
+
+struct ArKey {
+    using T = double;
+    static constexpr int VW = 2;
+    int S;  // predecessor bits
+    __device__ __forceinline__ T add(T a, T b) const { return a + b; }
+    __device__ __forceinline__ T mn(T a, T b) const { return __builtin_fmin(a, b); }
+    __device__ __forceinline__ T strip(T a) const {
+        return __builtin_ldexp(__builtin_floor(__builtin_ldexp(a, -S)), S);
+    }
+    __device__ __forceinline__ T relax2(T c, T a0, T b0, T a1, T b1) const {
+        return mn(mn(c, a0 + b0), a1 + b1);
+    }
+    __device__ __forceinline__ T relax1(T c, T a, T b) const {
+        T r = mn(c, add(a, b));
+        asm("" : "+v"(r));  // materialise this step's value: no fusion across steps
+        return r;
+    }
+};
+
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<int32_t> { using type = int4; };
+template <>
+struct Vec16<float> { using type = float4; };
+template <>
+struct Vec16<double> { using type = double2; };
+
+template <class T>
+__device__ __forceinline__ void ld16(const T *p, T *out) {
+    using V = typename Vec16<T>::type;
+    V v = *reinterpret_cast<const V *>(p);
+    __builtin_memcpy(out, &v, 16);
+}
+template <class T>
+__device__ __forceinline__ void st16(T *p, const T *in) {
+    using V = typename Vec16<T>::type;
+    V v;
+    __builtin_memcpy(&v, in, 16);
+    *reinterpret_cast<V *>(p) = v;
+}
+
+// ---------------------------------------------------------------------------
+// One workgroup's min-plus tile update
+//     C[MT x NT] <- min(C, A[MT x K] (x) B[K x NT]),  (x) = (min, add)
+// with C at (crow, ccol), A at (crow, k0), B at (k0, ccol) of the same
+// row-major matrix D (leading dimension ld, every row 16-byte aligned).
+//
+// Thread (ty, tx) keeps a TM x TN block of C in registers: rows
+// ty + TY*m (interleaved, so the A reads of one wavefront fall in distinct
+// LDS banks) and columns g*(NT/GN) + tx*VW + e (16-byte groups, so a
+// wavefront's B reads are contiguous).  A and B are staged through LDS in
+// KC-wide k-chunks with 16-byte global loads, double buffered: chunk c+1 is
+// fetched into registers while chunk c is consumed, one barrier per chunk.
+// Two k-steps are fused per update so integer/float32 minima become
+// three-input minima.
+//
+// In-place safety: the tile reads A and B only from global memory before it
+// writes C, and C is written once at the end, so A or B may alias C when
+// the workgroup owns every C element that its reads could see (the panel
+// updates use a tile that spans the whole k-block in that direction).
+// ---------------------------------------------------------------------------
+template <class Ar, int MT, int NT, int KC, int TM, int TN>
+struct TileProduct {
+    using T = typename Ar::T;
+    static constexpr int VW = Ar::VW;
+    static constexpr int TX = NT / TN;
+    static constexpr int TY = MT / TM;
+    static constexpr int NTH = TX * TY;
+    static constexpr int GN = TN / VW;        // 16-byte column groups per thread
+    static constexpr int GSTRIDE = NT / GN;   // column distance between groups
+    static constexpr int LDA = KC + VW;       // padded LDS row of an A chunk
+    static constexpr int NA = MT * KC / VW;   // 16-byte vectors per A chunk
+    static constexpr int NB = KC * NT / VW;   // 16-byte vectors per B chunk
+    static constexpr int PA = (NA + NTH - 1) / NTH;
+    static constexpr int PB = (NB + NTH - 1) / NTH;
+    static_assert(TN % VW == 0 && GSTRIDE == TX * VW, "column groups must tile NT");
+    static_assert(KC % VW == 0 && VW % 2 == 0, "k-chunk must be whole vectors");
+
+    struct Smem {
+        T a[2][MT * LDA];
+        T b[2][KC * NT];
+    };
+
+    // A chunk from Abase (= &D[crow][kk]), B chunk from Bbase (= &D[kk][ccol]);
+    // per-thread offsets are 32-bit so the loads use a scalar base address.
+    __device__ __forceinline__ static void load_chunk(const T *__restrict__ Abase,
+                                                      const T *__restrict__ Bbase, uint32_t ld,
+                                                      T (&ra)[PA][VW], T (&rb)[PB][VW]) {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int v = tid + NTH * i;
+            if (NA % NTH == 0 || v < NA) {
+                const uint32_t row = v / (KC / VW), cv = v % (KC / VW);
+                ld16(Abase + (row * ld + cv * VW), ra[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int v = tid + NTH * i;
+            if (NB % NTH == 0 || v < NB) {
+                const uint32_t row = v / (NT / VW), cv = v % (NT / VW);
+                ld16(Bbase + (row * ld + cv * VW), rb[i]);
+            }
+        }
+    }
+
+    __device__ __forceinline__ static void store_chunk(Smem &sm, int buf, const Ar &ar, T (&ra)[PA][VW],
+                                       T (&rb)[PB][VW]) {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int v = tid + NTH * i;
+            if (NA % NTH == 0 || v < NA) {
+                const int row = v / (KC / VW), cv = v % (KC / VW);
+                T t[VW];
+#pragma unroll
+                for (int e = 0; e < VW; ++e) t[e] = ar.strip(ra[i][e]);
+                st16(&sm.a[buf][row * LDA + cv * VW], t);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int v = tid + NTH * i;
+            if (NB % NTH == 0 || v < NB) {
+                const int row = v / (NT / VW), cv = v % (NT / VW);
+                st16(&sm.b[buf][row * NT + cv * VW], rb[i]);
+            }
+        }
+    }
+
+    __device__ __forceinline__ static void run(Smem &sm, T *__restrict__ D, int64_t ld64, int64_t crow,
+                                               int64_t ccol, int64_t k0, int kcount, const Ar &ar) {
+        const int tid = threadIdx.x;
+        const int tx = tid % TX, ty = tid / TX;
+        const uint32_t ld = (uint32_t)ld64;  // row offsets inside one tile fit in 32 bits
+        T *const Cbase = D + crow * ld64 + ccol;
+        const T *const Abase = D + crow * ld64 + k0;
+        const T *const Bbase = D + k0 * ld64 + ccol;
+        const uint32_t coff = (uint32_t)ty * ld + (uint32_t)tx * VW;
+        T c[TM][TN];
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+#pragma unroll
+            for (int g = 0; g < GN; ++g)
+                ld16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
+
+        T ra[PA][VW], rb[PB][VW];
+        const int nch = kcount / KC;
+        load_chunk(Abase, Bbase, ld, ra, rb);
+        store_chunk(sm, 0, ar, ra, rb);
+        __syncthreads();
+        for (int ch = 0; ch < nch; ++ch) {
+            const int buf = ch & 1;
+            const bool more = ch + 1 < nch;
+            if (more) load_chunk(Abase + (ch + 1) * KC, Bbase + (uint32_t)((ch + 1) * KC) * ld, ld, ra, rb);
+            const T *As = sm.a[buf];
+            const T *Bs = sm.b[buf];
+#pragma unroll 2
+            for (int kg = 0; kg < KC; kg += VW) {
+                T a[TM][VW];
+#pragma unroll
+                for (int m = 0; m < TM; ++m) ld16(&As[(ty + TY * m) * LDA + kg], a[m]);
+#pragma unroll
+                for (int kk = 0; kk < VW; kk += 2) {
+                    T b0[TN], b1[TN];
+#pragma unroll
+                    for (int g = 0; g < GN; ++g) {
+                        ld16(&Bs[(kg + kk) * NT + g * GSTRIDE + tx * VW], &b0[g * VW]);
+                        ld16(&Bs[(kg + kk + 1) * NT + g * GSTRIDE + tx * VW], &b1[g * VW]);
+                    }
+#pragma unroll
+                    for (int m = 0; m < TM; ++m)
+#pragma unroll
+                        for (int n = 0; n < TN; ++n)
+                            c[m][n] = ar.relax2(c[m][n], a[m][kk], b0[n], a[m][kk + 1], b1[n]);
+                }
+            }
+            if (more) store_chunk(sm, buf ^ 1, ar, ra, rb);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+#pragma unroll
+            for (int g = 0; g < GN; ++g)
+                st16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
+    }
+};
+
+}  // namespace apsp

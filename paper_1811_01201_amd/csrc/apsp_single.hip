@@ -1,0 +1,517 @@
+// Single-graph blocked Floyd–Warshall for gfx950.
+//
+// The round structure follows the paper's Section "Data Locality": for each
+// k-block r the diagonal block is closed first (phase 1), then the rest of
+// block row r and block column r (phase 2), then every other block from its
+// row's and column's panel blocks (phase 3).  Phase 2 is written here as a
+// min-plus product against the closed diagonal block (a path from the block
+// row to any vertex leaves block r for the last time at some k in block r),
+// which gives the same values as the paper's in-place sweep and lets all
+// three phases share one register-blocked tile routine.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "apsp_internal.h"
+
+namespace apsp {
+
+// ---------------------------------------------------------------- phase 1
+// Closes the BS x BS diagonal block in place with BS sequential k-steps.
+// One workgroup; thread (ty, tx) keeps the TM1 x 8 block at rows ty*TM1..,
+// columns tx*8.. in registers.  Before step k the owners of column k and
+// row k publish them through LDS (double buffered by k parity, so one
+// barrier per step suffices).
+template <int BS>
+struct P1Shape {
+    static constexpr int TM1 = BS >= 256 ? 16 : 8;
+    static constexpr int TX = BS / 8, TY = BS / TM1, NTH = TX * TY;
+};
+
+template <class Ar, int BS>
+__global__ void __launch_bounds__(P1Shape<BS>::NTH)
+phase1_kernel(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0, Ar ar,
+              const int32_t *__restrict__ skip) {
+    using T = typename Ar::T;
+    constexpr int TM1 = P1Shape<BS>::TM1, TX = P1Shape<BS>::TX;
+    constexpr int VW = Ar::VW;
+    if (skip && *skip != APSP_SUCCESS) return;
+    __shared__ T colbuf[2][BS];
+    __shared__ T rowbuf[2][BS];
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    T *const base = D + r0 * ld + r0;
+    const uint32_t ldu = (uint32_t)ld;
+    T c[TM1][8];
+#pragma unroll
+    for (int m = 0; m < TM1; ++m)
+#pragma unroll
+        for (int g = 0; g < 8 / VW; ++g)
+            ld16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * 8 + g * VW), &c[m][g * VW]);
+
+    // 16 steps per iteration keep every register index static for both
+    // thread-tile heights (the owner of row k holds it at m = k mod TM1).
+    for (int kb = 0; kb < BS / 16; ++kb) {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k = kb * 16 + kk;
+            const int buf = kk & 1;
+            if (tx == kb * 2 + kk / 8) {
+#pragma unroll
+                for (int m = 0; m < TM1; ++m) colbuf[buf][ty * TM1 + m] = ar.strip(c[m][kk % 8]);
+            }
+            if (ty == k / TM1) {  // k / TM1 is kb * (16 / TM1) + kk / TM1
+#pragma unroll
+                for (int n = 0; n < 8; ++n) rowbuf[buf][tx * 8 + n] = c[kk % TM1][n];
+            }
+            __syncthreads();
+            T a[TM1], b[8];
+#pragma unroll
+            for (int g = 0; g < TM1 / VW; ++g) ld16(&colbuf[buf][ty * TM1 + g * VW], &a[g * VW]);
+#pragma unroll
+            for (int g = 0; g < 8 / VW; ++g) ld16(&rowbuf[buf][tx * 8 + g * VW], &b[g * VW]);
+#pragma unroll
+            for (int m = 0; m < TM1; ++m)
+#pragma unroll
+                for (int n = 0; n < 8; ++n) {
+                    // large blocks: keep each step's minima separate (fusing two
+                    // steps into three-input minima costs a register per element)
+                    if constexpr (TM1 > 8)
+                        c[m][n] = ar.relax1(c[m][n], a[m], b[n]);
+                    else
+                        c[m][n] = ar.mn(c[m][n], ar.add(a[m], b[n]));
+                }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < TM1; ++m)
+#pragma unroll
+        for (int g = 0; g < 8 / VW; ++g)
+            st16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * 8 + g * VW), &c[m][g * VW]);
+}
+
+// ---------------------------------------------------------------- phase 2
+// Block row r:    C = D[r-block rows, J cols] (BS x P2W tiles), A = closed
+//                 diagonal block, B = C's own old values.
+// Block column r: C = D[I rows, r-block cols] (P2W x BS tiles), A = C's own
+//                 old values, B = closed diagonal block.
+// Each tile spans the whole k-block along the direction it reads from
+// itself, so it can update in place.  Workgroups [0, nt) do the row panel,
+// [nt, 2 nt) the column panel; nt = number of P2W-wide tiles outside block r.
+template <class Ar, int BS, int P2W>
+__global__ void __launch_bounds__((BS / 8) * (P2W / 8))
+__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? 2 : 1)))
+phase2_kernel(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0, int nt, Ar ar,
+              const int32_t *__restrict__ skip) {
+    using RowT = TileProduct<Ar, BS, P2W, 16, 8, 8>;
+    using ColT = TileProduct<Ar, P2W, BS, 16, 8, 8>;
+    static_assert(RowT::NTH == ColT::NTH, "both panel shapes use one block size");
+    if (skip && *skip != APSP_SUCCESS) return;
+    __shared__ union {
+        typename RowT::Smem row;
+        typename ColT::Smem col;
+    } sm;
+    int t = blockIdx.x;
+    const bool is_row = t < nt;
+    if (!is_row) t -= nt;
+    const int per_block = BS / P2W;
+    const int rb = (int)(r0 / P2W);
+    const int tt = t + (t >= rb ? per_block : 0);  // skip the diagonal block's tiles
+    const int64_t off = (int64_t)tt * P2W;
+    if (is_row)
+        RowT::run(sm.row, D, ld, r0, off, r0, BS, ar);
+    else
+        ColT::run(sm.col, D, ld, off, r0, r0, BS, ar);
+}
+
+// ---------------------------------------------------------------- phase 3
+// Every tile outside block row r and block column r:
+//     C <- min(C, D[C rows, r-block] (x) D[r-block, C cols]).
+// Workgroup ids are remapped so that each of the 8 XCDs (a dispatch places
+// workgroup w on XCD w mod 8) walks its own contiguous stretch of a grouped
+// tile order: GROUP tile rows at a time, all columns, so the panel slices
+// that the XCD's resident workgroups read stay in that XCD's L2.
+template <class Ar, int BS, int MT>
+__global__ void __launch_bounds__((MT / 8) * (MT / 8))
+__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? 2 : 1)))
+phase3_kernel(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0, int ntr, int per_xcd,
+              Ar ar, const int32_t *__restrict__ skip) {
+    using TP = TileProduct<Ar, MT, MT, 16, 8, 8>;
+    constexpr int GROUP = 8;
+    if (skip && *skip != APSP_SUCCESS) return;
+    __shared__ typename TP::Smem sm;
+    const int w = blockIdx.x;
+    const int seq = (w & 7) * per_xcd + (w >> 3);
+    const int total = ntr * ntr;
+    if (seq >= total) return;
+    const int group = seq / (GROUP * ntr);
+    const int first = group * GROUP;
+    const int rows = min(GROUP, ntr - first);
+    const int within = seq - group * GROUP * ntr;
+    int ti = first + within % rows;
+    int tj = within / rows;
+    const int per_block = BS / MT;
+    const int rb = (int)(r0 / MT);
+    ti += (ti >= rb) ? per_block : 0;
+    tj += (tj >= rb) ? per_block : 0;
+    TP::run(sm, D, ld, (int64_t)ti * MT, (int64_t)tj * MT, r0, BS, ar);
+}
+
+// ------------------------------------------------------ set-up / wrap-up
+__global__ void status_init_kernel(int32_t *status) { *status = APSP_SUCCESS; }
+
+// Checks the weight preconditions of the public header.
+template <class T>
+__global__ void validate_kernel(const T *__restrict__ W, int64_t n, int64_t bound,
+                                int32_t *__restrict__ status) {
+    const int64_t total = n * n;
+    bool bad = false;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e - i * n;
+        const T w = W[e];
+        if constexpr (std::is_same_v<T, float>) {
+            if (w != w || w == -__builtin_inff()) bad = true;
+            if (i == j && w != 0.0f) bad = true;
+        } else {
+            if (i == j) {
+                if (w != 0) bad = true;
+            } else if (w != kInf32 && (w > bound || w < -bound)) {
+                bad = true;
+            }
+        }
+    }
+    if (bad) *status = APSP_ERROR_INVALID_VALUE;
+}
+
+// Copies the caller's n x n matrix into the ld x ld work matrix; padding
+// vertices are isolated (INF off the diagonal, 0 on it).
+template <class T>
+__global__ void pad_in_kernel(const T *__restrict__ W, int64_t n, T *__restrict__ X, int64_t ld,
+                              T inf, const int32_t *__restrict__ skip) {
+    if (skip && *skip != APSP_SUCCESS) return;
+    const int64_t total = ld * ld;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ld, j = e - i * ld;
+        T v;
+        if (i < n && j < n)
+            v = W[i * n + j];
+        else
+            v = (i == j) ? T(0) : inf;
+        X[e] = v;
+    }
+}
+
+// Distance-only wrap-up: map int32 sums that carried the sentinel back to
+// INF, copy to the caller's buffer when a padded work matrix was used, and
+// report a negative diagonal (negative cycle).
+template <class T>
+__global__ void finalize_kernel(const T *__restrict__ X, int64_t ld, T *__restrict__ out, int64_t n,
+                                int32_t *__restrict__ status, const int32_t *__restrict__ skip) {
+    if (skip && *skip != APSP_SUCCESS) return;
+    const int64_t total = n * n;
+    bool neg = false;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e - i * n;
+        T v = X[i * ld + j];
+        if constexpr (std::is_same_v<T, int32_t>) {
+            if (v >= kFakeThreshold) v = kInf32;
+        }
+        if (i == j && v < T(0)) neg = true;
+        out[e] = v;
+    }
+    if (neg && status) *status = APSP_ERROR_NEGATIVE_CYCLE;
+}
+
+// Key mode: key = d * 2^S + p; p = i for an edge i->j (i != j), else 2^S - 1.
+template <class T>
+__global__ void key_pack_kernel(const T *__restrict__ W, int64_t n, double *__restrict__ X,
+                                int64_t ld, int S, const int32_t *__restrict__ skip) {
+    if (skip && *skip != APSP_SUCCESS) return;
+    const int64_t total = ld * ld;
+    const double none = (double)((1 << S) - 1);
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ld, j = e - i * ld;
+        double key;
+        if (i < n && j < n) {
+            const T w = W[i * n + j];
+            bool absent;
+            if constexpr (std::is_same_v<T, int32_t>)
+                absent = (w == kInf32);
+            else
+                absent = (w == __builtin_inff());
+            if (absent)
+                key = __builtin_inf();
+            else
+                key = __builtin_ldexp((double)w, S) + ((i != j) ? (double)i : none);
+        } else {
+            key = (i == j) ? none : __builtin_inf();
+        }
+        X[e] = key;
+    }
+}
+
+template <class T>
+__global__ void key_unpack_kernel(const double *__restrict__ X, int64_t ld, T *__restrict__ dist,
+                                  int32_t *__restrict__ pred, int64_t n, int S,
+                                  int32_t *__restrict__ status, const int32_t *__restrict__ skip) {
+    if (skip && *skip != APSP_SUCCESS) return;
+    const int64_t total = n * n;
+    const int32_t none = (1 << S) - 1;
+    bool neg = false;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e - i * n;
+        const double key = X[i * ld + j];
+        T d;
+        int32_t p;
+        if (key == __builtin_inf()) {
+            if constexpr (std::is_same_v<T, int32_t>)
+                d = kInf32;
+            else
+                d = __builtin_inff();
+            p = APSP_NO_PRED;
+        } else {
+            const double dd = __builtin_floor(__builtin_ldexp(key, -S));
+            p = (int32_t)(key - __builtin_ldexp(dd, S));
+            d = (T)dd;
+            if (p == none || i == j) p = APSP_NO_PRED;
+            if (i == j && dd < 0.0) neg = true;
+        }
+        dist[e] = d;
+        if (pred) pred[e] = p;
+    }
+    if (neg && status) *status = APSP_ERROR_NEGATIVE_CYCLE;
+}
+
+// --------------------------------------------------------------- runtime
+namespace {
+
+thread_local int g_last_hip = 0;
+
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+#define APSP_HIP(call)                                    \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) {                           \
+            g_last_hip = (int)e_;                         \
+            return APSP_ERROR_HIP;                        \
+        }                                                 \
+    } while (0)
+
+// Device workspace private to (device, stream): work on one stream is
+// ordered, so reusing it across calls on that stream is race-free.
+apsp_status_t workspace(int dev, hipStream_t s, size_t bytes, void **out) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace &w = g_ws[{dev, s}];
+    if (w.bytes < bytes) {
+        if (w.ptr) {
+            APSP_HIP(hipStreamSynchronize(s));
+            APSP_HIP(hipFree(w.ptr));
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        hipError_t e = hipMalloc(&w.ptr, bytes);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            w.ptr = nullptr;
+            return APSP_ERROR_OUT_OF_MEMORY;
+        }
+        w.bytes = bytes;
+    }
+    *out = w.ptr;
+    return APSP_SUCCESS;
+}
+
+inline int grid_for(int64_t elems, int per_block = 256) {
+    int64_t g = (elems + per_block - 1) / per_block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+int pred_bits(int64_t ld) {
+    int S = 1;
+    while ((int64_t(1) << S) < ld + 1) ++S;
+    return S;
+}
+
+// The round loop on a work matrix of size ld (a multiple of BS).
+template <class Ar, int BS>
+apsp_status_t run_rounds(typename Ar::T *X, int64_t ld, const Ar &ar, hipStream_t s,
+                         const int32_t *skip) {
+    constexpr int MT = BS >= 128 ? 128 : 64;
+    constexpr int P2W = 64;
+    const int R = (int)(ld / BS);
+    const int nt2 = (int)((ld - BS) / P2W);
+    const int ntr = (int)((ld - BS) / MT);
+    const int64_t tiles3 = (int64_t)ntr * ntr;
+    const int per_xcd = (int)((tiles3 + 7) / 8);
+    for (int r = 0; r < R; ++r) {
+        const int64_t r0 = (int64_t)r * BS;
+        hipLaunchKernelGGL((phase1_kernel<Ar, BS>), dim3(1), dim3(P1Shape<BS>::NTH), 0, s, X, ld, r0,
+                           ar, skip);
+        if (nt2 > 0) {
+            hipLaunchKernelGGL((phase2_kernel<Ar, BS, P2W>), dim3(2 * nt2), dim3((BS / 8) * (P2W / 8)),
+                               0, s, X, ld, r0, nt2, ar, skip);
+        }
+        if (tiles3 > 0) {
+            hipLaunchKernelGGL((phase3_kernel<Ar, BS, MT>), dim3(8 * per_xcd), dim3((MT / 8) * (MT / 8)),
+                               0, s, X, ld, r0, ntr, per_xcd, ar, skip);
+        }
+    }
+    APSP_HIP(hipGetLastError());
+    return APSP_SUCCESS;
+}
+
+template <class Ar>
+apsp_status_t run_rounds_bs(int bs, typename Ar::T *X, int64_t ld, const Ar &ar, hipStream_t s,
+                            const int32_t *skip) {
+    switch (bs) {
+        case 64: return run_rounds<Ar, 64>(X, ld, ar, s, skip);
+        case 128: return run_rounds<Ar, 128>(X, ld, ar, s, skip);
+        case 256:
+            if constexpr (sizeof(typename Ar::T) == 4) return run_rounds<Ar, 256>(X, ld, ar, s, skip);
+            return APSP_ERROR_INVALID_ARGUMENT;
+        default: return APSP_ERROR_INVALID_ARGUMENT;
+    }
+}
+
+int auto_block(int64_t n, bool key) {
+    if (n <= 64) return 64;
+    if (key || n <= 4096) return 128;
+    return 256;
+}
+
+template <class T>
+apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
+                          const apsp_options_t &opt) {
+    int dev = 0;
+    APSP_HIP(hipGetDevice(&dev));
+    const bool key = pred != nullptr;
+    const int bs = opt.block_size ? opt.block_size : auto_block(n, key);
+    if (key && bs == 256) return APSP_ERROR_INVALID_ARGUMENT;
+    const int64_t ld = (n + bs - 1) / bs * bs;
+    int32_t *status = opt.d_status;
+    const int32_t *skip = nullptr;
+    if (status) hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(1), 0, s, status);
+    if (opt.validate) {
+        hipLaunchKernelGGL((validate_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, dist, n,
+                           apsp_weight_bound(n), status);
+        skip = status;
+    }
+    constexpr T inf = std::is_same_v<T, int32_t> ? T(kInf32) : T(__builtin_huge_valf());
+    if (!key) {
+        T *X = dist;
+        const bool inplace = (ld == n) && ((uintptr_t)dist % 16 == 0);
+        if (!inplace) {
+            void *w = nullptr;
+            apsp_status_t st = workspace(dev, s, (size_t)(ld * ld) * sizeof(T), &w);
+            if (st != APSP_SUCCESS) return st;
+            X = (T *)w;
+            hipLaunchKernelGGL((pad_in_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n, X,
+                               ld, inf, skip);
+        }
+        apsp_status_t st;
+        if constexpr (std::is_same_v<T, int32_t>)
+            st = run_rounds_bs<ArI32>(bs, (int32_t *)X, ld, ArI32{}, s, skip);
+        else
+            st = run_rounds_bs<ArF32>(bs, (float *)X, ld, ArF32{}, s, skip);
+        if (st != APSP_SUCCESS) return st;
+        hipLaunchKernelGGL((finalize_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, X, ld, dist, n,
+                           status, skip);
+    } else {
+        void *w = nullptr;
+        apsp_status_t st = workspace(dev, s, (size_t)(ld * ld) * sizeof(double), &w);
+        if (st != APSP_SUCCESS) return st;
+        double *X = (double *)w;
+        ArKey ar{pred_bits(ld)};
+        hipLaunchKernelGGL((key_pack_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n, X, ld,
+                           ar.S, skip);
+        st = run_rounds_bs<ArKey>(bs, X, ld, ar, s, skip);
+        if (st != APSP_SUCCESS) return st;
+        hipLaunchKernelGGL((key_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, X, ld, dist,
+                           pred, n, ar.S, status, skip);
+    }
+    APSP_HIP(hipGetLastError());
+    return APSP_SUCCESS;
+}
+
+}  // namespace
+}  // namespace apsp
+
+using namespace apsp;
+
+extern "C" {
+
+const char *apsp_status_string(apsp_status_t st) {
+    switch (st) {
+        case APSP_SUCCESS: return "success";
+        case APSP_ERROR_INVALID_ARGUMENT: return "invalid argument";
+        case APSP_ERROR_INVALID_VALUE: return "invalid value";
+        case APSP_ERROR_NEGATIVE_CYCLE: return "negative cycle";
+        case APSP_ERROR_OUT_OF_MEMORY: return "out of memory";
+        case APSP_ERROR_HIP: return "HIP runtime error";
+        case APSP_ERROR_QUEUE_FULL: return "queue full";
+        case APSP_ERROR_NOT_READY: return "not ready";
+        case APSP_ERROR_CANCELLED: return "cancelled";
+        case APSP_ERROR_TIMEOUT: return "timeout";
+        case APSP_ERROR_UNKNOWN_TICKET: return "unknown ticket";
+    }
+    return "unknown status";
+}
+
+int apsp_last_hip_error(void) { return g_last_hip; }
+
+int apsp_version(void) { return 100; }
+
+int64_t apsp_weight_bound(int64_t n) { return n <= 1 ? (1LL << 28) - 1 : ((1LL << 28) - 1) / (n - 1); }
+
+apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype,
+                            hipStream_t stream, const apsp_options_t *options) {
+    apsp_options_t opt{};
+    if (options) opt = *options;
+    if (n < 0 || n > kMaxN) return APSP_ERROR_INVALID_ARGUMENT;
+    if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.block_size != 0 && opt.block_size != 64 && opt.block_size != 128 && opt.block_size != 256)
+        return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.block_size == 256 && pred) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
+    if (n == 0) return APSP_SUCCESS;
+    if (!dist || ((uintptr_t)dist % 4) != 0 || ((uintptr_t)pred % 4) != 0)
+        return APSP_ERROR_INVALID_ARGUMENT;
+    if (dtype == APSP_INT32) return solve_typed<int32_t>((int32_t *)dist, pred, n, stream, opt);
+    return solve_typed<float>((float *)dist, pred, n, stream, opt);
+}
+
+apsp_status_t apsp_solve(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t stream) {
+    return apsp_solve_ex(dist, pred, n, dtype, stream, nullptr);
+}
+
+apsp_status_t apsp_release_workspace(void) {
+    int dev = 0;
+    APSP_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    APSP_HIP(hipDeviceSynchronize());
+    for (auto it = g_ws.begin(); it != g_ws.end();) {
+        if (it->first.first == dev) {
+            if (it->second.ptr) APSP_HIP(hipFree(it->second.ptr));
+            it = g_ws.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return APSP_SUCCESS;
+}
+
+}  // extern "C"

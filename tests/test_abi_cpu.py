@@ -1,0 +1,63 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function
+include/apsp.h declares, and rejects bad arguments on the host before
+touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1811_01201_amd as apsp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "apsp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(apsp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["apsp_solve", "apsp_solve_ex", "apsp_solve_batched", "apsp_batch_plan_create",
+                 "apsp_batch_plan_execute", "apsp_batch_plan_destroy", "apsp_server_create",
+                 "apsp_server_submit", "apsp_server_wait", "apsp_server_destroy"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = apsp.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert missing == []
+    out = subprocess.run(["nm", "-D", "--defined-only", apsp.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r"\bT (apsp_[a-z0-9_]+)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+
+
+def test_host_side_argument_errors():
+    L = apsp.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails before any HIP call
+    assert apsp.solve_raw(fake, None, -1, apsp.INT32, None) == apsp.INVALID_ARGUMENT
+    assert apsp.solve_raw(fake, None, 65537, apsp.INT32, None) == apsp.INVALID_ARGUMENT
+    assert apsp.solve_raw(fake, None, 10, 7, None) == apsp.INVALID_ARGUMENT
+    assert apsp.solve_raw(None, None, 10, apsp.INT32, None) == apsp.INVALID_ARGUMENT
+    assert apsp.solve_raw(ctypes.c_void_p(0x1002), None, 10, apsp.INT32, None) == apsp.INVALID_ARGUMENT
+    assert apsp.solve_raw(fake, None, 0, apsp.INT32, None) == apsp.SUCCESS  # n = 0: nothing to do
+    bad_bs = apsp.Options(0, 96, 0, 0, None)
+    assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_bs) == apsp.INVALID_ARGUMENT
+    no_status = apsp.Options(1, 0, 0, 0, None)  # validate needs a status word
+    assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, no_status) == apsp.INVALID_ARGUMENT
+    pred256 = apsp.Options(0, 256, 0, 0, None)
+    assert apsp.solve_raw(fake, fake, 10, apsp.INT32, None, pred256) == apsp.INVALID_ARGUMENT
+    assert L.apsp_status_string(3) == b"negative cycle"
+    assert L.apsp_version() >= 100
+
+
+def test_weight_bound_matches_definition():
+    for n in [1, 2, 3, 1024, 8192, 32768, 65536]:
+        expect = (2 ** 28 - 1) if n <= 1 else (2 ** 28 - 1) // (n - 1)
+        assert apsp.weight_bound(n) == expect

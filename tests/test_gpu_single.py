@@ -1,0 +1,161 @@
+"""GPU parity of apsp_solve against the CPU oracle (element by element).
+
+Bit-exact for int32 weights and integer-valued float32 weights, distances
+and canonical predecessors; relative 1e-6 for real-valued float32 with
+predecessor chains checked for validity.  Sizes span one to many tiles with
+ragged tails, every block size, both dtypes, negative weights (potential
+graphs), unreachable pairs, validation failures and negative cycles."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+import synth
+from gpu_util import describe, first_mismatch, gpu_solve, oracle_expect
+
+pytestmark = pytest.mark.gpu
+INF32 = synth.INF32
+
+SIZES = [1, 2, 3, 17, 63, 64, 65, 127, 128, 129, 200, 255, 256, 257, 383, 513, 1000]
+
+
+def _graph(kind, n, seed):
+    if kind == "int":
+        return synth.single_int32(n, p=0.3, seed=seed)
+    if kind == "sparse":
+        return synth.single_int32(n, p=min(1.0, 2.0 / max(n, 1)), seed=seed)
+    if kind == "pot":
+        return synth.potential_int32(n, p=0.1, seed=seed)
+    if kind == "f32":
+        return synth.single_f32int(n, p=0.3, seed=seed)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("kind", ["int", "sparse", "pot", "f32"])
+@pytest.mark.parametrize("pred", [False, True])
+def test_parity_auto_block(orc, n, kind, pred):
+    describe(f"single auto n={n} kind={kind} pred={pred}")
+    W = _graph(kind, n, seed=1000 + n)
+    D0, P0, st0 = oracle_expect(orc, W, pred)
+    D, P, st = gpu_solve(W, pred)
+    assert st == 0 and st0 == 0
+    assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+    if pred:
+        assert first_mismatch(P, P0) is None, first_mismatch(P, P0)
+
+
+@pytest.mark.parametrize("bs", [64, 128, 256])
+@pytest.mark.parametrize("n,kind", [(130, "int"), (300, "pot"), (512, "f32"), (700, "sparse")])
+@pytest.mark.parametrize("pred", [False, True])
+def test_parity_every_block_size(orc, bs, n, kind, pred):
+    if bs == 256 and pred:
+        pytest.skip("predecessor solves use blocks of at most 128")
+    describe(f"single bs={bs} n={n} kind={kind} pred={pred}")
+    W = _graph(kind, n, seed=77 + n)
+    D0, P0, _ = oracle_expect(orc, W, pred)
+    D, P, st = gpu_solve(W, pred, block_size=bs)
+    assert st == 0
+    assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+    if pred:
+        assert first_mismatch(P, P0) is None, first_mismatch(P, P0)
+
+
+def test_config_n1024_dense_int32(orc):
+    """n=1024, p=0.5, weights 1..1000, distances only (the small single-graph workload)."""
+    describe("single n=1024 p=0.5 int32")
+    W = synth.single_int32(1024, p=0.5, seed=synth.BASE_SEED + 0)
+    D0, _, _ = orc.fw(W)
+    D, _, st = gpu_solve(W)
+    assert st == 0 and np.array_equal(D, D0)
+
+
+def test_real_valued_float32_tolerance(orc):
+    describe("single real f32 n=400 pred")
+    n = 400
+    W = synth.single_f32real(n, p=0.05, lo=0.5, hi=100.0, seed=5)
+    D0, _, _ = orc.fw(W)
+    D, P, st = gpu_solve(W, pred=False)
+    assert st == 0
+    fin = np.isfinite(D0)
+    assert np.array_equal(np.isfinite(D), fin)
+    rel = np.abs(D[fin].astype(np.float64) - D0[fin]) / np.maximum(1.0, np.abs(D0[fin]))
+    assert rel.max() <= 1e-6, rel.max()
+
+
+def test_empty_and_degenerate():
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe("single degenerate")
+    d = torch.empty((0, 0), dtype=torch.int32, device="cuda")
+    assert apsp.solve(d) == apsp.SUCCESS
+    W = np.zeros((1, 1), dtype=np.int32)
+    D, P, st = gpu_solve(W, pred=True)
+    assert D[0, 0] == 0 and P[0, 0] == -1 and st == 0
+    n = 150
+    W = np.full((n, n), INF32, dtype=np.int32)
+    np.fill_diagonal(W, 0)
+    D, P, st = gpu_solve(W, pred=True)
+    assert np.array_equal(D, W) and (P == -1).all()
+
+
+def test_validate_rejects_and_leaves_input():
+    describe("single validate")
+    n = 90
+    W = synth.single_int32(n, p=0.2, seed=3)
+    W[5, 5] = 1
+    D, _, st = gpu_solve(W, validate=True)
+    assert st == 2 and np.array_equal(D, W)
+    W = synth.single_int32(n, p=0.2, seed=3)
+    W[1, 2] = 10 ** 7  # beyond the weight bound for n=90
+    D, _, st = gpu_solve(W, validate=True)
+    assert st == 2 and np.array_equal(D, W)
+    F = synth.single_f32int(n, p=0.2, seed=3)
+    F[3, 4] = np.nan
+    D, _, st = gpu_solve(F, validate=True)
+    assert st == 2
+    W = synth.single_int32(n, p=0.2, seed=3)
+    D, _, st = gpu_solve(W, validate=True)
+    assert st == 0
+
+
+@pytest.mark.parametrize("pred", [False, True])
+@pytest.mark.parametrize("dtype", ["int", "f32"])
+def test_negative_cycle_reported(orc, pred, dtype):
+    describe(f"single negative cycle pred={pred} {dtype}")
+    n = 200
+    W = synth.single_int32(n, p=0.05, seed=11)
+    W[10, 150], W[150, 10] = 5, -9
+    if dtype == "f32":
+        W = np.where(W == INF32, np.inf, W).astype(np.float32)
+    _, _, st0 = orc.fw(W)
+    assert st0 == oracle.NEGATIVE_CYCLE
+    _, _, st = gpu_solve(W, pred=pred)
+    assert st == 3
+
+
+def test_pred_chains_reproduce_distances():
+    describe("single pred chains n=333")
+    n = 333
+    W = synth.single_int32(n, p=0.02, seed=8)
+    D, P, st = gpu_solve(W, pred=True)
+    for i in range(0, n, 37):
+        for j in range(n):
+            assert pins.walk_pred_chain(W, D, P, i, j)
+
+
+def test_full_size_n8192_f32_pred_sampled_rows(orc):
+    """The n=8192 float32 (integer weights 1..1000, p=0.3) distances + predecessors
+    workload at full size: sampled rows against the row oracle, exactly."""
+    describe("single n=8192 f32 pred sampled")
+    n = 8192
+    W = synth.single_f32int(n, p=0.3, seed=synth.BASE_SEED + 1)
+    D, P, st = gpu_solve(W, pred=True)
+    assert st == 0
+    for src in [0, 1, 4095, 5000, 8190, 8191]:
+        dr, pr, s = orc.row(W, src, pred=True)
+        assert s == 0
+        assert np.array_equal(D[src], dr.astype(np.float32)), src
+        assert np.array_equal(P[src], pr), src
+    assert (np.diag(D) == 0).all()
