@@ -130,6 +130,32 @@ typedef struct {
 apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype,
                             hipStream_t stream, const apsp_options_t *options);
 
+/* ---------------------------------------------------------------- profiling
+ *
+ * Per-kernel timing of the single-graph path for benchmarks: between
+ * apsp_profile_begin and apsp_profile_end every phase kernel the library
+ * launches (from any thread) is bracketed by two hipEvents on its own
+ * stream.  apsp_profile_end waits for the recorded events, fills *out with
+ * launch counts, summed and largest durations, and the number of
+ * (i, j, k) relaxations each kind performed, then stops recording.
+ */
+typedef struct {
+    int64_t launches;
+    double total_ms;
+    double max_ms;
+    double updates; /* (i,j,k) relaxations summed over the launches */
+} apsp_kernel_time_t;
+
+typedef struct {
+    apsp_kernel_time_t phase1; /* diagonal block closure */
+    apsp_kernel_time_t phase2; /* block row / block column products */
+    apsp_kernel_time_t phase3; /* remaining-block products */
+    apsp_kernel_time_t other;  /* set-up and wrap-up passes */
+} apsp_profile_t;
+
+apsp_status_t apsp_profile_begin(void);
+apsp_status_t apsp_profile_end(apsp_profile_t *out);
+
 /* Release the calling device's internal workspace and cached graphs.
  * Must not overlap with solves in flight on that device. */
 apsp_status_t apsp_release_workspace(void);

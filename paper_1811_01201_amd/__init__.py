@@ -36,6 +36,24 @@ class APSPError(RuntimeError):
         super().__init__(msg)
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("updates", ctypes.c_double)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("phase1", KernelTime), ("phase2", KernelTime), ("phase3", KernelTime),
+                ("other", KernelTime)]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            k = getattr(self, name)
+            out[name] = {"launches": int(k.launches), "total_ms": k.total_ms, "max_ms": k.max_ms,
+                         "updates": k.updates}
+        return out
+
+
 class Options(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
@@ -65,6 +83,9 @@ def lib():
         L.apsp_weight_bound.argtypes = [i64]
         L.apsp_weight_bound.restype = i64
         L.apsp_release_workspace.restype = c_int
+        L.apsp_profile_begin.restype = c_int
+        L.apsp_profile_end.argtypes = [ctypes.POINTER(Profile)]
+        L.apsp_profile_end.restype = c_int
         _bind_optional(L)
         _lib = L
     return _lib
@@ -155,6 +176,19 @@ def solve_raw(dist_ptr, pred_ptr, n, dtype_code, stream_ptr, options: Options | 
     if options is None:
         return L.apsp_solve(dist_ptr, pred_ptr, n, dtype_code, stream_ptr)
     return L.apsp_solve_ex(dist_ptr, pred_ptr, n, dtype_code, stream_ptr, ctypes.byref(options))
+
+
+def profile_begin() -> None:
+    lib().apsp_profile_begin()
+
+
+def profile_end() -> dict:
+    """Stop per-kernel timing; returns {phase: {launches, total_ms, max_ms, updates}}."""
+    prof = Profile()
+    st = lib().apsp_profile_end(ctypes.byref(prof))
+    if st != SUCCESS:
+        raise APSPError(st, "apsp_profile_end")
+    return prof.as_dict()
 
 
 def release_workspace() -> None:

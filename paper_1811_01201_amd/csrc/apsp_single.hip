@@ -335,6 +335,43 @@ apsp_status_t workspace(int dev, hipStream_t s, size_t bytes, void **out) {
     return APSP_SUCCESS;
 }
 
+// Optional per-launch timing (apsp_profile_begin / _end).
+enum KernelKind { kPhase1 = 0, kPhase2 = 1, kPhase3 = 2, kOther = 3 };
+struct ProfRecord {
+    int kind;
+    double updates;
+    hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof;
+
+struct ProfScope {
+    ProfRecord rec{};
+    hipStream_t s;
+    bool on;
+    ProfScope(int kind, double updates, hipStream_t stream) : s(stream) {
+        {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            on = g_prof_on;
+        }
+        if (!on) return;
+        rec.kind = kind;
+        rec.updates = updates;
+        if (hipEventCreate(&rec.start) != hipSuccess || hipEventCreate(&rec.stop) != hipSuccess) {
+            on = false;
+            return;
+        }
+        hipEventRecord(rec.start, s);
+    }
+    ~ProfScope() {
+        if (!on) return;
+        hipEventRecord(rec.stop, s);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof.push_back(rec);
+    }
+};
+
 inline int grid_for(int64_t elems, int per_block = 256) {
     int64_t g = (elems + per_block - 1) / per_block;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
@@ -357,15 +394,21 @@ apsp_status_t run_rounds(typename Ar::T *X, int64_t ld, const Ar &ar, hipStream_
     const int ntr = (int)((ld - BS) / MT);
     const int64_t tiles3 = (int64_t)ntr * ntr;
     const int per_xcd = (int)((tiles3 + 7) / 8);
+    const double bs3 = (double)BS * BS * BS;
     for (int r = 0; r < R; ++r) {
         const int64_t r0 = (int64_t)r * BS;
-        hipLaunchKernelGGL((phase1_kernel<Ar, BS>), dim3(1), dim3(P1Shape<BS>::NTH), 0, s, X, ld, r0,
-                           ar, skip);
+        {
+            ProfScope ps(kPhase1, bs3, s);
+            hipLaunchKernelGGL((phase1_kernel<Ar, BS>), dim3(1), dim3(P1Shape<BS>::NTH), 0, s, X, ld,
+                               r0, ar, skip);
+        }
         if (nt2 > 0) {
+            ProfScope ps(kPhase2, 2.0 * bs3 * (ld / BS - 1), s);
             hipLaunchKernelGGL((phase2_kernel<Ar, BS, P2W>), dim3(2 * nt2), dim3((BS / 8) * (P2W / 8)),
                                0, s, X, ld, r0, nt2, ar, skip);
         }
         if (tiles3 > 0) {
+            ProfScope ps(kPhase3, (double)(ld - BS) * (ld - BS) * BS, s);
             hipLaunchKernelGGL((phase3_kernel<Ar, BS, MT>), dim3(8 * per_xcd), dim3((MT / 8) * (MT / 8)),
                                0, s, X, ld, r0, ntr, per_xcd, ar, skip);
         }
@@ -496,6 +539,47 @@ apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t d
 
 apsp_status_t apsp_solve(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t stream) {
     return apsp_solve_ex(dist, pred, n, dtype, stream, nullptr);
+}
+
+apsp_status_t apsp_profile_begin(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &r : g_prof) {
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    g_prof.clear();
+    g_prof_on = true;
+    return APSP_SUCCESS;
+}
+
+apsp_status_t apsp_profile_end(apsp_profile_t *out) {
+    if (!out) return APSP_ERROR_INVALID_ARGUMENT;
+    std::vector<ProfRecord> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_on = false;
+        recs.swap(g_prof);
+    }
+    *out = apsp_profile_t{};
+    apsp_kernel_time_t *slot[4] = {&out->phase1, &out->phase2, &out->phase3, &out->other};
+    apsp_status_t st = APSP_SUCCESS;
+    for (auto &r : recs) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            st = APSP_ERROR_HIP;
+        }
+        apsp_kernel_time_t *k = slot[r.kind];
+        k->launches += 1;
+        k->total_ms += ms;
+        k->max_ms = std::max(k->max_ms, (double)ms);
+        k->updates += r.updates;
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    return st;
 }
 
 apsp_status_t apsp_release_workspace(void) {
