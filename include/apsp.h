@@ -163,17 +163,27 @@ apsp_status_t apsp_release_workspace(void);
 /* ----------------------------------------------------------------- batched
  *
  * Many independent graphs of uneven size, solved by one persistent fused
- * launch that runs all three phases of every graph (each workgroup pulls
- * graphs, largest first, from a device work counter).
+ * launch that runs all three phases of every graph: each 256-thread
+ * workgroup pulls graphs, largest first, from a device work counter; graphs
+ * with n > 64 are solved by a whole workgroup with 64-wide k-blocks, graphs
+ * with n <= 64 by a single wavefront in registers.  Same conventions and
+ * results as apsp_solve, graph by graph.
  *
- *   ns          host, batch sizes, 1 <= ns[b] <= 1024
+ *   ns          host, sizes of the batch graphs, 1 <= ns[b] <= 1024
  *   offsets     host, element offset of graph b in the packed buffers;
- *               offsets[b] % 4 == 0 and graphs must not overlap
- *   packed_dist device, graph b occupies [offsets[b], offsets[b] + ns[b]^2),
- *               row-major with leading dimension ns[b]; in place
- *   packed_pred device int32, same offsets, or NULL (plan made without pred)
- * A plan holds the device copy of the metadata and the tuned tile choice;
- * it may be executed any number of times (also under stream capture) and
+ *               offsets[b] % 4 == 0; graphs must not overlap
+ *   packed_dist device, 16-byte aligned; graph b occupies
+ *               [offsets[b], offsets[b] + ns[b]^2), row-major with leading
+ *               dimension ns[b]; weights in, distances out
+ *   packed_pred device int32, 16-byte aligned, same offsets; required when
+ *               the plan was made with want_pred, NULL otherwise
+ *   d_status    device int32[batch] or NULL: per graph APSP_SUCCESS or
+ *               APSP_ERROR_NEGATIVE_CYCLE
+ * A plan owns the device copy of the metadata, the per-workgroup work
+ * matrices and the work counters (device memory of about
+ * 2 x CUs x 64-padded max(n)^2 x 4 or 8 bytes).  It may be executed any
+ * number of times, also from a captured hipGraph, but executions of one plan
+ * must not overlap in time (use one plan per concurrent stream).  The plan
  * must outlive the work it enqueued.
  */
 typedef struct apsp_batch_plan apsp_batch_plan_t;
@@ -182,10 +192,11 @@ apsp_status_t apsp_batch_plan_create(const int32_t *ns, const int64_t *offsets, 
                                      apsp_dtype_t dtype, int32_t want_pred,
                                      apsp_batch_plan_t **out_plan);
 apsp_status_t apsp_batch_plan_execute(const apsp_batch_plan_t *plan, void *packed_dist,
-                                      int32_t *packed_pred, hipStream_t stream);
+                                      int32_t *packed_pred, int32_t *d_status, hipStream_t stream);
 apsp_status_t apsp_batch_plan_destroy(apsp_batch_plan_t *plan);
 
-/* create + execute; the plan is released once the stream reaches it. */
+/* create + execute; the plan is freed by a later library call once the
+ * stream has passed it (no synchronisation here). */
 apsp_status_t apsp_solve_batched(void *packed_dist, int32_t *packed_pred, const int32_t *ns,
                                  const int64_t *offsets, int32_t batch, apsp_dtype_t dtype,
                                  hipStream_t stream);

@@ -97,7 +97,7 @@ def _bind_optional(L):
                                 ctypes.c_uint64)
     table = {
         "apsp_batch_plan_create": ([vp, vp, i32, c_int, i32, ctypes.POINTER(vp)], c_int),
-        "apsp_batch_plan_execute": ([vp, vp, vp, vp], c_int),
+        "apsp_batch_plan_execute": ([vp, vp, vp, vp, vp], c_int),
         "apsp_batch_plan_destroy": ([vp], c_int),
         "apsp_solve_batched": ([vp, vp, vp, vp, i32, c_int, vp], c_int),
         "apsp_server_create": ([vp, ctypes.POINTER(vp)], c_int),
@@ -195,3 +195,57 @@ def release_workspace() -> None:
     st = lib().apsp_release_workspace()
     if st != SUCCESS:
         raise APSPError(st, "apsp_release_workspace")
+
+
+class BatchPlan:
+    """A reusable plan for solving many graphs of uneven size in one launch.
+
+    ns / offsets: host sequences (graph sizes, element offsets of each graph
+    in the packed buffers; offsets multiples of 4)."""
+
+    def __init__(self, ns, offsets, dtype: str = "int32", want_pred: bool = False):
+        import numpy as np
+        self._ns = np.ascontiguousarray(ns, dtype=np.int32)
+        self._offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        assert self._ns.shape == self._offsets.shape
+        self.batch = int(self._ns.shape[0])
+        self.dtype = INT32 if dtype in ("int32", INT32) else FLOAT32
+        self.want_pred = bool(want_pred)
+        self._plan = ctypes.c_void_p()
+        st = lib().apsp_batch_plan_create(self._ns.ctypes.data, self._offsets.ctypes.data, self.batch,
+                                          self.dtype, int(self.want_pred), ctypes.byref(self._plan))
+        if st != SUCCESS:
+            raise APSPError(st, "apsp_batch_plan_create")
+
+    def execute(self, packed_dist, packed_pred=None, status=None, stream=None, check=True) -> int:
+        st = lib().apsp_batch_plan_execute(
+            self._plan, packed_dist.data_ptr(),
+            packed_pred.data_ptr() if packed_pred is not None else None,
+            status.data_ptr() if status is not None else None, _stream_ptr(stream))
+        if check and st != SUCCESS:
+            raise APSPError(st, "apsp_batch_plan_execute")
+        return st
+
+    def destroy(self) -> None:
+        if self._plan:
+            lib().apsp_batch_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def solve_batched(packed_dist, ns, offsets, packed_pred=None, stream=None) -> None:
+    """One-shot batched solve (plan created, executed and retired by the library)."""
+    import numpy as np
+    ns = np.ascontiguousarray(ns, dtype=np.int32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    st = lib().apsp_solve_batched(packed_dist.data_ptr(),
+                                  packed_pred.data_ptr() if packed_pred is not None else None,
+                                  ns.ctypes.data, offsets.ctypes.data, int(ns.shape[0]),
+                                  _dtype_code(packed_dist), _stream_ptr(stream))
+    if st != SUCCESS:
+        raise APSPError(st, "apsp_solve_batched")

@@ -1,0 +1,495 @@
+// Batched blocked Floyd–Warshall: many independent graphs of uneven size in
+// one persistent, fused launch.
+//
+// Each 256-thread workgroup (four wavefronts) loops, pulling work from a
+// device counter, graphs ordered largest first:
+//   * a graph with n > 64 is solved by the whole workgroup: it is copied
+//     into the workgroup's private work matrix (padded to a multiple of 64
+//     with isolated vertices), then the paper's rounds (Section "Data
+//     Locality") run with 64-wide k-blocks: wavefront 0 closes the diagonal
+//     block, the four wavefronts share the block-row/block-column tiles and
+//     then the remaining tiles (64 x 64 each, one wavefront per tile, no
+//     workgroup barrier inside a tile), and the result is copied back;
+//   * once those are exhausted each wavefront pulls graphs with n <= 64 on
+//     its own and closes them entirely in registers (n k-steps).
+// The last workgroup to finish resets the counters, so the plan can be
+// replayed (also from a captured hipGraph) without a separate reset launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "apsp_internal.h"
+
+namespace apsp {
+
+struct BatchMeta {
+    const int32_t *order;    // graph ids, largest n first
+    const int32_t *ns;       // n of each graph
+    const int64_t *offsets;  // element offset of each graph in the packed buffers
+    int32_t batch;
+    int32_t n_team;          // order[0, n_team) have n > 64
+    int64_t scratch_elems;   // work-matrix elements per workgroup
+};
+
+constexpr int kBatchBS = 64;
+constexpr int kBatchThreads = 256;
+
+// ------------------------------------------------ input/output conversion
+template <class Ar, class Tin>
+__device__ __forceinline__ typename Ar::T to_work(const Ar &ar, Tin w, bool inside, int64_t i,
+                                                  int64_t j) {
+    bool absent;
+    if (!inside)
+        absent = (i != j);
+    else if constexpr (std::is_same_v<Tin, int32_t>)
+        absent = (w == kInf32);
+    else
+        absent = (w == __builtin_inff());
+    const bool edge = !absent && i != j;
+    const double x = inside ? (double)w : 0.0;
+    if constexpr (std::is_same_v<Ar, ArI32>) {
+        return absent ? kInf32 : (int32_t)x;
+    } else if constexpr (std::is_same_v<Ar, ArF32>) {
+        return absent ? __builtin_inff() : (float)x;
+    } else if constexpr (std::is_same_v<Ar, ArKey>) {
+        const double none = (double)((1 << ar.S) - 1);
+        return absent ? __builtin_inf() : __builtin_ldexp(x, ar.S) + (edge ? (double)i : none);
+    } else {
+        return DistPred{absent ? __builtin_inff() : (float)x, edge ? (int32_t)i : kLexNone};
+    }
+}
+
+// Writes distance (and predecessor) of one element; returns true for a
+// negative diagonal entry.
+template <class Ar, class Tin>
+__device__ __forceinline__ bool from_work(const Ar &ar, typename Ar::T v, int64_t i, int64_t j,
+                                          Tin *d, int32_t *p) {
+    constexpr Tin inf = std::is_same_v<Tin, int32_t> ? Tin(kInf32) : Tin(__builtin_huge_valf());
+    bool neg = false;
+    int32_t pr = APSP_NO_PRED;
+    Tin out;
+    if constexpr (std::is_same_v<Ar, ArI32>) {
+        out = v >= kFakeThreshold ? kInf32 : v;
+        neg = (i == j) && v < 0;
+    } else if constexpr (std::is_same_v<Ar, ArF32>) {
+        out = v;
+        neg = (i == j) && v < 0.0f;
+    } else if constexpr (std::is_same_v<Ar, ArKey>) {
+        if (v == __builtin_inf()) {
+            out = inf;
+        } else {
+            const double dd = __builtin_floor(__builtin_ldexp(v, -ar.S));
+            pr = (int32_t)(v - __builtin_ldexp(dd, ar.S));
+            if (pr == (1 << ar.S) - 1) pr = APSP_NO_PRED;
+            out = (Tin)dd;
+            neg = (i == j) && dd < 0.0;
+        }
+    } else {
+        if (v.d == __builtin_inff()) {
+            out = inf;
+        } else {
+            out = (Tin)v.d;
+            pr = (v.p == kLexNone) ? APSP_NO_PRED : v.p;
+            neg = (i == j) && v.d < 0.0f;
+        }
+    }
+    if (i == j) pr = APSP_NO_PRED;
+    *d = out;
+    if (p) *p = pr;
+    return neg;
+}
+
+// ------------------------------------------------------------ team path
+template <class Ar>
+using BTile = TileProduct<Ar, kBatchBS, kBatchBS, (sizeof(typename Ar::T) == 4 ? 16 : 8), 8, 8, true>;
+
+template <class Ar>
+struct alignas(16) TeamSmem {
+    typename BTile<Ar>::Smem tile[kBatchThreads / 64];
+};
+
+template <class Ar, class Tin>
+__device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__restrict__ pred,
+                           int32_t *__restrict__ status, int g, int64_t n, int64_t off,
+                           typename Ar::T *__restrict__ X, TeamSmem<Ar> &sm) {
+    using T = typename Ar::T;
+    Ar ar = ar0;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int64_t ldp = (n + kBatchBS - 1) / kBatchBS * kBatchBS;
+    if constexpr (std::is_same_v<Ar, ArKey>) {
+        int S = 1;
+        while ((int64_t(1) << S) < ldp + 1) ++S;
+        ar.S = S;
+    }
+    for (int64_t e = tid; e < ldp * ldp; e += kBatchThreads) {
+        const int64_t i = e / ldp, j = e - i * ldp;
+        const bool inside = i < n && j < n;
+        const Tin w = inside ? dist[off + i * n + j] : Tin(0);
+        X[e] = to_work(ar, w, inside, i, j);
+    }
+    __syncthreads();
+    const int R = (int)(ldp / kBatchBS);
+    const int nt = R - 1;
+    for (int r = 0; r < R; ++r) {
+        const int64_t r0 = (int64_t)r * kBatchBS;
+        if (wave == 0) {
+            T(*buf)[kBatchBS] = reinterpret_cast<T(*)[kBatchBS]>(&sm.tile[0]);
+            phase1_body<Ar, kBatchBS, true>(X, ldp, r0, ar, buf, buf + 2);
+        }
+        __syncthreads();
+        for (int t = wave; t < 2 * nt; t += kBatchThreads / 64) {
+            const bool is_row = t < nt;
+            int tt = is_row ? t : t - nt;
+            tt += (tt >= r) ? 1 : 0;
+            const int64_t o = (int64_t)tt * kBatchBS;
+            if (is_row)
+                BTile<Ar>::run(sm.tile[wave], X, ldp, r0, o, r0, kBatchBS, ar);
+            else
+                BTile<Ar>::run(sm.tile[wave], X, ldp, o, r0, r0, kBatchBS, ar);
+        }
+        __syncthreads();
+        for (int t = wave; t < nt * nt; t += kBatchThreads / 64) {
+            int ti = t / nt, tj = t - (t / nt) * nt;
+            ti += (ti >= r) ? 1 : 0;
+            tj += (tj >= r) ? 1 : 0;
+            BTile<Ar>::run(sm.tile[wave], X, ldp, (int64_t)ti * kBatchBS, (int64_t)tj * kBatchBS, r0,
+                           kBatchBS, ar);
+        }
+        __syncthreads();
+    }
+    bool neg = false;
+    for (int64_t e = tid; e < n * n; e += kBatchThreads) {
+        const int64_t i = e / n, j = e - i * n;
+        neg |= from_work(ar, X[i * ldp + j], i, j, dist + off + e, pred ? pred + off + e : nullptr);
+    }
+    neg = __syncthreads_or(neg);
+    if (status && tid == 0) status[g] = neg ? APSP_ERROR_NEGATIVE_CYCLE : APSP_SUCCESS;
+    __syncthreads();
+}
+
+// ------------------------------------------------------ wavefront path
+// n <= 64: the whole graph in one wavefront's registers (8 x 8 per lane).
+template <class Ar, class Tin>
+__device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__restrict__ pred,
+                           int32_t *__restrict__ status, int g, int64_t n, int64_t off,
+                           typename Ar::T (*colbuf)[kBatchBS], typename Ar::T (*rowbuf)[kBatchBS]) {
+    using T = typename Ar::T;
+    Ar ar = ar0;
+    if constexpr (std::is_same_v<Ar, ArKey>) ar.S = 7;  // vertices 0..63, none = 127
+    const int lane = threadIdx.x & 63, tx = lane % 8, ty = lane / 8;
+    T c[8][8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = ty * 8 + m, j = tx * 8 + q;
+            const bool inside = i < n && j < n;
+            const Tin w = inside ? dist[off + i * n + j] : Tin(0);
+            c[m][q] = to_work(ar, w, inside, i, j);
+        }
+    const int ksteps = (int)((n + 15) / 16 * 16);  // vertices >= n are isolated
+    phase1_steps<Ar, kBatchBS, true>(c, ksteps, ar, colbuf, rowbuf);
+    bool neg = false;
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = ty * 8 + m, j = tx * 8 + q;
+            if (i < n && j < n)
+                neg |= from_work(ar, c[m][q], i, j, dist + off + i * n + j,
+                                 pred ? pred + off + i * n + j : nullptr);
+        }
+    neg = __any(neg);
+    if (status && lane == 0) status[g] = neg ? APSP_ERROR_NEGATIVE_CYCLE : APSP_SUCCESS;
+}
+
+// ------------------------------------------------------------- the kernel
+// counters[0]: next team graph, [1]: next wavefront graph, [2]: finished
+// workgroups.  mode_alt: float32 predecessor solves pick the pair policy
+// for graphs whose weights are not all integers within the bound.
+template <class Tin, class Ar, class Alt>
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(2)))
+batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pred,
+               int32_t *__restrict__ status, void *__restrict__ scratch, int32_t *__restrict__ counters,
+               Ar ar, Alt alt) {
+    constexpr bool kDual = !std::is_same_v<Alt, NoAlt>;
+    __shared__ union {
+        TeamSmem<Ar> a;
+        TeamSmem<std::conditional_t<kDual, Alt, Ar>> b;
+    } sm;
+    __shared__ int s_q;
+    const int tid = threadIdx.x;
+    char *const my_scratch = (char *)scratch + (int64_t)blockIdx.x * meta.scratch_elems *
+                                                   std::max(sizeof(typename Ar::T),
+                                                            sizeof(typename Alt::T));
+    for (;;) {
+        if (tid == 0) s_q = atomicAdd(&counters[0], 1);
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= meta.n_team) break;
+        const int g = meta.order[q];
+        const int64_t n = meta.ns[g], off = meta.offsets[g];
+        bool use_alt = false;
+        if constexpr (kDual) {
+            const float bound = (float)weight_bound(n);
+            bool lex = false;
+            for (int64_t e = tid; e < n * n; e += kBatchThreads) {
+                const float w = (float)dist[off + e];
+                if (w != __builtin_inff() && (w != __builtin_floorf(w) || __builtin_fabsf(w) > bound))
+                    lex = true;
+            }
+            use_alt = __syncthreads_or(lex);
+        }
+        if constexpr (kDual) {
+            if (use_alt) {
+                team_solve<Alt, Tin>(alt, dist, pred, status, g, n, off, (typename Alt::T *)my_scratch,
+                                     sm.b);
+                continue;
+            }
+        }
+        team_solve<Ar, Tin>(ar, dist, pred, status, g, n, off, (typename Ar::T *)my_scratch, sm.a);
+    }
+    // small graphs: every wavefront on its own
+    const int wave = tid >> 6, lane = tid & 63;
+    for (;;) {
+        int q = 0;
+        if (lane == 0) q = atomicAdd(&counters[1], 1);
+        q = __shfl(q, 0) + meta.n_team;
+        if (q >= meta.batch) break;
+        const int g = meta.order[q];
+        const int64_t n = meta.ns[g], off = meta.offsets[g];
+        bool use_alt = false;
+        if constexpr (kDual) {
+            const float bound = (float)weight_bound(n);
+            bool lex = false;
+            for (int64_t e = lane; e < n * n; e += 64) {
+                const float w = (float)dist[off + e];
+                if (w != __builtin_inff() && (w != __builtin_floorf(w) || __builtin_fabsf(w) > bound))
+                    lex = true;
+            }
+            use_alt = __any(lex);
+        }
+        if constexpr (kDual) {
+            if (use_alt) {
+                using TA = typename Alt::T;
+                TA(*buf)[kBatchBS] = reinterpret_cast<TA(*)[kBatchBS]>(&sm.b.tile[wave]);
+                wave_solve<Alt, Tin>(alt, dist, pred, status, g, n, off, buf, buf + 2);
+                continue;
+            }
+        }
+        using TR = typename Ar::T;
+        TR(*buf)[kBatchBS] = reinterpret_cast<TR(*)[kBatchBS]>(&sm.a.tile[wave]);
+        wave_solve<Ar, Tin>(ar, dist, pred, status, g, n, off, buf, buf + 2);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(&counters[2], 1) == (int)gridDim.x - 1) {
+            counters[0] = 0;
+            counters[1] = 0;
+            counters[2] = 0;
+            __threadfence();
+        }
+    }
+}
+
+}  // namespace apsp
+
+// --------------------------------------------------------------- plans
+using namespace apsp;
+
+struct apsp_batch_plan {
+    int device = 0;
+    apsp_dtype_t dtype = APSP_INT32;
+    int32_t want_pred = 0;
+    int32_t batch = 0;
+    int32_t n_team = 0;
+    int grid = 0;
+    int64_t scratch_elems = 0;
+    int64_t max_end = 0;       // elements the packed buffers must hold
+    void *dev_meta = nullptr;  // order | ns | offsets
+    void *scratch = nullptr;
+    int32_t *counters = nullptr;
+};
+
+namespace {
+
+thread_local int t_last_hip = 0;
+
+apsp_status_t plan_free(apsp_batch_plan_t *p) {
+    if (!p) return APSP_SUCCESS;
+    apsp_status_t st = APSP_SUCCESS;
+    if (p->dev_meta && hipFree(p->dev_meta) != hipSuccess) st = APSP_ERROR_HIP;
+    if (p->scratch && hipFree(p->scratch) != hipSuccess) st = APSP_ERROR_HIP;
+    if (p->counters && hipFree(p->counters) != hipSuccess) st = APSP_ERROR_HIP;
+    delete p;
+    return st;
+}
+
+// Plans of apsp_solve_batched are freed once their stream has passed them
+// (an event per plan, swept on later calls and on apsp_release_workspace).
+std::mutex g_retired_mu;
+std::vector<std::pair<apsp_batch_plan_t *, hipEvent_t>> g_retired;
+
+apsp_status_t retire(apsp_batch_plan_t *p, hipStream_t s) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev, s) != hipSuccess) {
+        hipStreamSynchronize(s);
+        plan_free(p);
+        return APSP_SUCCESS;
+    }
+    std::lock_guard<std::mutex> lk(g_retired_mu);
+    g_retired.push_back({p, ev});
+    return APSP_SUCCESS;
+}
+
+template <class Tin, class Ar, class Alt>
+apsp_status_t launch(const apsp_batch_plan_t *p, void *dist, int32_t *pred, int32_t *status,
+                     hipStream_t s, Ar ar, Alt alt) {
+    BatchMeta m;
+    m.order = (const int32_t *)p->dev_meta;
+    m.ns = m.order + p->batch;
+    m.offsets = (const int64_t *)((const char *)p->dev_meta + (size_t)p->batch * 8);
+    m.batch = p->batch;
+    m.n_team = p->n_team;
+    m.scratch_elems = p->scratch_elems;
+    hipLaunchKernelGGL((batched_kernel<Tin, Ar, Alt>), dim3(p->grid), dim3(kBatchThreads), 0, s, m,
+                       (Tin *)dist, pred, status, p->scratch, p->counters, ar, alt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        t_last_hip = (int)e;
+        return APSP_ERROR_HIP;
+    }
+    return APSP_SUCCESS;
+}
+
+}  // namespace
+
+namespace apsp {
+// wait == true: block until every retired plan can be freed.
+void sweep_retired(bool wait) {
+    std::lock_guard<std::mutex> lk(g_retired_mu);
+    for (auto it = g_retired.begin(); it != g_retired.end();) {
+        if (wait) hipEventSynchronize(it->second);
+        if (hipEventQuery(it->second) == hipSuccess) {
+            hipEventDestroy(it->second);
+            plan_free(it->first);
+            it = g_retired.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+}  // namespace apsp
+
+extern "C" {
+
+apsp_status_t apsp_batch_plan_create(const int32_t *ns, const int64_t *offsets, int32_t batch,
+                                     apsp_dtype_t dtype, int32_t want_pred, apsp_batch_plan_t **out_plan) {
+    if (!out_plan) return APSP_ERROR_INVALID_ARGUMENT;
+    sweep_retired(false);
+    *out_plan = nullptr;
+    if (batch < 0 || (batch > 0 && (!ns || !offsets))) return APSP_ERROR_INVALID_ARGUMENT;
+    if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
+    int64_t max_n = 0, max_end = 0;
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    spans.reserve(batch);
+    for (int32_t b = 0; b < batch; ++b) {
+        if (ns[b] < 1 || ns[b] > 1024 || offsets[b] < 0 || offsets[b] % 4 != 0)
+            return APSP_ERROR_INVALID_ARGUMENT;
+        max_n = std::max<int64_t>(max_n, ns[b]);
+        const int64_t end = offsets[b] + (int64_t)ns[b] * ns[b];
+        max_end = std::max(max_end, end);
+        spans.push_back({offsets[b], end});
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return APSP_ERROR_INVALID_ARGUMENT;  // overlap
+
+    auto *p = new (std::nothrow) apsp_batch_plan_t();
+    if (!p) return APSP_ERROR_OUT_OF_MEMORY;
+    p->dtype = dtype;
+    p->want_pred = want_pred ? 1 : 0;
+    p->batch = batch;
+    p->max_end = max_end;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        plan_free(p);
+        return APSP_ERROR_HIP;
+    }
+    int cus = 256;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+
+    std::vector<int32_t> order(batch);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ns[a] > ns[b]; });
+    p->n_team = 0;
+    while (p->n_team < batch && ns[order[p->n_team]] > kBatchBS) ++p->n_team;
+    const int64_t ldp_max = std::max<int64_t>(kBatchBS, (max_n + kBatchBS - 1) / kBatchBS * kBatchBS);
+    p->scratch_elems = p->n_team > 0 ? ldp_max * ldp_max : 0;
+    p->grid = std::max(1, 2 * cus);
+
+    const size_t elem = p->want_pred ? 8 : 4;
+    // device metadata: order[batch] int32 | ns[batch] int32 | offsets[batch] int64
+    const size_t meta_bytes = (size_t)batch * 16;
+    std::vector<char> host(std::max<size_t>(meta_bytes, 16));
+    std::copy(order.begin(), order.end(), (int32_t *)host.data());
+    std::copy(ns, ns + batch, (int32_t *)host.data() + batch);
+    std::copy(offsets, offsets + batch, (int64_t *)(host.data() + (size_t)batch * 8));
+    if (hipMalloc(&p->dev_meta, host.size()) != hipSuccess ||
+        hipMalloc((void **)&p->counters, 4 * sizeof(int32_t)) != hipSuccess ||
+        (p->scratch_elems > 0 &&
+         hipMalloc(&p->scratch, (size_t)p->grid * p->scratch_elems * elem) != hipSuccess)) {
+        plan_free(p);
+        return APSP_ERROR_OUT_OF_MEMORY;
+    }
+    if (hipMemcpy(p->dev_meta, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(p->counters, 0, 4 * sizeof(int32_t)) != hipSuccess) {
+        plan_free(p);
+        return APSP_ERROR_HIP;
+    }
+    *out_plan = p;
+    return APSP_SUCCESS;
+}
+
+apsp_status_t apsp_batch_plan_execute(const apsp_batch_plan_t *plan, void *packed_dist,
+                                      int32_t *packed_pred, int32_t *d_status, hipStream_t stream) {
+    if (!plan) return APSP_ERROR_INVALID_ARGUMENT;
+    if (plan->batch == 0) return APSP_SUCCESS;
+    if (!packed_dist || (plan->want_pred && !packed_pred) || (!plan->want_pred && packed_pred))
+        return APSP_ERROR_INVALID_ARGUMENT;
+    if ((uintptr_t)packed_dist % 16 || (uintptr_t)packed_pred % 16) return APSP_ERROR_INVALID_ARGUMENT;
+    if (plan->dtype == APSP_INT32) {
+        if (plan->want_pred)
+            return launch<int32_t>(plan, packed_dist, packed_pred, d_status, stream, ArKey{7}, NoAlt{});
+        return launch<int32_t>(plan, packed_dist, nullptr, d_status, stream, ArI32{}, NoAlt{});
+    }
+    if (plan->want_pred)
+        return launch<float>(plan, packed_dist, packed_pred, d_status, stream, ArKey{7}, ArLexF32{});
+    return launch<float>(plan, packed_dist, nullptr, d_status, stream, ArF32{}, NoAlt{});
+}
+
+apsp_status_t apsp_batch_plan_destroy(apsp_batch_plan_t *plan) { return plan_free(plan); }
+
+apsp_status_t apsp_solve_batched(void *packed_dist, int32_t *packed_pred, const int32_t *ns,
+                                 const int64_t *offsets, int32_t batch, apsp_dtype_t dtype,
+                                 hipStream_t stream) {
+    sweep_retired(false);
+    apsp_batch_plan_t *plan = nullptr;
+    apsp_status_t st =
+        apsp_batch_plan_create(ns, offsets, batch, dtype, packed_pred != nullptr ? 1 : 0, &plan);
+    if (st != APSP_SUCCESS) return st;
+    st = apsp_batch_plan_execute(plan, packed_dist, packed_pred, nullptr, stream);
+    if (st != APSP_SUCCESS) {
+        plan_free(plan);
+        return st;
+    }
+    return retire(plan, stream);
+}
+
+}  // extern "C"

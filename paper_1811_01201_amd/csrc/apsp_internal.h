@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "apsp.h"
 
 namespace apsp {
@@ -15,6 +17,14 @@ constexpr int32_t kInf32 = APSP_INF_INT32;
 // involved the INF sentinel stays above INF - 2 * 2^28 > 2^29.
 constexpr int32_t kFakeThreshold = 1 << 29;
 constexpr int kMaxN = 65536;
+
+// Largest |w| accepted for int32 weights (and for exact key arithmetic on
+// integer float32 weights) at size n: (n-1)|w| < 2^28.
+__host__ __device__ inline int64_t weight_bound(int64_t n) {
+    return n <= 1 ? (int64_t(1) << 28) - 1 : ((int64_t(1) << 28) - 1) / (n - 1);
+}
+
+void sweep_retired(bool wait);
 
 // ---------------------------------------------------------------------------
 // Arithmetic policies.  Each supplies the element type T, the number of
@@ -93,27 +103,65 @@ struct ArKey {
     }
 };
 
-template <class T>
-struct Vec16;
-template <>
-struct Vec16<int32_t> { using type = int4; };
-template <>
-struct Vec16<float> { using type = float4; };
-template <>
-struct Vec16<double> { using type = double2; };
+// Lexicographic mode for real-valued float32 weights with predecessors:
+// (distance, predecessor) pairs stored side by side, compared
+// lexicographically; the sum takes the right operand's predecessor.
+struct alignas(8) DistPred {
+    float d;
+    int32_t p;
+};
+constexpr int32_t kLexNone = 0x7fffffff;
 
+struct ArLexF32 {
+    using T = DistPred;
+    static constexpr int VW = 2;
+    __device__ __forceinline__ T add(T a, T b) const { return T{a.d + b.d, b.p}; }
+    __device__ __forceinline__ T mn(T c, T s) const {
+        const bool take = (s.d < c.d) | ((s.d == c.d) & (s.p < c.p));
+        return T{take ? s.d : c.d, take ? s.p : c.p};
+    }
+    __device__ __forceinline__ T strip(T a) const { return a; }
+    __device__ __forceinline__ T relax2(T c, T a0, T b0, T a1, T b1) const {
+        return mn(mn(c, add(a0, b0)), add(a1, b1));
+    }
+    __device__ __forceinline__ T relax1(T c, T a, T b) const {
+        T r = mn(c, add(a, b));
+        asm("" : "+v"(r.d), "+v"(r.p));
+        return r;
+    }
+};
+
+// 16-byte vector load/store of VW elements of any 4/8-byte element type.
 template <class T>
 __device__ __forceinline__ void ld16(const T *p, T *out) {
-    using V = typename Vec16<T>::type;
-    V v = *reinterpret_cast<const V *>(p);
+    int4 v = *reinterpret_cast<const int4 *>(p);
     __builtin_memcpy(out, &v, 16);
 }
 template <class T>
 __device__ __forceinline__ void st16(T *p, const T *in) {
-    using V = typename Vec16<T>::type;
-    V v;
+    int4 v;
     __builtin_memcpy(&v, in, 16);
-    *reinterpret_cast<V *>(p) = v;
+    *reinterpret_cast<int4 *>(p) = v;
+}
+
+// Barrier between the LDS writes and reads of a tile step.  Workgroup mode:
+// s_barrier.  Wavefront mode (one wavefront owns the tile): a wavefront's LDS
+// operations execute in issue order, so only the compiler must be kept from
+// moving LDS accesses across this point.
+template <bool WAVE>
+__device__ __forceinline__ void tile_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <bool WAVE>
+__device__ __forceinline__ int tile_tid() {
+    return WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
 }
 
 // ---------------------------------------------------------------------------
@@ -136,7 +184,7 @@ __device__ __forceinline__ void st16(T *p, const T *in) {
 // the workgroup owns every C element that its reads could see (the panel
 // updates use a tile that spans the whole k-block in that direction).
 // ---------------------------------------------------------------------------
-template <class Ar, int MT, int NT, int KC, int TM, int TN>
+template <class Ar, int MT, int NT, int KC, int TM, int TN, bool WAVE = false>
 struct TileProduct {
     using T = typename Ar::T;
     static constexpr int VW = Ar::VW;
@@ -151,6 +199,7 @@ struct TileProduct {
     static constexpr int PA = (NA + NTH - 1) / NTH;
     static constexpr int PB = (NB + NTH - 1) / NTH;
     static_assert(TN % VW == 0 && GSTRIDE == TX * VW, "column groups must tile NT");
+    static_assert(!WAVE || NTH == 64, "a wavefront tile has 64 threads");
     static_assert(KC % VW == 0 && VW % 2 == 0, "k-chunk must be whole vectors");
 
     struct Smem {
@@ -163,7 +212,7 @@ struct TileProduct {
     __device__ __forceinline__ static void load_chunk(const T *__restrict__ Abase,
                                                       const T *__restrict__ Bbase, uint32_t ld,
                                                       T (&ra)[PA][VW], T (&rb)[PB][VW]) {
-        const int tid = threadIdx.x;
+        const int tid = tile_tid<WAVE>();
 #pragma unroll
         for (int i = 0; i < PA; ++i) {
             const int v = tid + NTH * i;
@@ -184,7 +233,7 @@ struct TileProduct {
 
     __device__ __forceinline__ static void store_chunk(Smem &sm, int buf, const Ar &ar, T (&ra)[PA][VW],
                                        T (&rb)[PB][VW]) {
-        const int tid = threadIdx.x;
+        const int tid = tile_tid<WAVE>();
 #pragma unroll
         for (int i = 0; i < PA; ++i) {
             const int v = tid + NTH * i;
@@ -208,7 +257,7 @@ struct TileProduct {
 
     __device__ __forceinline__ static void run(Smem &sm, T *__restrict__ D, int64_t ld64, int64_t crow,
                                                int64_t ccol, int64_t k0, int kcount, const Ar &ar) {
-        const int tid = threadIdx.x;
+        const int tid = tile_tid<WAVE>();
         const int tx = tid % TX, ty = tid / TX;
         const uint32_t ld = (uint32_t)ld64;  // row offsets inside one tile fit in 32 bits
         T *const Cbase = D + crow * ld64 + ccol;
@@ -226,7 +275,7 @@ struct TileProduct {
         const int nch = kcount / KC;
         load_chunk(Abase, Bbase, ld, ra, rb);
         store_chunk(sm, 0, ar, ra, rb);
-        __syncthreads();
+        tile_sync<WAVE>();
         for (int ch = 0; ch < nch; ++ch) {
             const int buf = ch & 1;
             const bool more = ch + 1 < nch;
@@ -254,7 +303,7 @@ struct TileProduct {
                 }
             }
             if (more) store_chunk(sm, buf ^ 1, ar, ra, rb);
-            __syncthreads();
+            tile_sync<WAVE>();
         }
 #pragma unroll
         for (int m = 0; m < TM; ++m)
@@ -263,5 +312,106 @@ struct TileProduct {
                 st16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
     }
 };
+
+// Kernels take the work matrix as void* and a policy Ar; those launched for
+// float32 solves with predecessors carry a second policy Alt and pick one of
+// the two from a device word written by the set-up pass (exact fp64 keys
+// when every weight is an integer within the bound, lexicographic pairs
+// otherwise), so the launch sequence does not depend on the data.
+struct NoAlt {
+    using T = char;
+};
+template <class Ar, class Alt>
+__device__ __forceinline__ bool use_alt(const int32_t *mode) {
+    if constexpr (std::is_same_v<Alt, NoAlt>)
+        return false;
+    else
+        return *mode != 0;
+}
+
+// ---------------------------------------------------------------- phase 1
+// Closes the BS x BS diagonal block in place with BS sequential k-steps.
+// One workgroup; thread (ty, tx) keeps the TM1 x 8 block at rows ty*TM1..,
+// columns tx*8.. in registers.  Before step k the owners of column k and
+// row k publish them through LDS (double buffered by k parity, so one
+// barrier per step suffices).
+template <int BS>
+struct P1Shape {
+    static constexpr int TM1 = BS >= 256 ? 16 : 8;
+    static constexpr int TX = BS / 8, TY = BS / TM1, NTH = TX * TY;
+};
+
+// The k-steps of a diagonal-block closure on a register-resident block:
+// thread (ty, tx) holds c = rows ty*TM1.., columns tx*8..; steps
+// 0 <= k < ksteps (ksteps a multiple of 16, at most BS).
+template <class Ar, int BS, bool WAVE>
+__device__ __forceinline__ void phase1_steps(typename Ar::T (&c)[P1Shape<BS>::TM1][8], int ksteps,
+                                             const Ar &ar, typename Ar::T (*colbuf)[BS],
+                                             typename Ar::T (*rowbuf)[BS]) {
+    using T = typename Ar::T;
+    constexpr int TM1 = P1Shape<BS>::TM1, TX = P1Shape<BS>::TX;
+    constexpr int VW = Ar::VW;
+    const int tid = tile_tid<WAVE>(), tx = tid % TX, ty = tid / TX;
+    // 16 steps per iteration keep every register index static for both
+    // thread-tile heights (the owner of row k holds it at m = k mod TM1).
+    for (int kb = 0; kb < ksteps / 16; ++kb) {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k = kb * 16 + kk;
+            const int buf = kk & 1;
+            if (tx == kb * 2 + kk / 8) {
+#pragma unroll
+                for (int m = 0; m < TM1; ++m) colbuf[buf][ty * TM1 + m] = ar.strip(c[m][kk % 8]);
+            }
+            if (ty == k / TM1) {
+#pragma unroll
+                for (int n = 0; n < 8; ++n) rowbuf[buf][tx * 8 + n] = c[kk % TM1][n];
+            }
+            tile_sync<WAVE>();
+            T a[TM1], b[8];
+#pragma unroll
+            for (int g = 0; g < TM1 / VW; ++g) ld16(&colbuf[buf][ty * TM1 + g * VW], &a[g * VW]);
+#pragma unroll
+            for (int g = 0; g < 8 / VW; ++g) ld16(&rowbuf[buf][tx * 8 + g * VW], &b[g * VW]);
+#pragma unroll
+            for (int m = 0; m < TM1; ++m)
+#pragma unroll
+                for (int n = 0; n < 8; ++n) {
+                    // large blocks: keep each step's minima separate (fusing two
+                    // steps into three-input minima costs a register per element)
+                    if constexpr (TM1 > 8)
+                        c[m][n] = ar.relax1(c[m][n], a[m], b[n]);
+                    else
+                        c[m][n] = ar.mn(c[m][n], ar.add(a[m], b[n]));
+                }
+        }
+    }
+}
+
+// Closes the BS x BS diagonal block at (r0, r0) of D in place.
+template <class Ar, int BS, bool WAVE = false>
+__device__ __forceinline__ void phase1_body(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0,
+                                            const Ar &ar, typename Ar::T (*colbuf)[BS],
+                                            typename Ar::T (*rowbuf)[BS]) {
+    using T = typename Ar::T;
+    constexpr int TM1 = P1Shape<BS>::TM1, TX = P1Shape<BS>::TX;
+    constexpr int VW = Ar::VW;
+    static_assert(!WAVE || P1Shape<BS>::NTH == 64, "a wavefront closes 64 x 64 blocks");
+    const int tid = tile_tid<WAVE>(), tx = tid % TX, ty = tid / TX;
+    T *const base = D + r0 * ld + r0;
+    const uint32_t ldu = (uint32_t)ld;
+    T c[TM1][8];
+#pragma unroll
+    for (int m = 0; m < TM1; ++m)
+#pragma unroll
+        for (int g = 0; g < 8 / VW; ++g)
+            ld16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * 8 + g * VW), &c[m][g * VW]);
+    phase1_steps<Ar, BS, WAVE>(c, BS, ar, colbuf, rowbuf);
+#pragma unroll
+    for (int m = 0; m < TM1; ++m)
+#pragma unroll
+        for (int g = 0; g < 8 / VW; ++g)
+            st16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * 8 + g * VW), &c[m][g * VW]);
+}
 
 }  // namespace apsp

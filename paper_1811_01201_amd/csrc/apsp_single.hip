@@ -20,77 +20,23 @@
 
 namespace apsp {
 
-// ---------------------------------------------------------------- phase 1
-// Closes the BS x BS diagonal block in place with BS sequential k-steps.
-// One workgroup; thread (ty, tx) keeps the TM1 x 8 block at rows ty*TM1..,
-// columns tx*8.. in registers.  Before step k the owners of column k and
-// row k publish them through LDS (double buffered by k parity, so one
-// barrier per step suffices).
-template <int BS>
-struct P1Shape {
-    static constexpr int TM1 = BS >= 256 ? 16 : 8;
-    static constexpr int TX = BS / 8, TY = BS / TM1, NTH = TX * TY;
-};
-
-template <class Ar, int BS>
+template <class Ar, class Alt, int BS>
 __global__ void __launch_bounds__(P1Shape<BS>::NTH)
-phase1_kernel(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0, Ar ar,
+phase1_kernel(void *X, int64_t ld, int64_t r0, Ar ar, Alt alt, const int32_t *__restrict__ mode,
               const int32_t *__restrict__ skip) {
-    using T = typename Ar::T;
-    constexpr int TM1 = P1Shape<BS>::TM1, TX = P1Shape<BS>::TX;
-    constexpr int VW = Ar::VW;
     if (skip && *skip != APSP_SUCCESS) return;
-    __shared__ T colbuf[2][BS];
-    __shared__ T rowbuf[2][BS];
-    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
-    T *const base = D + r0 * ld + r0;
-    const uint32_t ldu = (uint32_t)ld;
-    T c[TM1][8];
-#pragma unroll
-    for (int m = 0; m < TM1; ++m)
-#pragma unroll
-        for (int g = 0; g < 8 / VW; ++g)
-            ld16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * 8 + g * VW), &c[m][g * VW]);
-
-    // 16 steps per iteration keep every register index static for both
-    // thread-tile heights (the owner of row k holds it at m = k mod TM1).
-    for (int kb = 0; kb < BS / 16; ++kb) {
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            const int k = kb * 16 + kk;
-            const int buf = kk & 1;
-            if (tx == kb * 2 + kk / 8) {
-#pragma unroll
-                for (int m = 0; m < TM1; ++m) colbuf[buf][ty * TM1 + m] = ar.strip(c[m][kk % 8]);
-            }
-            if (ty == k / TM1) {  // k / TM1 is kb * (16 / TM1) + kk / TM1
-#pragma unroll
-                for (int n = 0; n < 8; ++n) rowbuf[buf][tx * 8 + n] = c[kk % TM1][n];
-            }
-            __syncthreads();
-            T a[TM1], b[8];
-#pragma unroll
-            for (int g = 0; g < TM1 / VW; ++g) ld16(&colbuf[buf][ty * TM1 + g * VW], &a[g * VW]);
-#pragma unroll
-            for (int g = 0; g < 8 / VW; ++g) ld16(&rowbuf[buf][tx * 8 + g * VW], &b[g * VW]);
-#pragma unroll
-            for (int m = 0; m < TM1; ++m)
-#pragma unroll
-                for (int n = 0; n < 8; ++n) {
-                    // large blocks: keep each step's minima separate (fusing two
-                    // steps into three-input minima costs a register per element)
-                    if constexpr (TM1 > 8)
-                        c[m][n] = ar.relax1(c[m][n], a[m], b[n]);
-                    else
-                        c[m][n] = ar.mn(c[m][n], ar.add(a[m], b[n]));
-                }
+    constexpr int E = sizeof(typename Ar::T) > sizeof(typename Alt::T) ? sizeof(typename Ar::T)
+                                                                        : sizeof(typename Alt::T);
+    __shared__ __attribute__((aligned(16))) char lds[2 * 2 * BS * E];
+    if constexpr (!std::is_same_v<Alt, NoAlt>) {
+        if (use_alt<Ar, Alt>(mode)) {
+            using T = typename Alt::T;
+            phase1_body<Alt, BS>((T *)X, ld, r0, alt, (T(*)[BS])lds, (T(*)[BS])(lds + 2 * BS * sizeof(T)));
+            return;
         }
     }
-#pragma unroll
-    for (int m = 0; m < TM1; ++m)
-#pragma unroll
-        for (int g = 0; g < 8 / VW; ++g)
-            st16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * 8 + g * VW), &c[m][g * VW]);
+    using T = typename Ar::T;
+    phase1_body<Ar, BS>((T *)X, ld, r0, ar, (T(*)[BS])lds, (T(*)[BS])(lds + 2 * BS * sizeof(T)));
 }
 
 // ---------------------------------------------------------------- phase 2
@@ -102,29 +48,58 @@ phase1_kernel(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0, Ar ar,
 // itself, so it can update in place.  Workgroups [0, nt) do the row panel,
 // [nt, 2 nt) the column panel; nt = number of P2W-wide tiles outside block r.
 template <class Ar, int BS, int P2W>
-__global__ void __launch_bounds__((BS / 8) * (P2W / 8))
-__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? 2 : 1)))
-phase2_kernel(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0, int nt, Ar ar,
-              const int32_t *__restrict__ skip) {
+struct P2 {
     using RowT = TileProduct<Ar, BS, P2W, 16, 8, 8>;
     using ColT = TileProduct<Ar, P2W, BS, 16, 8, 8>;
     static_assert(RowT::NTH == ColT::NTH, "both panel shapes use one block size");
-    if (skip && *skip != APSP_SUCCESS) return;
-    __shared__ union {
+    union Smem {
         typename RowT::Smem row;
         typename ColT::Smem col;
-    } sm;
-    int t = blockIdx.x;
-    const bool is_row = t < nt;
-    if (!is_row) t -= nt;
-    const int per_block = BS / P2W;
-    const int rb = (int)(r0 / P2W);
-    const int tt = t + (t >= rb ? per_block : 0);  // skip the diagonal block's tiles
-    const int64_t off = (int64_t)tt * P2W;
-    if (is_row)
-        RowT::run(sm.row, D, ld, r0, off, r0, BS, ar);
-    else
-        ColT::run(sm.col, D, ld, off, r0, r0, BS, ar);
+    };
+    __device__ __forceinline__ static void run(Smem &sm, typename Ar::T *D, int64_t ld, int64_t r0,
+                                               int nt, const Ar &ar) {
+        int t = blockIdx.x;
+        const bool is_row = t < nt;
+        if (!is_row) t -= nt;
+        const int per_block = BS / P2W;
+        const int rb = (int)(r0 / P2W);
+        const int tt = t + (t >= rb ? per_block : 0);  // skip the diagonal block's tiles
+        const int64_t off = (int64_t)tt * P2W;
+        if (is_row)
+            RowT::run(sm.row, D, ld, r0, off, r0, BS, ar);
+        else
+            ColT::run(sm.col, D, ld, off, r0, r0, BS, ar);
+    }
+};
+
+template <class T>
+constexpr int elem_size() {
+    return sizeof(T);
+}
+template <>
+constexpr int elem_size<char>() {
+    return 0;
+}
+
+template <class Ar, class Alt, int BS, int P2W>
+__global__ void __launch_bounds__((BS / 8) * (P2W / 8))
+__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? 2 : 1)))
+phase2_kernel(void *X, int64_t ld, int64_t r0, int nt, Ar ar, Alt alt,
+              const int32_t *__restrict__ mode, const int32_t *__restrict__ skip) {
+    if (skip && *skip != APSP_SUCCESS) return;
+    if constexpr (!std::is_same_v<Alt, NoAlt>) {
+        __shared__ union {
+            typename P2<Ar, BS, P2W>::Smem a;
+            typename P2<Alt, BS, P2W>::Smem b;
+        } sm;
+        if (use_alt<Ar, Alt>(mode))
+            P2<Alt, BS, P2W>::run(sm.b, (typename Alt::T *)X, ld, r0, nt, alt);
+        else
+            P2<Ar, BS, P2W>::run(sm.a, (typename Ar::T *)X, ld, r0, nt, ar);
+    } else {
+        __shared__ typename P2<Ar, BS, P2W>::Smem sm;
+        P2<Ar, BS, P2W>::run(sm, (typename Ar::T *)X, ld, r0, nt, ar);
+    }
 }
 
 // ---------------------------------------------------------------- phase 3
@@ -134,19 +109,14 @@ phase2_kernel(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0, int nt, Ar
 // workgroup w on XCD w mod 8) walks its own contiguous stretch of a grouped
 // tile order: GROUP tile rows at a time, all columns, so the panel slices
 // that the XCD's resident workgroups read stay in that XCD's L2.
-template <class Ar, int BS, int MT>
-__global__ void __launch_bounds__((MT / 8) * (MT / 8))
-__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? 2 : 1)))
-phase3_kernel(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0, int ntr, int per_xcd,
-              Ar ar, const int32_t *__restrict__ skip) {
-    using TP = TileProduct<Ar, MT, MT, 16, 8, 8>;
+template <int BS, int MT>
+__device__ __forceinline__ bool phase3_tile(int64_t r0, int ntr, int per_xcd, int64_t &crow,
+                                            int64_t &ccol) {
     constexpr int GROUP = 8;
-    if (skip && *skip != APSP_SUCCESS) return;
-    __shared__ typename TP::Smem sm;
     const int w = blockIdx.x;
     const int seq = (w & 7) * per_xcd + (w >> 3);
     const int total = ntr * ntr;
-    if (seq >= total) return;
+    if (seq >= total) return false;
     const int group = seq / (GROUP * ntr);
     const int first = group * GROUP;
     const int rows = min(GROUP, ntr - first);
@@ -157,7 +127,34 @@ phase3_kernel(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0, int ntr, i
     const int rb = (int)(r0 / MT);
     ti += (ti >= rb) ? per_block : 0;
     tj += (tj >= rb) ? per_block : 0;
-    TP::run(sm, D, ld, (int64_t)ti * MT, (int64_t)tj * MT, r0, BS, ar);
+    crow = (int64_t)ti * MT;
+    ccol = (int64_t)tj * MT;
+    return true;
+}
+
+template <class Ar, class Alt, int BS, int MT>
+__global__ void __launch_bounds__((MT / 8) * (MT / 8))
+__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? 2 : 1)))
+phase3_kernel(void *X, int64_t ld, int64_t r0, int ntr, int per_xcd, Ar ar, Alt alt,
+              const int32_t *__restrict__ mode, const int32_t *__restrict__ skip) {
+    using TP = TileProduct<Ar, MT, MT, 16, 8, 8>;
+    if (skip && *skip != APSP_SUCCESS) return;
+    int64_t crow, ccol;
+    if (!phase3_tile<BS, MT>(r0, ntr, per_xcd, crow, ccol)) return;
+    if constexpr (!std::is_same_v<Alt, NoAlt>) {
+        using TQ = TileProduct<Alt, MT, MT, 16, 8, 8>;
+        __shared__ union {
+            typename TP::Smem a;
+            typename TQ::Smem b;
+        } sm;
+        if (use_alt<Ar, Alt>(mode))
+            TQ::run(sm.b, (typename Alt::T *)X, ld, crow, ccol, r0, BS, alt);
+        else
+            TP::run(sm.a, (typename Ar::T *)X, ld, crow, ccol, r0, BS, ar);
+    } else {
+        __shared__ typename TP::Smem sm;
+        TP::run(sm, (typename Ar::T *)X, ld, crow, ccol, r0, BS, ar);
+    }
 }
 
 // ------------------------------------------------------ set-up / wrap-up
@@ -228,62 +225,97 @@ __global__ void finalize_kernel(const T *__restrict__ X, int64_t ld, T *__restri
     if (neg && status) *status = APSP_ERROR_NEGATIVE_CYCLE;
 }
 
-// Key mode: key = d * 2^S + p; p = i for an edge i->j (i != j), else 2^S - 1.
+// Predecessor solves.  mode == nullptr or *mode == 0: key mode,
+// key = d * 2^S + p (p = i for an edge i->j, i != j, else 2^S - 1 = none;
+// +inf when absent).  *mode != 0 (float32 weights that are not all
+// integers within the bound): (distance, predecessor) pairs.
+__global__ void mode_init_kernel(int32_t *mode) { *mode = 0; }
+
+// Sets *mode = 1 if some finite off-diagonal float32 weight is not an
+// integer of magnitude <= bound (key arithmetic would then not be exact).
+__global__ void integral_check_kernel(const float *__restrict__ W, int64_t n, float bound,
+                                      int32_t *__restrict__ mode) {
+    const int64_t total = n * n;
+    bool lex = false;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const float w = W[e];
+        if (w == __builtin_inff()) continue;
+        if (w != __builtin_floorf(w) || __builtin_fabsf(w) > bound) lex = true;
+    }
+    if (lex) *mode = 1;
+}
+
 template <class T>
-__global__ void key_pack_kernel(const T *__restrict__ W, int64_t n, double *__restrict__ X,
-                                int64_t ld, int S, const int32_t *__restrict__ skip) {
+__global__ void pred_pack_kernel(const T *__restrict__ W, int64_t n, void *__restrict__ Xv,
+                                 int64_t ld, int S, const int32_t *__restrict__ mode,
+                                 const int32_t *__restrict__ skip) {
     if (skip && *skip != APSP_SUCCESS) return;
+    const bool lex = mode && *mode;
     const int64_t total = ld * ld;
     const double none = (double)((1 << S) - 1);
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e / ld, j = e - i * ld;
-        double key;
+        bool absent = i != j;
+        double w = 0.0;
         if (i < n && j < n) {
-            const T w = W[i * n + j];
-            bool absent;
+            const T x = W[i * n + j];
             if constexpr (std::is_same_v<T, int32_t>)
-                absent = (w == kInf32);
+                absent = (x == kInf32);
             else
-                absent = (w == __builtin_inff());
-            if (absent)
-                key = __builtin_inf();
-            else
-                key = __builtin_ldexp((double)w, S) + ((i != j) ? (double)i : none);
-        } else {
-            key = (i == j) ? none : __builtin_inf();
+                absent = (x == __builtin_inff());
+            w = (double)x;
         }
-        X[e] = key;
+        const bool edge = !absent && i != j;
+        if (lex) {
+            DistPred v{absent ? __builtin_inff() : (float)w, edge ? (int32_t)i : kLexNone};
+            ((DistPred *)Xv)[e] = v;
+        } else {
+            ((double *)Xv)[e] = absent ? __builtin_inf() : __builtin_ldexp(w, S) + (edge ? (double)i : none);
+        }
     }
 }
 
 template <class T>
-__global__ void key_unpack_kernel(const double *__restrict__ X, int64_t ld, T *__restrict__ dist,
-                                  int32_t *__restrict__ pred, int64_t n, int S,
-                                  int32_t *__restrict__ status, const int32_t *__restrict__ skip) {
+__global__ void pred_unpack_kernel(const void *__restrict__ Xv, int64_t ld, T *__restrict__ dist,
+                                   int32_t *__restrict__ pred, int64_t n, int S,
+                                   const int32_t *__restrict__ mode, int32_t *__restrict__ status,
+                                   const int32_t *__restrict__ skip) {
     if (skip && *skip != APSP_SUCCESS) return;
+    const bool lex = mode && *mode;
     const int64_t total = n * n;
     const int32_t none = (1 << S) - 1;
     bool neg = false;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e / n, j = e - i * n;
-        const double key = X[i * ld + j];
         T d;
         int32_t p;
-        if (key == __builtin_inf()) {
+        bool unreachable;
+        if (lex) {
+            const DistPred v = ((const DistPred *)Xv)[i * ld + j];
+            unreachable = v.d == __builtin_inff();
+            d = (T)v.d;
+            p = (v.p == kLexNone) ? APSP_NO_PRED : v.p;
+            if (i == j && v.d < 0.0f) neg = true;
+        } else {
+            const double key = ((const double *)Xv)[i * ld + j];
+            unreachable = key == __builtin_inf();
+            const double dd = unreachable ? 0.0 : __builtin_floor(__builtin_ldexp(key, -S));
+            p = unreachable ? APSP_NO_PRED : (int32_t)(key - __builtin_ldexp(dd, S));
+            d = (T)dd;
+            if (p == none) p = APSP_NO_PRED;
+            if (i == j && dd < 0.0) neg = true;
+        }
+        if (unreachable) {
             if constexpr (std::is_same_v<T, int32_t>)
                 d = kInf32;
             else
                 d = __builtin_inff();
             p = APSP_NO_PRED;
-        } else {
-            const double dd = __builtin_floor(__builtin_ldexp(key, -S));
-            p = (int32_t)(key - __builtin_ldexp(dd, S));
-            d = (T)dd;
-            if (p == none || i == j) p = APSP_NO_PRED;
-            if (i == j && dd < 0.0) neg = true;
         }
+        if (i == j) p = APSP_NO_PRED;
         dist[e] = d;
         if (pred) pred[e] = p;
     }
@@ -384,9 +416,9 @@ int pred_bits(int64_t ld) {
 }
 
 // The round loop on a work matrix of size ld (a multiple of BS).
-template <class Ar, int BS>
-apsp_status_t run_rounds(typename Ar::T *X, int64_t ld, const Ar &ar, hipStream_t s,
-                         const int32_t *skip) {
+template <class Ar, class Alt, int BS>
+apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, const int32_t *mode,
+                         hipStream_t s, const int32_t *skip) {
     constexpr int MT = BS >= 128 ? 128 : 64;
     constexpr int P2W = 64;
     const int R = (int)(ld / BS);
@@ -399,40 +431,42 @@ apsp_status_t run_rounds(typename Ar::T *X, int64_t ld, const Ar &ar, hipStream_
         const int64_t r0 = (int64_t)r * BS;
         {
             ProfScope ps(kPhase1, bs3, s);
-            hipLaunchKernelGGL((phase1_kernel<Ar, BS>), dim3(1), dim3(P1Shape<BS>::NTH), 0, s, X, ld,
-                               r0, ar, skip);
+            hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS>), dim3(1), dim3(P1Shape<BS>::NTH), 0, s, X,
+                               ld, r0, ar, alt, mode, skip);
         }
         if (nt2 > 0) {
             ProfScope ps(kPhase2, 2.0 * bs3 * (ld / BS - 1), s);
-            hipLaunchKernelGGL((phase2_kernel<Ar, BS, P2W>), dim3(2 * nt2), dim3((BS / 8) * (P2W / 8)),
-                               0, s, X, ld, r0, nt2, ar, skip);
+            hipLaunchKernelGGL((phase2_kernel<Ar, Alt, BS, P2W>), dim3(2 * nt2),
+                               dim3((BS / 8) * (P2W / 8)), 0, s, X, ld, r0, nt2, ar, alt, mode, skip);
         }
         if (tiles3 > 0) {
             ProfScope ps(kPhase3, (double)(ld - BS) * (ld - BS) * BS, s);
-            hipLaunchKernelGGL((phase3_kernel<Ar, BS, MT>), dim3(8 * per_xcd), dim3((MT / 8) * (MT / 8)),
-                               0, s, X, ld, r0, ntr, per_xcd, ar, skip);
+            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT>), dim3(8 * per_xcd),
+                               dim3((MT / 8) * (MT / 8)), 0, s, X, ld, r0, ntr, per_xcd, ar, alt, mode,
+                               skip);
         }
     }
     APSP_HIP(hipGetLastError());
     return APSP_SUCCESS;
 }
 
-template <class Ar>
-apsp_status_t run_rounds_bs(int bs, typename Ar::T *X, int64_t ld, const Ar &ar, hipStream_t s,
-                            const int32_t *skip) {
+template <class Ar, class Alt = NoAlt>
+apsp_status_t run_rounds_bs(int bs, void *X, int64_t ld, const Ar &ar, hipStream_t s,
+                            const int32_t *skip, const Alt &alt = Alt{}, const int32_t *mode = nullptr) {
     switch (bs) {
-        case 64: return run_rounds<Ar, 64>(X, ld, ar, s, skip);
-        case 128: return run_rounds<Ar, 128>(X, ld, ar, s, skip);
+        case 64: return run_rounds<Ar, Alt, 64>(X, ld, ar, alt, mode, s, skip);
+        case 128: return run_rounds<Ar, Alt, 128>(X, ld, ar, alt, mode, s, skip);
         case 256:
-            if constexpr (sizeof(typename Ar::T) == 4) return run_rounds<Ar, 256>(X, ld, ar, s, skip);
+            if constexpr (sizeof(typename Ar::T) == 4)
+                return run_rounds<Ar, Alt, 256>(X, ld, ar, alt, mode, s, skip);
             return APSP_ERROR_INVALID_ARGUMENT;
         default: return APSP_ERROR_INVALID_ARGUMENT;
     }
 }
 
-int auto_block(int64_t n, bool key) {
+int auto_block(int64_t n, bool pred) {
     if (n <= 64) return 64;
-    if (key || n <= 4096) return 128;
+    if (pred || n <= 4096) return 128;
     return 256;
 }
 
@@ -441,9 +475,9 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
                           const apsp_options_t &opt) {
     int dev = 0;
     APSP_HIP(hipGetDevice(&dev));
-    const bool key = pred != nullptr;
-    const int bs = opt.block_size ? opt.block_size : auto_block(n, key);
-    if (key && bs == 256) return APSP_ERROR_INVALID_ARGUMENT;
+    const bool with_pred = pred != nullptr;
+    const int bs = opt.block_size ? opt.block_size : auto_block(n, with_pred);
+    if (with_pred && bs == 256) return APSP_ERROR_INVALID_ARGUMENT;
     const int64_t ld = (n + bs - 1) / bs * bs;
     int32_t *status = opt.d_status;
     const int32_t *skip = nullptr;
@@ -454,7 +488,7 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         skip = status;
     }
     constexpr T inf = std::is_same_v<T, int32_t> ? T(kInf32) : T(__builtin_huge_valf());
-    if (!key) {
+    if (!with_pred) {
         T *X = dist;
         const bool inplace = (ld == n) && ((uintptr_t)dist % 16 == 0);
         if (!inplace) {
@@ -467,24 +501,35 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         }
         apsp_status_t st;
         if constexpr (std::is_same_v<T, int32_t>)
-            st = run_rounds_bs<ArI32>(bs, (int32_t *)X, ld, ArI32{}, s, skip);
+            st = run_rounds_bs<ArI32>(bs, X, ld, ArI32{}, s, skip);
         else
-            st = run_rounds_bs<ArF32>(bs, (float *)X, ld, ArF32{}, s, skip);
+            st = run_rounds_bs<ArF32>(bs, X, ld, ArF32{}, s, skip);
         if (st != APSP_SUCCESS) return st;
         hipLaunchKernelGGL((finalize_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, X, ld, dist, n,
                            status, skip);
     } else {
+        // ld^2 8-byte elements, then one int32 mode word
         void *w = nullptr;
-        apsp_status_t st = workspace(dev, s, (size_t)(ld * ld) * sizeof(double), &w);
+        const size_t mat = (size_t)(ld * ld) * 8;
+        apsp_status_t st = workspace(dev, s, mat + 256, &w);
         if (st != APSP_SUCCESS) return st;
-        double *X = (double *)w;
+        int32_t *mode = nullptr;
         ArKey ar{pred_bits(ld)};
-        hipLaunchKernelGGL((key_pack_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n, X, ld,
-                           ar.S, skip);
-        st = run_rounds_bs<ArKey>(bs, X, ld, ar, s, skip);
+        if constexpr (std::is_same_v<T, float>) {
+            mode = (int32_t *)((char *)w + mat);
+            hipLaunchKernelGGL(mode_init_kernel, dim3(1), dim3(1), 0, s, mode);
+            hipLaunchKernelGGL(integral_check_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, dist, n,
+                               (float)apsp_weight_bound(n), mode);
+        }
+        hipLaunchKernelGGL((pred_pack_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n, w,
+                           ld, ar.S, mode, skip);
+        if constexpr (std::is_same_v<T, float>)
+            st = run_rounds_bs<ArKey, ArLexF32>(bs, w, ld, ar, s, skip, ArLexF32{}, mode);
+        else
+            st = run_rounds_bs<ArKey>(bs, w, ld, ar, s, skip);
         if (st != APSP_SUCCESS) return st;
-        hipLaunchKernelGGL((key_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, X, ld, dist,
-                           pred, n, ar.S, status, skip);
+        hipLaunchKernelGGL((pred_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, w, ld, dist,
+                           pred, n, ar.S, mode, status, skip);
     }
     APSP_HIP(hipGetLastError());
     return APSP_SUCCESS;
@@ -518,7 +563,7 @@ int apsp_last_hip_error(void) { return g_last_hip; }
 
 int apsp_version(void) { return 100; }
 
-int64_t apsp_weight_bound(int64_t n) { return n <= 1 ? (1LL << 28) - 1 : ((1LL << 28) - 1) / (n - 1); }
+int64_t apsp_weight_bound(int64_t n) { return weight_bound(n); }
 
 apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype,
                             hipStream_t stream, const apsp_options_t *options) {
@@ -585,6 +630,7 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out) {
 apsp_status_t apsp_release_workspace(void) {
     int dev = 0;
     APSP_HIP(hipGetDevice(&dev));
+    sweep_retired(true);
     std::lock_guard<std::mutex> lk(g_ws_mu);
     APSP_HIP(hipDeviceSynchronize());
     for (auto it = g_ws.begin(); it != g_ws.end();) {

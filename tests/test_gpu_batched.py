@@ -1,0 +1,162 @@
+"""GPU parity of the batched fused launch: every graph of a packed ragged
+batch against the oracle (and against apsp_solve on the same graph)."""
+import numpy as np
+import pytest
+
+import pins
+import synth
+from gpu_util import describe, first_mismatch, gpu_solve
+
+pytestmark = pytest.mark.gpu
+INF32 = synth.INF32
+
+
+def _pack(graphs, dtype):
+    ns = np.array([g.shape[0] for g in graphs], dtype=np.int32)
+    sizes = ns.astype(np.int64) ** 2
+    offsets = np.zeros(len(graphs), dtype=np.int64)
+    offsets[1:] = np.cumsum((sizes + 3) // 4 * 4)[:-1]
+    total = int(offsets[-1] + sizes[-1]) if len(graphs) else 0
+    fill = INF32 if dtype == np.int32 else np.inf
+    buf = np.full(max(total, 4), fill, dtype=dtype)
+    for g, o in zip(graphs, offsets):
+        buf[o:o + g.size] = g.ravel()
+    return buf, ns, offsets
+
+
+def _run(graphs, dtype, pred, reps=1):
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    buf, ns, offs = _pack(graphs, dtype)
+    plan = apsp.BatchPlan(ns, offs, "int32" if dtype == np.int32 else "float32", want_pred=pred)
+    outs = []
+    for _ in range(reps):
+        d = torch.from_numpy(buf.copy()).cuda()
+        p = torch.full(d.shape, -7, dtype=torch.int32, device="cuda") if pred else None
+        st = torch.full((len(graphs),), -1, dtype=torch.int32, device="cuda")
+        plan.execute(d, p, st)
+        torch.cuda.synchronize()
+        outs.append((d.cpu().numpy(), p.cpu().numpy() if pred else None, st.cpu().numpy()))
+    plan.destroy()
+    return outs, ns, offs
+
+
+def _graphs(kind, sizes, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for b, n in enumerate(sizes):
+        p = float(rng.uniform(0.05, 0.9))
+        if kind == "int":
+            out.append(synth.int32_rows(n, p, 1, 1000, seed, g=b))
+        elif kind == "f32":
+            out.append(synth.single_f32int(n, p, seed=seed, g=b))
+        elif kind == "half":
+            W = pins.random_graph(rng, n, p, 0, 3, dtype=np.float32)
+            fin = np.isfinite(W) & ~np.eye(n, dtype=bool)
+            W[fin] += 0.5
+            out.append(W)
+        elif kind == "pot":
+            out.append(synth.potential_int32(n, p=0.1, seed=seed, g=b))
+    return out
+
+
+SIZES = [1, 2, 5, 16, 17, 33, 63, 64, 65, 100, 127, 128, 129, 190, 255, 256, 257, 300, 511, 512, 513,
+         700, 1024, 40, 3, 64, 200]
+
+
+@pytest.mark.parametrize("kind,pred", [("int", False), ("int", True), ("f32", False), ("f32", True),
+                                       ("half", True), ("pot", False), ("pot", True)])
+def test_batched_matches_oracle(orc, kind, pred):
+    describe(f"batched kind={kind} pred={pred}")
+    graphs = _graphs(kind, SIZES, seed=100 + len(kind))
+    dtype = np.int32 if kind in ("int", "pot") else np.float32
+    (out,), ns, offs = _run(graphs, dtype, pred)
+    D, P, st = out
+    for b, W in enumerate(graphs):
+        n = W.shape[0]
+        o = int(offs[b])
+        D0, P0, s0 = orc.fw(W, pred=pred)
+        if dtype == np.float32:
+            D0 = D0.astype(np.float32)
+        got = D[o:o + n * n].reshape(n, n)
+        assert first_mismatch(got, D0) is None, (b, n, first_mismatch(got, D0))
+        if pred:
+            gp = P[o:o + n * n].reshape(n, n)
+            assert first_mismatch(gp, P0) is None, (b, n, first_mismatch(gp, P0))
+        assert st[b] == 0
+
+
+def test_batched_replay_and_negative_cycle_status(orc):
+    describe("batched replay + status")
+    graphs = _graphs("int", [70, 10, 300, 64, 129], seed=7)
+    graphs[1] = graphs[1].copy()
+    graphs[1][2, 3], graphs[1][3, 2] = 4, -9
+    graphs[2] = graphs[2].copy()
+    graphs[2][5, 200], graphs[2][200, 5] = 1, -3
+    outs, ns, offs = _run(graphs, np.int32, False, reps=3)
+    for D, _, st in outs:
+        assert list(st) == [0, 3, 3, 0, 0]
+        assert np.array_equal(D, outs[0][0])
+    D = outs[0][0]
+    for b in (0, 3, 4):
+        n = graphs[b].shape[0]
+        o = int(offs[b])
+        D0, _, _ = orc.fw(graphs[b])
+        assert np.array_equal(D[o:o + n * n].reshape(n, n), D0)
+
+
+def test_batched_equals_single_and_one_shot():
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe("batched == single")
+    graphs = _graphs("int", [300, 64, 17, 129], seed=9)
+    (out,), ns, offs = _run(graphs, np.int32, True)
+    D, P, _ = out
+    for b, W in enumerate(graphs):
+        n = W.shape[0]
+        o = int(offs[b])
+        Ds, Ps, _ = gpu_solve(W, pred=True)
+        assert np.array_equal(D[o:o + n * n].reshape(n, n), Ds)
+        assert np.array_equal(P[o:o + n * n].reshape(n, n), Ps)
+    buf, ns, offs = _pack(graphs, np.int32)
+    d = torch.from_numpy(buf.copy()).cuda()
+    apsp.solve_batched(d, ns, offs)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy()
+    for b, W in enumerate(graphs):
+        n = W.shape[0]
+        o = int(offs[b])
+        assert np.array_equal(got[o:o + n * n], D[o:o + n * n])
+
+
+def test_batched_full_workload_sampled(orc):
+    """The 4096-graph batch (n uniform in [16, 512], p uniform in [0.05, 0.9],
+    int32 weights 1..1000) at full size; 48 graphs across the size range are
+    compared with the oracle, every graph's diagonal is checked."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe("batched full 4096")
+    bt = synth.batch()
+    buf = bt.pack_int32()
+    plan = apsp.BatchPlan(bt.ns, bt.offsets, "int32")
+    d = torch.from_numpy(buf).cuda()
+    st = torch.full((len(bt.ns),), -1, dtype=torch.int32, device="cuda")
+    plan.execute(d, status=st)
+    torch.cuda.synchronize()
+    D = d.cpu().numpy()
+    assert (st.cpu().numpy() == 0).all()
+    order = np.argsort(bt.ns)
+    picks = order[np.linspace(0, len(order) - 1, 48).astype(int)]
+    for b in picks:
+        n = int(bt.ns[b])
+        o = int(bt.offsets[b])
+        D0, _, _ = orc.fw(bt.graph(b))
+        assert np.array_equal(D[o:o + n * n].reshape(n, n), D0), (b, n)
+    for b in range(len(bt.ns)):
+        n = int(bt.ns[b])
+        o = int(bt.offsets[b])
+        assert (D[o:o + n * n:n + 1] == 0).all()
+    plan.destroy()

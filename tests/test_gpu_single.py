@@ -159,3 +159,49 @@ def test_full_size_n8192_f32_pred_sampled_rows(orc):
         assert np.array_equal(D[src], dr.astype(np.float32)), src
         assert np.array_equal(P[src], pr), src
     assert (np.diag(D) == 0).all()
+
+
+@pytest.mark.parametrize("n", [100, 257])
+def test_half_integer_float32_pred_exact(orc, n):
+    """Non-integer weights switch predecessor solves to (distance, predecessor)
+    pairs; half-integers keep every float32 sum exact, so distances and the
+    canonical predecessors (with many ties) must still match bit for bit."""
+    describe(f"single half-integer f32 pred n={n}")
+    rng = np.random.default_rng(n)
+    W = pins.random_graph(rng, n, 0.3, 0, 2, dtype=np.float32)
+    fin = np.isfinite(W) & ~np.eye(n, dtype=bool)
+    W[fin] += 0.5
+    D0, P0, _ = orc.fw(W, pred=True)
+    D, P, st = gpu_solve(W, pred=True)
+    assert st == 0
+    assert first_mismatch(D, D0.astype(np.float32)) is None
+    assert first_mismatch(P, P0) is None, first_mismatch(P, P0)
+
+
+def test_float32_pred_weight_beyond_key_bound(orc):
+    """An integer weight above the key-mode bound also takes the pair path."""
+    describe("single f32 pred big weight")
+    n = 200
+    W = synth.single_f32int(n, p=0.2, seed=12)
+    W[3, 7] = 1.0e7
+    D0, P0, _ = orc.fw(W, pred=True)
+    D, P, st = gpu_solve(W, pred=True)
+    assert st == 0
+    assert first_mismatch(D, D0.astype(np.float32)) is None
+    assert first_mismatch(P, P0) is None
+
+
+def test_real_valued_float32_pred_chains(orc):
+    describe("single real f32 pred n=300")
+    n = 300
+    W = synth.single_f32real(n, p=0.05, lo=0.5, hi=100.0, seed=6)
+    D0, _, _ = orc.fw(W)
+    D, P, st = gpu_solve(W, pred=True)
+    assert st == 0
+    fin = np.isfinite(D0)
+    assert np.array_equal(np.isfinite(D), fin)
+    rel = np.abs(D[fin].astype(np.float64) - D0[fin]) / np.maximum(1.0, np.abs(D0[fin]))
+    assert rel.max() <= 1e-6
+    for i in range(0, n, 23):
+        for j in range(n):
+            assert pins.walk_pred_chain(W, D, P, i, j, tol=1e-5), (i, j)
