@@ -203,11 +203,25 @@ apsp_status_t apsp_solve_batched(void *packed_dist, int32_t *packed_pred, const 
 
 /* ------------------------------------------------------------------ server
  *
- * A request loop on one GPU: requests (host weight matrices) are copied
- * into library-owned device slots when the HBM budget and the in-flight
- * limit allow, solved with their work overlapping other requests' work on
- * the device (small graphs are coalesced into batched launches), and their
- * distance/predecessor matrices stay resident until released.
+ * A request loop on one GPU with continuous batching.  apsp_server_submit
+ * copies the host weights (n x n, row-major, dtype) into library-owned
+ * pinned memory and queues the request; a scheduler thread admits queued
+ * requests in arrival order whenever the device-memory budget
+ * (hbm_budget_bytes) and the resident-request limit (max_inflight) allow,
+ * and launches them without waiting for earlier work: requests admitted
+ * together with n <= batch_max_n are coalesced per (dtype, predecessors)
+ * into one batched fused launch, larger ones run apsp_solve on one of
+ * n_streams streams, so work of different requests overlaps on the device.
+ * Results (distances, and predecessors when asked for) stay resident in
+ * device memory until apsp_server_release, which returns their bytes to the
+ * budget.  Each result equals what apsp_solve computes for that request
+ * alone.  A request whose footprint exceeds the whole budget is refused at
+ * submit with APSP_ERROR_OUT_OF_MEMORY; a full queue gives
+ * APSP_ERROR_QUEUE_FULL.  Latency = completion observed by the scheduler
+ * (event polled every 50 us) minus entry into apsp_server_submit.
+ * All calls are thread-safe; apsp_server_destroy must not overlap other
+ * calls on the same server except waits already blocked in
+ * apsp_server_wait (they return APSP_ERROR_CANCELLED).
  */
 typedef struct apsp_server apsp_server_t;
 
@@ -216,14 +230,19 @@ typedef struct {
     int32_t max_inflight;     /* requests resident at once (0 = 64) */
     int32_t n_streams;        /* HIP streams used for large requests (0 = 4) */
     int32_t max_queue;        /* pending requests before submit fails (0 = 4096) */
-    int32_t batch_max_n;      /* requests with n <= this are coalesced (0 = 512) */
+    int32_t batch_max_n;      /* requests with n <= this are coalesced into batched launches
+                                 (0 = 512, negative = never; at most 1024) */
 } apsp_server_config_t;
 
 typedef struct {
-    const void *weights; /* host, n*n elements of dtype, row-major; copied during submit */
+    const void *weights; /* host, n rows of n elements of dtype, row-major, leading dimension ld */
     int64_t n;
+    int64_t ld;          /* elements between row starts (0 = n) */
     apsp_dtype_t dtype;
     int32_t want_pred;
+    int32_t borrow;      /* 0: weights are copied during submit; nonzero: weights are pinned host
+                            memory (hipHostMalloc) that stays valid and unchanged until the
+                            request completes, uploaded directly without a host copy */
 } apsp_request_t;
 
 typedef struct {

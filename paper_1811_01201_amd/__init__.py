@@ -67,6 +67,9 @@ def lib():
     """Load libapsp.so (built by ``python -m paper_1811_01201_amd._build``)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime: load it first so libapsp.so binds to the
+        # same libamdhip64 instance (two runtimes in one process cannot share a GPU)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1811_01201_amd._build`")
@@ -249,3 +252,116 @@ def solve_batched(packed_dist, ns, offsets, packed_pred=None, stream=None) -> No
                                   _dtype_code(packed_dist), _stream_ptr(stream))
     if st != SUCCESS:
         raise APSPError(st, "apsp_solve_batched")
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("batch_max_n", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("weights", ctypes.c_void_p), ("n", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("dtype", ctypes.c_int), ("want_pred", ctypes.c_int32), ("borrow", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("inflight", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_int64), ("p50_latency_ms", ctypes.c_double),
+                ("p99_latency_ms", ctypes.c_double), ("solves_per_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Server:
+    """Request loop with continuous batching on the current device (see
+    include/apsp.h).  Weights are numpy arrays (copied at submit) or, with
+    borrow=True, pinned host tensors that stay alive until completion."""
+
+    def __init__(self, hbm_budget_bytes=0, max_inflight=0, n_streams=0, max_queue=0, batch_max_n=0):
+        self._h = ctypes.c_void_p()
+        cfg = ServerConfig(int(hbm_budget_bytes), int(max_inflight), int(n_streams), int(max_queue),
+                           int(batch_max_n))
+        st = lib().apsp_server_create(ctypes.byref(cfg), ctypes.byref(self._h))
+        if st != SUCCESS:
+            raise APSPError(st, "apsp_server_create")
+        self._dtypes = {}
+
+    def submit(self, weights, want_pred=False, n=None, ld=None, borrow=False, check=True):
+        """weights: numpy int32/float32 [n, >=n] C-contiguous rows, or (borrow=True) a
+        pinned torch CPU tensor.  Returns the ticket (or the status if check=False)."""
+        import numpy as np
+        if hasattr(weights, "data_ptr"):
+            ptr = weights.data_ptr()
+            rows, cols = weights.shape
+            dt = INT32 if str(weights.dtype).endswith("int32") else FLOAT32
+            stride = weights.stride(0)
+        else:
+            assert weights.flags.c_contiguous
+            ptr = weights.ctypes.data
+            rows, cols = weights.shape
+            dt = INT32 if weights.dtype == np.int32 else FLOAT32
+            stride = cols
+        n = rows if n is None else n
+        req = Request(ptr, int(n), int(ld if ld is not None else stride), dt, int(want_pred),
+                      int(borrow))
+        t = ctypes.c_uint64()
+        st = lib().apsp_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if st != SUCCESS:
+            if check:
+                raise APSPError(st, "apsp_server_submit")
+            return st
+        self._dtypes[t.value] = (dt, int(n), bool(want_pred))
+        return t.value
+
+    def poll(self, ticket) -> int:
+        return lib().apsp_server_poll(self._h, ticket)
+
+    def wait(self, ticket, timeout_us=-1) -> int:
+        return lib().apsp_server_wait(self._h, ticket, int(timeout_us))
+
+    def device_result(self, ticket):
+        d = ctypes.c_void_p()
+        p = ctypes.c_void_p()
+        st = lib().apsp_server_result(self._h, ticket, ctypes.byref(d), ctypes.byref(p))
+        if st != SUCCESS:
+            raise APSPError(st, "apsp_server_result")
+        return d.value, p.value
+
+    def result(self, ticket):
+        """Copy a finished request's (distances, predecessors or None) to numpy."""
+        import numpy as np
+        dt, n, wp = self._dtypes[ticket]
+        D = np.empty((n, n), dtype=np.int32 if dt == INT32 else np.float32)
+        P = np.empty((n, n), dtype=np.int32) if wp else None
+        st = lib().apsp_server_copy_result(self._h, ticket, D.ctypes.data,
+                                           P.ctypes.data if P is not None else None)
+        if st != SUCCESS:
+            raise APSPError(st, "apsp_server_copy_result")
+        return D, P
+
+    def release(self, ticket) -> int:
+        st = lib().apsp_server_release(self._h, ticket)
+        self._dtypes.pop(ticket, None)
+        return st
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        st = lib().apsp_server_stats(self._h, ctypes.byref(s))
+        if st != SUCCESS:
+            raise APSPError(st, "apsp_server_stats")
+        return s.as_dict()
+
+    def destroy(self) -> None:
+        if self._h:
+            lib().apsp_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()

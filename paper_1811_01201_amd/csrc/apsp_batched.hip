@@ -350,17 +350,17 @@ apsp_status_t retire(apsp_batch_plan_t *p, hipStream_t s) {
 }
 
 template <class Tin, class Ar, class Alt>
-apsp_status_t launch(const apsp_batch_plan_t *p, void *dist, int32_t *pred, int32_t *status,
-                     hipStream_t s, Ar ar, Alt alt) {
+apsp_status_t launch(const BatchLaunch &L, void *dist, int32_t *pred, int32_t *status, hipStream_t s,
+                     Ar ar, Alt alt) {
     BatchMeta m;
-    m.order = (const int32_t *)p->dev_meta;
-    m.ns = m.order + p->batch;
-    m.offsets = (const int64_t *)((const char *)p->dev_meta + (size_t)p->batch * 8);
-    m.batch = p->batch;
-    m.n_team = p->n_team;
-    m.scratch_elems = p->scratch_elems;
-    hipLaunchKernelGGL((batched_kernel<Tin, Ar, Alt>), dim3(p->grid), dim3(kBatchThreads), 0, s, m,
-                       (Tin *)dist, pred, status, p->scratch, p->counters, ar, alt);
+    m.order = (const int32_t *)L.meta;
+    m.ns = m.order + L.batch;
+    m.offsets = (const int64_t *)((const char *)L.meta + (size_t)L.batch * 8);
+    m.batch = L.batch;
+    m.n_team = L.n_team;
+    m.scratch_elems = L.scratch_elems;
+    hipLaunchKernelGGL((batched_kernel<Tin, Ar, Alt>), dim3(L.grid), dim3(kBatchThreads), 0, s, m,
+                       (Tin *)dist, pred, status, L.scratch, L.counters, ar, alt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         t_last_hip = (int)e;
@@ -372,6 +372,26 @@ apsp_status_t launch(const apsp_batch_plan_t *p, void *dist, int32_t *pred, int3
 }  // namespace
 
 namespace apsp {
+
+apsp_status_t batched_launch(const BatchLaunch &L, apsp_dtype_t dtype, bool want_pred, void *dist,
+                             int32_t *pred, int32_t *status, hipStream_t s) {
+    if (L.batch == 0) return APSP_SUCCESS;
+    if (dtype == APSP_INT32) {
+        if (want_pred) return launch<int32_t>(L, dist, pred, status, s, ArKey{7}, NoAlt{});
+        return launch<int32_t>(L, dist, nullptr, status, s, ArI32{}, NoAlt{});
+    }
+    if (want_pred) return launch<float>(L, dist, pred, status, s, ArKey{7}, ArLexF32{});
+    return launch<float>(L, dist, nullptr, status, s, ArF32{}, NoAlt{});
+}
+
+void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, int32_t &n_team) {
+    order.resize(batch);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ns[a] > ns[b]; });
+    n_team = 0;
+    while (n_team < batch && ns[order[n_team]] > kBatchBS) ++n_team;
+}
+
 // wait == true: block until every retired plan can be freed.
 void sweep_retired(bool wait) {
     std::lock_guard<std::mutex> lk(g_retired_mu);
@@ -425,11 +445,8 @@ apsp_status_t apsp_batch_plan_create(const int32_t *ns, const int64_t *offsets, 
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
 
-    std::vector<int32_t> order(batch);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ns[a] > ns[b]; });
-    p->n_team = 0;
-    while (p->n_team < batch && ns[order[p->n_team]] > kBatchBS) ++p->n_team;
+    std::vector<int32_t> order;
+    batch_order(ns, batch, order, p->n_team);
     const int64_t ldp_max = std::max<int64_t>(kBatchBS, (max_n + kBatchBS - 1) / kBatchBS * kBatchBS);
     p->scratch_elems = p->n_team > 0 ? ldp_max * ldp_max : 0;
     p->grid = std::max(1, 2 * cus);
@@ -464,14 +481,9 @@ apsp_status_t apsp_batch_plan_execute(const apsp_batch_plan_t *plan, void *packe
     if (!packed_dist || (plan->want_pred && !packed_pred) || (!plan->want_pred && packed_pred))
         return APSP_ERROR_INVALID_ARGUMENT;
     if ((uintptr_t)packed_dist % 16 || (uintptr_t)packed_pred % 16) return APSP_ERROR_INVALID_ARGUMENT;
-    if (plan->dtype == APSP_INT32) {
-        if (plan->want_pred)
-            return launch<int32_t>(plan, packed_dist, packed_pred, d_status, stream, ArKey{7}, NoAlt{});
-        return launch<int32_t>(plan, packed_dist, nullptr, d_status, stream, ArI32{}, NoAlt{});
-    }
-    if (plan->want_pred)
-        return launch<float>(plan, packed_dist, packed_pred, d_status, stream, ArKey{7}, ArLexF32{});
-    return launch<float>(plan, packed_dist, nullptr, d_status, stream, ArF32{}, NoAlt{});
+    BatchLaunch L{plan->dev_meta, plan->batch, plan->n_team, plan->scratch_elems, plan->scratch,
+                  plan->counters, plan->grid};
+    return batched_launch(L, plan->dtype, plan->want_pred, packed_dist, packed_pred, d_status, stream);
 }
 
 apsp_status_t apsp_batch_plan_destroy(apsp_batch_plan_t *plan) { return plan_free(plan); }

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <vector>
 
 #include "apsp.h"
 
@@ -25,6 +26,28 @@ __host__ __device__ inline int64_t weight_bound(int64_t n) {
 }
 
 void sweep_retired(bool wait);
+
+// Single-graph solve with optional caller-provided work memory (ws may be
+// null: the per-(device, stream) cache is used).  Arguments already checked.
+apsp_status_t solve_internal(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t s,
+                             const apsp_options_t &opt, void *ws, size_t ws_bytes);
+// Work memory solve_internal needs for (n, pred) with automatic block size
+// and a 16-byte aligned dist.
+size_t solve_work_bytes(int64_t n, apsp_dtype_t dtype, bool with_pred);
+
+// Batched launch on caller-owned metadata (see apsp_batched.hip).
+struct BatchLaunch {
+    const void *meta;       // order[batch] int32 | ns[batch] int32 | offsets[batch] int64
+    int32_t batch, n_team;
+    int64_t scratch_elems;  // per workgroup
+    void *scratch;          // grid * scratch_elems * (4 or 8 bytes)
+    int32_t *counters;      // 4 int32, zero before the first launch
+    int grid;
+};
+apsp_status_t batched_launch(const BatchLaunch &L, apsp_dtype_t dtype, bool want_pred, void *dist,
+                             int32_t *pred, int32_t *status, hipStream_t s);
+// Host side of a plan: device metadata bytes for (ns, offsets), largest first.
+void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, int32_t &n_team);
 
 // ---------------------------------------------------------------------------
 // Arithmetic policies.  Each supplies the element type T, the number of

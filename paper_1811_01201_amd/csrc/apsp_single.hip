@@ -345,7 +345,7 @@ std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
 // Device workspace private to (device, stream): work on one stream is
 // ordered, so reusing it across calls on that stream is race-free.
-apsp_status_t workspace(int dev, hipStream_t s, size_t bytes, void **out) {
+apsp_status_t cached_workspace(int dev, hipStream_t s, size_t bytes, void **out) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace &w = g_ws[{dev, s}];
     if (w.bytes < bytes) {
@@ -470,13 +470,30 @@ int auto_block(int64_t n, bool pred) {
     return 256;
 }
 
+// Work memory a solve needs beyond dist/pred (0 when it runs in place).
+size_t work_bytes(int64_t n, bool with_pred, int bs, bool aligned) {
+    const int64_t ld = (n + bs - 1) / bs * bs;
+    if (with_pred) return (size_t)(ld * ld) * 8 + 256;
+    if (ld == n && aligned) return 0;
+    return (size_t)(ld * ld) * 4;
+}
+
 template <class T>
 apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
-                          const apsp_options_t &opt) {
+                          const apsp_options_t &opt, void *ext_ws, size_t ext_bytes) {
     int dev = 0;
     APSP_HIP(hipGetDevice(&dev));
     const bool with_pred = pred != nullptr;
     const int bs = opt.block_size ? opt.block_size : auto_block(n, with_pred);
+    // caller-provided work memory (the server) or the per-stream cache
+    auto workspace = [&](int d, hipStream_t st, size_t bytes, void **out) -> apsp_status_t {
+        if (ext_ws) {
+            if (ext_bytes < bytes) return APSP_ERROR_INVALID_ARGUMENT;
+            *out = ext_ws;
+            return APSP_SUCCESS;
+        }
+        return cached_workspace(d, st, bytes, out);
+    };
     if (with_pred && bs == 256) return APSP_ERROR_INVALID_ARGUMENT;
     const int64_t ld = (n + bs - 1) / bs * bs;
     int32_t *status = opt.d_status;
@@ -536,6 +553,18 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
 }
 
 }  // namespace
+
+size_t solve_work_bytes(int64_t n, apsp_dtype_t, bool with_pred) {
+    return work_bytes(n, with_pred, auto_block(n, with_pred), true);
+}
+
+apsp_status_t solve_internal(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t s,
+                             const apsp_options_t &opt, void *ws, size_t ws_bytes) {
+    if (n == 0) return APSP_SUCCESS;
+    if (dtype == APSP_INT32) return solve_typed<int32_t>((int32_t *)dist, pred, n, s, opt, ws, ws_bytes);
+    return solve_typed<float>((float *)dist, pred, n, s, opt, ws, ws_bytes);
+}
+
 }  // namespace apsp
 
 using namespace apsp;
@@ -578,8 +607,7 @@ apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t d
     if (n == 0) return APSP_SUCCESS;
     if (!dist || ((uintptr_t)dist % 4) != 0 || ((uintptr_t)pred % 4) != 0)
         return APSP_ERROR_INVALID_ARGUMENT;
-    if (dtype == APSP_INT32) return solve_typed<int32_t>((int32_t *)dist, pred, n, stream, opt);
-    return solve_typed<float>((float *)dist, pred, n, stream, opt);
+    return solve_internal(dist, pred, n, dtype, stream, opt, nullptr, 0);
 }
 
 apsp_status_t apsp_solve(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t stream) {

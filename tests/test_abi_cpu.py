@@ -61,3 +61,41 @@ def test_weight_bound_matches_definition():
     for n in [1, 2, 3, 1024, 8192, 32768, 65536]:
         expect = (2 ** 28 - 1) if n <= 1 else (2 ** 28 - 1) // (n - 1)
         assert apsp.weight_bound(n) == expect
+
+
+def test_server_host_argument_errors():
+    L = apsp.lib()
+    t = ctypes.c_uint64()
+    req = apsp.Request(None, 10, 0, apsp.INT32, 0, 0)
+    assert L.apsp_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == apsp.INVALID_ARGUMENT
+    assert L.apsp_server_poll(None, 1) == apsp.INVALID_ARGUMENT
+    assert L.apsp_server_wait(None, 1, 0) == apsp.INVALID_ARGUMENT
+    assert L.apsp_server_release(None, 1) == apsp.INVALID_ARGUMENT
+    assert L.apsp_server_destroy(None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_server_create(None, None) == apsp.INVALID_ARGUMENT
+    bad = apsp.ServerConfig(-1, 0, 0, 0, 0)
+    out = ctypes.c_void_p()
+    assert L.apsp_server_create(ctypes.byref(bad), ctypes.byref(out)) == apsp.INVALID_ARGUMENT
+    bad = apsp.ServerConfig(0, 0, 0, 0, 2048)
+    assert L.apsp_server_create(ctypes.byref(bad), ctypes.byref(out)) == apsp.INVALID_ARGUMENT
+
+
+def test_batch_plan_host_argument_errors():
+    import numpy as np
+    L = apsp.lib()
+    plan = ctypes.c_void_p()
+    ns = np.array([10, 20], dtype=np.int32)
+    offs = np.array([0, 100], dtype=np.int64)
+    assert L.apsp_batch_plan_create(ns.ctypes.data, offs.ctypes.data, 2, 0, 0, None) == apsp.INVALID_ARGUMENT
+    bad = np.array([0, 96], dtype=np.int64)   # 10*10 = 100 > 96: overlapping graphs
+    assert L.apsp_batch_plan_create(ns.ctypes.data, bad.ctypes.data, 2, 0, 0,
+                                    ctypes.byref(plan)) == apsp.INVALID_ARGUMENT
+    bad = np.array([0, 102], dtype=np.int64)  # not a multiple of 4
+    assert L.apsp_batch_plan_create(ns.ctypes.data, bad.ctypes.data, 2, 0, 0,
+                                    ctypes.byref(plan)) == apsp.INVALID_ARGUMENT
+    big = np.array([10, 1025], dtype=np.int32)
+    assert L.apsp_batch_plan_create(big.ctypes.data, offs.ctypes.data, 2, 0, 0,
+                                    ctypes.byref(plan)) == apsp.INVALID_ARGUMENT
+    assert L.apsp_batch_plan_create(ns.ctypes.data, offs.ctypes.data, 2, 5, 0,
+                                    ctypes.byref(plan)) == apsp.INVALID_ARGUMENT
+    assert L.apsp_batch_plan_execute(None, None, None, None, None) == apsp.INVALID_ARGUMENT
