@@ -63,6 +63,124 @@ def cpu_baseline(W, budget_s: float):
     }
 
 
+def batched_leg(replays: int):
+    """4096 graphs (n uniform in [16, 512], p uniform in [0.05, 0.9], int32
+    weights 1..1000) in one fused launch per replay, against the same graphs
+    solved one apsp_solve launch sequence per graph on one stream."""
+    import numpy as np
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    import synth
+
+    bt = synth.batch()
+    pristine = torch.from_numpy(bt.pack_int32()).cuda()
+    d = torch.empty_like(pristine)
+    plan = apsp.BatchPlan(bt.ns, bt.offsets, "int32")
+    ops = float((2.0 * bt.ns.astype(np.float64) ** 3).sum())
+    times = []
+    for r in range(replays + 1):
+        d.copy_(pristine)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.execute(d)
+        e1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            times.append(e0.elapsed_time(e1))
+    med = float(np.median(times))
+    views = [d[int(o):int(o) + int(n) * int(n)].view(int(n), int(n)) for n, o in zip(bt.ns, bt.offsets)]
+    d.copy_(pristine)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for v in views:
+        apsp.solve(v)
+    e1.record()
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1)
+    plan.destroy()
+    return {
+        "workload": "4096 graphs, n uniform int [16,512], edge prob uniform [0.05,0.9], int32 w in [1,1000], "
+                    "packed ragged, one fused launch",
+        "solves_per_s": round(4096 / (med / 1e3), 1),
+        "batch_ms_median": round(med, 3),
+        "batch_ms_p99": round(float(np.percentile(times, 99)), 3),
+        "replays": replays,
+        "gops": round(ops / (med / 1e3) / 1e9, 1),
+        "one_graph_per_launch": {"solves_per_s": round(4096 / (loop_ms / 1e3), 1), "batch_ms": round(loop_ms, 3)},
+        "speedup_vs_one_graph_per_launch": round(loop_ms / med, 2),
+    }
+
+
+def serving_leg(count: int):
+    """Poisson request streams (n log-uniform in [32, 8192], int32 / float32
+    integer weights 1..1000 half each, p=0.2, predecessors for 30%) through
+    the server at its saturated rate and at 0.5x / 0.9x of it; the same
+    saturated stream through a FIFO one-request-at-a-time server."""
+    import threading
+
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    import synth
+
+    nmax = 8192
+    base = {"int32": torch.from_numpy(synth.single_int32(nmax, 0.2, seed=synth.BASE_SEED + 4)).pin_memory(),
+            "float32": torch.from_numpy(synth.single_f32int(nmax, 0.2, seed=synth.BASE_SEED + 4)).pin_memory()}
+
+    def run(rate, n_req, fifo=False):
+        reqs = synth.requests(n_req, rate if rate else 1e9)
+        kw = dict(max_inflight=1, batch_max_n=-1) if fifo else dict(max_inflight=64, n_streams=4)
+        sv = apsp.Server(**kw)
+        tickets = []
+        done = threading.Event()
+        errors = []
+
+        def drain():
+            i = 0
+            while True:
+                while i >= len(tickets):
+                    if done.is_set():
+                        return
+                    time.sleep(0.0002)
+                st = sv.wait(tickets[i])
+                if st != apsp.SUCCESS:
+                    errors.append(st)
+                sv.release(tickets[i])
+                i += 1
+
+        th = threading.Thread(target=drain)
+        th.start()
+        t0 = time.perf_counter()
+        for r in reqs:
+            if rate:
+                now = time.perf_counter() - t0
+                if r.arrival_s > now:
+                    time.sleep(r.arrival_s - now)
+            # a request's graph is the leading n x n block of a pinned base matrix
+            # (a principal submatrix of a p=0.2 random graph is one too)
+            tickets.append(sv.submit(base[r.dtype], n=r.n, want_pred=r.want_pred, borrow=True))
+        done.set()
+        th.join()
+        s = sv.stats()
+        sv.destroy()
+        if errors:
+            raise RuntimeError(f"serving requests failed: {errors[:5]}")
+        return {"offered_rate": round(rate, 1) if rate else "saturated", "requests": n_req,
+                "solves_per_s": round(s["solves_per_s"], 1), "p50_ms": round(s["p50_latency_ms"], 3),
+                "p99_ms": round(s["p99_latency_ms"], 3)}
+
+    sat = run(None, count)
+    out = {"workload": "Poisson stream, n=round(exp U[ln32,ln8192]), int32/float32 integer weights "
+                       "[1,1000] half each, p=0.2, predecessors for 30%",
+           "continuous_batching": [sat], "fifo_one_at_a_time": [run(None, max(100, count // 2), fifo=True)]}
+    for f in (0.5, 0.9):
+        out["continuous_batching"].append(run(f * sat["solves_per_s"], count))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +190,10 @@ def main():
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--batched-replays", type=int, default=10)
+    ap.add_argument("--serving-requests", type=int, default=400)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -139,13 +261,24 @@ def main():
     phases = {k: {"launches": v["launches"], "ms_per_step": round(v["total_ms"] / args.steps, 3)}
               for k, v in prof.items() if v["launches"]}
 
+    del work, pristine
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.skip_batched:
+        log("[bench] batched leg")
+        batched = batched_leg(args.batched_replays)
+    serving = None
+    if not args.skip_serving:
+        log("[bench] serving leg")
+        serving = serving_leg(args.serving_requests)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s budget)")
         cpu = cpu_baseline(W, args.cpu_seconds)
 
     out = {
-        "metric": "min-plus GOPS (2n^3/t) vs VALU peak at n=32768",
+        "metric": "min-plus GOPS (2n^3/t) vs VALU peak at n=32768; batched solves/s + p99 latency",
         "value": round(gops, 2),
         "unit": "GOPS",
         "n_gpus": 1,
@@ -168,6 +301,8 @@ def main():
         "roofline": roofline,
         "phases": phases,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     del np
