@@ -121,7 +121,9 @@ typedef struct {
     int32_t block_size;    /* 0 = automatic; else 64, 128 or 256 (256: distances only) */
     int32_t use_graph;     /* nonzero: capture the round sequence once per shape into a
                               hipGraph and replay it (fewer launches for small n) */
-    int32_t reserved;
+    int32_t schedule;      /* 0 = automatic: for n >= 4096, phase 3 of round r is split so that
+                              phases 1-2 of round r+1 run beside most of it on a library-owned
+                              second stream; 1 = one stream, rounds in order */
     int32_t *d_status;     /* device int32 or NULL: receives APSP_SUCCESS,
                               APSP_ERROR_INVALID_VALUE or APSP_ERROR_NEGATIVE_CYCLE */
 } apsp_options_t;
@@ -147,14 +149,23 @@ typedef struct {
 } apsp_kernel_time_t;
 
 typedef struct {
-    apsp_kernel_time_t phase1; /* diagonal block closure */
-    apsp_kernel_time_t phase2; /* block row / block column products */
-    apsp_kernel_time_t phase3; /* remaining-block products */
-    apsp_kernel_time_t other;  /* set-up and wrap-up passes */
+    apsp_kernel_time_t phase1;       /* diagonal block closure */
+    apsp_kernel_time_t phase2;       /* block row / block column products */
+    apsp_kernel_time_t phase3;       /* remaining-block products (all, or all but the next
+                                        round's block row/column under the two-stream schedule) */
+    apsp_kernel_time_t other;        /* set-up and wrap-up passes */
+    apsp_kernel_time_t phase3_cross; /* two-stream schedule: the next round's block row/column */
 } apsp_profile_t;
 
 apsp_status_t apsp_profile_begin(void);
 apsp_status_t apsp_profile_end(apsp_profile_t *out);
+
+/* Measures the device's 32-bit VALU throughput (lane-instructions per
+ * second) with the instruction mix of the min-plus kernels (clamp-saturating
+ * add, three-input minimum), every CU busy; synchronises the device.  The
+ * benchmark reports kernel rates against this measured peak beside the
+ * datasheet one (256 CUs x 64 lanes x 2.4 GHz). */
+apsp_status_t apsp_probe_valu(double *lane_instr_per_s, double *elapsed_ms);
 
 /* Release the calling device's internal workspace and cached graphs.
  * Must not overlap with solves in flight on that device. */

@@ -43,7 +43,7 @@ class KernelTime(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("phase1", KernelTime), ("phase2", KernelTime), ("phase3", KernelTime),
-                ("other", KernelTime)]
+                ("other", KernelTime), ("phase3_cross", KernelTime)]
 
     def as_dict(self):
         out = {}
@@ -56,7 +56,7 @@ class Profile(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("d_status", ctypes.c_void_p)]
 
 
@@ -112,6 +112,7 @@ def _bind_optional(L):
         "apsp_server_release": ([vp, u64], c_int),
         "apsp_server_stats": ([vp, vp], c_int),
         "apsp_server_destroy": ([vp], c_int),
+        "apsp_probe_valu": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], c_int),
     }
     for name, (args, res) in table.items():
         f = getattr(L, name, None)
@@ -145,7 +146,7 @@ def _dtype_code(t):
 
 
 def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, status=None,
-          stream=None, check=True) -> int:
+          stream=None, check=True, schedule=0) -> int:
     """Solve APSP in place on a square device tensor.
 
     dist   : torch.Tensor [n, n] int32/float32 on the GPU, contiguous (weights in,
@@ -164,7 +165,7 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
         assert pred.dtype == torch.int32 and pred.is_cuda and pred.is_contiguous()
         assert tuple(pred.shape) == (n, n)
         pp = pred.data_ptr()
-    opt = Options(int(validate), int(block_size), int(use_graph), 0,
+    opt = Options(int(validate), int(block_size), int(use_graph), int(schedule),
                   status.data_ptr() if status is not None else None)
     st = lib().apsp_solve_ex(dist.data_ptr(), pp, n, _dtype_code(dist), _stream_ptr(stream),
                              ctypes.byref(opt))
@@ -192,6 +193,16 @@ def profile_end() -> dict:
     if st != SUCCESS:
         raise APSPError(st, "apsp_profile_end")
     return prof.as_dict()
+
+
+def probe_valu() -> dict:
+    """Measured 32-bit VALU lane-instructions per second (synchronises the device)."""
+    r = ctypes.c_double()
+    ms = ctypes.c_double()
+    st = lib().apsp_probe_valu(ctypes.byref(r), ctypes.byref(ms))
+    if st != SUCCESS:
+        raise APSPError(st, "apsp_probe_valu")
+    return {"lane_instr_per_s": r.value, "elapsed_ms": ms.value}
 
 
 def release_workspace() -> None:

@@ -167,6 +167,141 @@ __device__ __forceinline__ void st16(T *p, const T *in) {
     *reinterpret_cast<int4 *>(p) = v;
 }
 
+// ---------------------------------------------------------------------------
+// The same workgroup tile update for 4-byte elements, with the A and B
+// chunks copied from global memory straight into LDS by gfx950's
+// global_load_lds_dwordx4 (each lane's 16 bytes land at LDS base + 16 *
+// lane): no staging registers and no LDS store instructions, which frees
+// the registers for three workgroups per CU.  The two chunk buffers are
+// distinct LDS arrays and the chunk loop is unrolled by two, so the
+// compiler can see that the copy into one buffer never aliases the reads of
+// the other and keeps the copy in flight across the computation.
+//
+// A chunks are stored packed (KC elements per row); the 16-byte pieces of
+// row r are XOR-swizzled by ((r >> 1) & 1) so the four rows a wavefront
+// reads at one k fall into distinct LDS bank groups.
+// ---------------------------------------------------------------------------
+template <class Ar, int MT, int NT, int KC, int TM, int TN>
+struct TileProductDMA {
+    using T = typename Ar::T;
+    static_assert(sizeof(T) == 4, "16-byte pieces of 4-byte elements");
+    static constexpr int VW = 4;
+    static constexpr int TX = NT / TN;
+    static constexpr int TY = MT / TM;
+    static constexpr int NTH = TX * TY;
+    static constexpr int NWAVES = NTH / 64;
+    static constexpr int GN = TN / VW;
+    static constexpr int GSTRIDE = NT / GN;
+    static constexpr int KP = KC / VW;               // 16-byte pieces per A row
+    static constexpr int IA = MT * KC / VW / 64;     // wave copies per A chunk
+    static constexpr int IB = KC * NT / VW / 64;     // wave copies per B chunk
+    static_assert(GSTRIDE == TX * VW && KP >= 2, "tile shape");
+    static_assert(IA % NWAVES == 0 && IB % NWAVES == 0, "copies split evenly over wavefronts");
+
+    struct Smem {
+        T a0[MT * KC];
+        T a1[MT * KC];
+        T b0[KC * NT];
+        T b1[KC * NT];
+    };
+
+    __device__ __forceinline__ static int swz(int row) { return (row >> 1) & 1; }
+
+    __device__ __forceinline__ static void copy_chunk(T *__restrict__ la, T *__restrict__ lb,
+                                                      const T *__restrict__ Abase,
+                                                      const T *__restrict__ Bbase, uint32_t ld) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int j = 0; j < IA / NWAVES; ++j) {
+            const int i = wave * (IA / NWAVES) + j;
+            const int v = i * 64 + lane;
+            const int row = v / KP, piece = v % KP;
+            const T *g = Abase + ((uint32_t)row * ld + (uint32_t)((piece ^ swz(row)) * VW));
+            __builtin_amdgcn_global_load_lds((const void *)g,
+                                             (__attribute__((address_space(3))) void *)(la + i * 64 * VW),
+                                             16, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < IB / NWAVES; ++j) {
+            const int i = wave * (IB / NWAVES) + j;
+            const int v = i * 64 + lane;
+            const int row = v / (NT / VW), cv = v % (NT / VW);
+            const T *g = Bbase + ((uint32_t)row * ld + (uint32_t)(cv * VW));
+            __builtin_amdgcn_global_load_lds((const void *)g,
+                                             (__attribute__((address_space(3))) void *)(lb + i * 64 * VW),
+                                             16, 0, 0);
+        }
+    }
+
+    // wait for this wavefront's copies (vmcnt 0), then for everyone's
+    __device__ __forceinline__ static void copies_done() {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ static void compute(T (&c)[TM][TN], const T *__restrict__ As,
+                                                   const T *__restrict__ Bs, int tx, int ty,
+                                                   const Ar &ar) {
+#pragma unroll 1
+        for (int kg = 0; kg < KC; kg += VW) {
+            T a[TM][VW];
+#pragma unroll
+            for (int m = 0; m < TM; ++m) {
+                const int row = ty + TY * m;
+                ld16(&As[row * KC + (((kg / VW) ^ swz(row)) * VW)], a[m]);
+            }
+#pragma unroll
+            for (int kk = 0; kk < VW; kk += 2) {
+                T b0[TN], b1[TN];
+#pragma unroll
+                for (int g = 0; g < GN; ++g) {
+                    ld16(&Bs[(kg + kk) * NT + g * GSTRIDE + tx * VW], &b0[g * VW]);
+                    ld16(&Bs[(kg + kk + 1) * NT + g * GSTRIDE + tx * VW], &b1[g * VW]);
+                }
+#pragma unroll
+                for (int m = 0; m < TM; ++m)
+#pragma unroll
+                    for (int n = 0; n < TN; ++n)
+                        c[m][n] = ar.relax2(c[m][n], a[m][kk], b0[n], a[m][kk + 1], b1[n]);
+            }
+        }
+    }
+
+    __device__ __forceinline__ static void run(Smem &sm, T *__restrict__ D, int64_t ld64, int64_t crow,
+                                               int64_t ccol, int64_t k0, int kcount, const Ar &ar) {
+        const int tid = threadIdx.x;
+        const int tx = tid % TX, ty = tid / TX;
+        const uint32_t ld = (uint32_t)ld64;
+        T *const Cbase = D + crow * ld64 + ccol;
+        const T *const Abase = D + crow * ld64 + k0;
+        const T *const Bbase = D + k0 * ld64 + ccol;
+        const uint32_t coff = (uint32_t)ty * ld + (uint32_t)tx * VW;
+        T c[TM][TN];
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+#pragma unroll
+            for (int g = 0; g < GN; ++g)
+                ld16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
+        const int nch = kcount / KC;  // even: kcount is a multiple of 2 KC
+        copy_chunk(sm.a0, sm.b0, Abase, Bbase, ld);
+        copies_done();
+        for (int ch = 0; ch < nch; ch += 2) {
+            copy_chunk(sm.a1, sm.b1, Abase + (ch + 1) * KC, Bbase + (uint32_t)((ch + 1) * KC) * ld, ld);
+            compute(c, sm.a0, sm.b0, tx, ty, ar);
+            copies_done();
+            if (ch + 2 < nch)
+                copy_chunk(sm.a0, sm.b0, Abase + (ch + 2) * KC, Bbase + (uint32_t)((ch + 2) * KC) * ld, ld);
+            compute(c, sm.a1, sm.b1, tx, ty, ar);
+            copies_done();
+        }
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+#pragma unroll
+            for (int g = 0; g < GN; ++g)
+                st16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
+    }
+};
+
 // Barrier between the LDS writes and reads of a tile step.  Workgroup mode:
 // s_barrier.  Wavefront mode (one wavefront owns the tile): a wavefront's LDS
 // operations execute in issue order, so only the compiler must be kept from
@@ -207,6 +342,10 @@ __device__ __forceinline__ int tile_tid() {
 // the workgroup owns every C element that its reads could see (the panel
 // updates use a tile that spans the whole k-block in that direction).
 // ---------------------------------------------------------------------------
+#ifndef KG_UNROLL
+#define KG_UNROLL 1
+#endif
+
 template <class Ar, int MT, int NT, int KC, int TM, int TN, bool WAVE = false>
 struct TileProduct {
     using T = typename Ar::T;
@@ -305,7 +444,7 @@ struct TileProduct {
             if (more) load_chunk(Abase + (ch + 1) * KC, Bbase + (uint32_t)((ch + 1) * KC) * ld, ld, ra, rb);
             const T *As = sm.a[buf];
             const T *Bs = sm.b[buf];
-#pragma unroll 2
+#pragma unroll KG_UNROLL
             for (int kg = 0; kg < KC; kg += VW) {
                 T a[TM][VW];
 #pragma unroll

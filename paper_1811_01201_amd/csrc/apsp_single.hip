@@ -18,6 +18,16 @@
 
 #include "apsp_internal.h"
 
+#ifndef P3_WAVES
+#define P3_WAVES 3
+#endif
+#ifndef P3_KC
+#define P3_KC 16
+#endif
+#ifndef P3_DMA
+#define P3_DMA 1
+#endif
+
 namespace apsp {
 
 template <class Ar, class Alt, int BS>
@@ -109,40 +119,82 @@ phase2_kernel(void *X, int64_t ld, int64_t r0, int nt, Ar ar, Alt alt,
 // workgroup w on XCD w mod 8) walks its own contiguous stretch of a grouped
 // tile order: GROUP tile rows at a time, all columns, so the panel slices
 // that the XCD's resident workgroups read stay in that XCD's L2.
-template <int BS, int MT>
-__device__ __forceinline__ bool phase3_tile(int64_t r0, int ntr, int per_xcd, int64_t &crow,
-                                            int64_t &ccol) {
+// Tile sets of phase 3 (tile = MT x MT, pb = BS / MT tiles per block):
+//   kAll    every tile outside block row r and block column r
+//   kRest   every tile outside block rows/columns r and r + 1
+//   kCross  the tiles of block row r + 1 and block column r + 1 outside
+//           block row/column r (the next round's diagonal and panels)
+// kRest + kCross = kAll.  The two-stream schedule runs kCross on the
+// critical path and kRest beside the next round's phases 1 and 2.
+enum P3Set { kAll = 0, kRest = 1, kCross = 2 };
+
+__host__ __device__ inline int64_t p3_count(int set, int nt, int pb) {
+    if (set == kAll) return (int64_t)(nt - pb) * (nt - pb);
+    if (set == kRest) return (int64_t)(nt - 2 * pb) * (nt - 2 * pb);
+    return (int64_t)pb * (nt - pb) + (int64_t)(nt - 2 * pb) * pb;
+}
+
+// Maps workgroup blockIdx.x to a tile; false if it has none.  kAll/kRest
+// walk a grouped order (GROUP tile rows at a time, all columns), each of the
+// 8 XCDs (a dispatch places workgroup w on XCD w mod 8) taking its own
+// contiguous stretch so the panel slices its resident workgroups read stay
+// in that XCD's L2.
+__device__ __forceinline__ bool phase3_tile(int set, int r, int nt, int pb, int per_xcd, int MT,
+                                            int64_t &crow, int64_t &ccol) {
     constexpr int GROUP = 8;
     const int w = blockIdx.x;
     const int seq = (w & 7) * per_xcd + (w >> 3);
-    const int total = ntr * ntr;
+    const int total = (int)p3_count(set, nt, pb);
     if (seq >= total) return false;
-    const int group = seq / (GROUP * ntr);
-    const int first = group * GROUP;
-    const int rows = min(GROUP, ntr - first);
-    const int within = seq - group * GROUP * ntr;
-    int ti = first + within % rows;
-    int tj = within / rows;
-    const int per_block = BS / MT;
-    const int rb = (int)(r0 / MT);
-    ti += (ti >= rb) ? per_block : 0;
-    tj += (tj >= rb) ? per_block : 0;
+    const int e1 = r * pb;  // first tile index of block r
+    int ti, tj;
+    if (set == kCross) {
+        const int nrow = pb * (nt - pb);
+        if (seq < nrow) {  // rows of block r + 1, columns outside block r
+            ti = (r + 1) * pb + seq / (nt - pb);
+            tj = seq % (nt - pb);
+            tj += (tj >= e1) ? pb : 0;
+        } else {           // columns of block r + 1, rows outside blocks r, r + 1
+            const int q = seq - nrow;
+            ti = q / pb;
+            tj = (r + 1) * pb + q % pb;
+            ti += (ti >= e1) ? 2 * pb : 0;
+        }
+    } else {
+        const int skip = (set == kAll) ? pb : 2 * pb;  // excluded tiles start at e1
+        const int ntr = nt - skip;
+        const int group = seq / (GROUP * ntr);
+        const int first = group * GROUP;
+        const int rows = min(GROUP, ntr - first);
+        const int within = seq - group * GROUP * ntr;
+        ti = first + within % rows;
+        tj = within / rows;
+        ti += (ti >= e1) ? skip : 0;
+        tj += (tj >= e1) ? skip : 0;
+    }
     crow = (int64_t)ti * MT;
     ccol = (int64_t)tj * MT;
     return true;
 }
 
-template <class Ar, class Alt, int BS, int MT>
+template <class Ar, class Alt, int BS, int MT, int SET>
 __global__ void __launch_bounds__((MT / 8) * (MT / 8))
-__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? 2 : 1)))
-phase3_kernel(void *X, int64_t ld, int64_t r0, int ntr, int per_xcd, Ar ar, Alt alt,
+__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? P3_WAVES : 1)))
+phase3_kernel(void *X, int64_t ld, int r, int per_xcd, Ar ar, Alt alt,
               const int32_t *__restrict__ mode, const int32_t *__restrict__ skip) {
-    using TP = TileProduct<Ar, MT, MT, 16, 8, 8>;
+    constexpr int set = SET;
+#if P3_DMA
+    using TP = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, MT, MT, P3_KC, 8, 8>,
+                                  TileProduct<Ar, MT, MT, 16, 8, 8>>;
+#else
+    using TP = TileProduct<Ar, MT, MT, (sizeof(typename Ar::T) == 4 ? P3_KC : 16), 8, 8>;
+#endif
     if (skip && *skip != APSP_SUCCESS) return;
     int64_t crow, ccol;
-    if (!phase3_tile<BS, MT>(r0, ntr, per_xcd, crow, ccol)) return;
+    if (!phase3_tile(set, r, (int)(ld / MT), BS / MT, per_xcd, MT, crow, ccol)) return;
+    const int64_t r0 = (int64_t)r * BS;
     if constexpr (!std::is_same_v<Alt, NoAlt>) {
-        using TQ = TileProduct<Alt, MT, MT, 16, 8, 8>;
+        using TQ = TileProduct<Alt, MT, MT, (sizeof(typename Alt::T) == 4 ? P3_KC : 16), 8, 8>;
         __shared__ union {
             typename TP::Smem a;
             typename TQ::Smem b;
@@ -368,7 +420,7 @@ apsp_status_t cached_workspace(int dev, hipStream_t s, size_t bytes, void **out)
 }
 
 // Optional per-launch timing (apsp_profile_begin / _end).
-enum KernelKind { kPhase1 = 0, kPhase2 = 1, kPhase3 = 2, kOther = 3 };
+enum KernelKind { kPhase1 = 0, kPhase2 = 1, kPhase3 = 2, kOther = 3, kPhase3Cross = 4 };
 struct ProfRecord {
     int kind;
     double updates;
@@ -415,50 +467,119 @@ int pred_bits(int64_t ld) {
     return S;
 }
 
+// Auxiliary stream per (device, caller stream) for the two-stream schedule,
+// with the two events it uses.
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t panels = nullptr;  // caller stream: phase 2 of the current round done
+    hipEvent_t rest = nullptr;    // aux stream: kRest tiles of the previous round done
+};
+std::mutex g_aux_mu;
+std::map<std::pair<int, hipStream_t>, AuxStream> g_aux;
+
+apsp_status_t aux_stream(int dev, hipStream_t s, AuxStream **out) {
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    AuxStream &a = g_aux[{dev, s}];
+    if (!a.s) {
+        APSP_HIP(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
+        APSP_HIP(hipEventCreateWithFlags(&a.panels, hipEventDisableTiming));
+        APSP_HIP(hipEventCreateWithFlags(&a.rest, hipEventDisableTiming));
+    }
+    *out = &a;
+    return APSP_SUCCESS;
+}
+
 // The round loop on a work matrix of size ld (a multiple of BS).
+//
+// One stream, in order: for each round r, phase 1, phase 2, phase 3.
+// Two streams (lookahead, from three rounds on): phase 3 of round r is
+// split into the tiles the next round's phases 1-2 read (kCross, on the
+// caller's stream, the critical path) and all others (kRest, on an
+// auxiliary stream), so phases 1 and 2 of round r+1 run beside the bulk of
+// phase 3 of round r:
+//   caller: P1(0) P2(0) [panels] | wait(rest) P3x(r) P1(r+1) P2(r+1) [panels] | ...
+//   aux:    wait(panels) P3r(r) [rest] | ...
+// kCross(r+1) touches tiles last written by kRest(r), hence its wait.
 template <class Ar, class Alt, int BS>
 apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, const int32_t *mode,
-                         hipStream_t s, const int32_t *skip) {
+                         hipStream_t s, const int32_t *skip, bool lookahead) {
     constexpr int MT = BS >= 128 ? 128 : 64;
     constexpr int P2W = 64;
     const int R = (int)(ld / BS);
     const int nt2 = (int)((ld - BS) / P2W);
-    const int ntr = (int)((ld - BS) / MT);
-    const int64_t tiles3 = (int64_t)ntr * ntr;
-    const int per_xcd = (int)((tiles3 + 7) / 8);
+    const int nt = (int)(ld / MT), pb = BS / MT;
     const double bs3 = (double)BS * BS * BS;
-    for (int r = 0; r < R; ++r) {
-        const int64_t r0 = (int64_t)r * BS;
-        {
-            ProfScope ps(kPhase1, bs3, s);
-            hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS>), dim3(1), dim3(P1Shape<BS>::NTH), 0, s, X,
-                               ld, r0, ar, alt, mode, skip);
+    int dev = 0;
+    APSP_HIP(hipGetDevice(&dev));
+    AuxStream *aux = nullptr;
+    // the split pays off once phase 3 is throughput- rather than latency-bound
+    if (lookahead && R >= 3 && ld >= 4096) {
+        apsp_status_t st = aux_stream(dev, s, &aux);
+        if (st != APSP_SUCCESS) return st;
+    }
+    auto p1 = [&](int r) {
+        ProfScope ps(kPhase1, bs3, s);
+        hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS>), dim3(1), dim3(P1Shape<BS>::NTH), 0, s, X, ld,
+                           (int64_t)r * BS, ar, alt, mode, skip);
+    };
+    auto p2 = [&](int r) {
+        if (nt2 <= 0) return;
+        ProfScope ps(kPhase2, 2.0 * bs3 * (ld / BS - 1), s);
+        hipLaunchKernelGGL((phase2_kernel<Ar, Alt, BS, P2W>), dim3(2 * nt2), dim3((BS / 8) * (P2W / 8)),
+                           0, s, X, ld, (int64_t)r * BS, nt2, ar, alt, mode, skip);
+    };
+    auto p3 = [&](int r, int set, hipStream_t st) {
+        const int64_t tiles = p3_count(set, nt, pb);
+        if (tiles <= 0) return;
+        const int per_xcd = (int)((tiles + 7) / 8);
+        ProfScope ps(set == kCross ? kPhase3Cross : kPhase3, (double)tiles * MT * MT * BS, st);
+        const dim3 grid(8 * per_xcd), block((MT / 8) * (MT / 8));
+        if (set == kAll)
+            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kAll>), grid, block, 0, st, X, ld, r, per_xcd,
+                               ar, alt, mode, skip);
+        else if (set == kRest)
+            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kRest>), grid, block, 0, st, X, ld, r,
+                               per_xcd, ar, alt, mode, skip);
+        else
+            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kCross>), grid, block, 0, st, X, ld, r,
+                               per_xcd, ar, alt, mode, skip);
+    };
+    if (!aux) {
+        for (int r = 0; r < R; ++r) {
+            p1(r);
+            p2(r);
+            p3(r, kAll, s);
         }
-        if (nt2 > 0) {
-            ProfScope ps(kPhase2, 2.0 * bs3 * (ld / BS - 1), s);
-            hipLaunchKernelGGL((phase2_kernel<Ar, Alt, BS, P2W>), dim3(2 * nt2),
-                               dim3((BS / 8) * (P2W / 8)), 0, s, X, ld, r0, nt2, ar, alt, mode, skip);
+    } else {
+        p1(0);
+        p2(0);
+        APSP_HIP(hipEventRecord(aux->panels, s));
+        for (int r = 0; r + 1 < R; ++r) {
+            APSP_HIP(hipStreamWaitEvent(aux->s, aux->panels, 0));
+            p3(r, kRest, aux->s);
+            if (r > 0) APSP_HIP(hipStreamWaitEvent(s, aux->rest, 0));
+            APSP_HIP(hipEventRecord(aux->rest, aux->s));
+            p3(r, kCross, s);
+            p1(r + 1);
+            p2(r + 1);
+            APSP_HIP(hipEventRecord(aux->panels, s));
         }
-        if (tiles3 > 0) {
-            ProfScope ps(kPhase3, (double)(ld - BS) * (ld - BS) * BS, s);
-            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT>), dim3(8 * per_xcd),
-                               dim3((MT / 8) * (MT / 8)), 0, s, X, ld, r0, ntr, per_xcd, ar, alt, mode,
-                               skip);
-        }
+        APSP_HIP(hipStreamWaitEvent(s, aux->rest, 0));
+        p3(R - 1, kAll, s);
     }
     APSP_HIP(hipGetLastError());
     return APSP_SUCCESS;
 }
 
 template <class Ar, class Alt = NoAlt>
-apsp_status_t run_rounds_bs(int bs, void *X, int64_t ld, const Ar &ar, hipStream_t s,
+apsp_status_t run_rounds_bs(int bs, bool lookahead, void *X, int64_t ld, const Ar &ar, hipStream_t s,
                             const int32_t *skip, const Alt &alt = Alt{}, const int32_t *mode = nullptr) {
     switch (bs) {
-        case 64: return run_rounds<Ar, Alt, 64>(X, ld, ar, alt, mode, s, skip);
-        case 128: return run_rounds<Ar, Alt, 128>(X, ld, ar, alt, mode, s, skip);
+        case 64: return run_rounds<Ar, Alt, 64>(X, ld, ar, alt, mode, s, skip, lookahead);
+        case 128: return run_rounds<Ar, Alt, 128>(X, ld, ar, alt, mode, s, skip, lookahead);
         case 256:
             if constexpr (sizeof(typename Ar::T) == 4)
-                return run_rounds<Ar, Alt, 256>(X, ld, ar, alt, mode, s, skip);
+                return run_rounds<Ar, Alt, 256>(X, ld, ar, alt, mode, s, skip, lookahead);
             return APSP_ERROR_INVALID_ARGUMENT;
         default: return APSP_ERROR_INVALID_ARGUMENT;
     }
@@ -485,6 +606,7 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
     APSP_HIP(hipGetDevice(&dev));
     const bool with_pred = pred != nullptr;
     const int bs = opt.block_size ? opt.block_size : auto_block(n, with_pred);
+    const bool lookahead = opt.schedule != 1;
     // caller-provided work memory (the server) or the per-stream cache
     auto workspace = [&](int d, hipStream_t st, size_t bytes, void **out) -> apsp_status_t {
         if (ext_ws) {
@@ -518,9 +640,9 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         }
         apsp_status_t st;
         if constexpr (std::is_same_v<T, int32_t>)
-            st = run_rounds_bs<ArI32>(bs, X, ld, ArI32{}, s, skip);
+            st = run_rounds_bs<ArI32>(bs, lookahead, X, ld, ArI32{}, s, skip);
         else
-            st = run_rounds_bs<ArF32>(bs, X, ld, ArF32{}, s, skip);
+            st = run_rounds_bs<ArF32>(bs, lookahead, X, ld, ArF32{}, s, skip);
         if (st != APSP_SUCCESS) return st;
         hipLaunchKernelGGL((finalize_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, X, ld, dist, n,
                            status, skip);
@@ -541,9 +663,9 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         hipLaunchKernelGGL((pred_pack_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n, w,
                            ld, ar.S, mode, skip);
         if constexpr (std::is_same_v<T, float>)
-            st = run_rounds_bs<ArKey, ArLexF32>(bs, w, ld, ar, s, skip, ArLexF32{}, mode);
+            st = run_rounds_bs<ArKey, ArLexF32>(bs, lookahead, w, ld, ar, s, skip, ArLexF32{}, mode);
         else
-            st = run_rounds_bs<ArKey>(bs, w, ld, ar, s, skip);
+            st = run_rounds_bs<ArKey>(bs, lookahead, w, ld, ar, s, skip);
         if (st != APSP_SUCCESS) return st;
         hipLaunchKernelGGL((pred_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, w, ld, dist,
                            pred, n, ar.S, mode, status, skip);
@@ -634,7 +756,8 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out) {
         recs.swap(g_prof);
     }
     *out = apsp_profile_t{};
-    apsp_kernel_time_t *slot[4] = {&out->phase1, &out->phase2, &out->phase3, &out->other};
+    apsp_kernel_time_t *slot[5] = {&out->phase1, &out->phase2, &out->phase3, &out->other,
+                                   &out->phase3_cross};
     apsp_status_t st = APSP_SUCCESS;
     for (auto &r : recs) {
         float ms = 0.f;

@@ -205,3 +205,40 @@ def test_real_valued_float32_pred_chains(orc):
     for i in range(0, n, 23):
         for j in range(n):
             assert pins.walk_pred_chain(W, D, P, i, j, tol=1e-5), (i, j)
+
+
+@pytest.mark.parametrize("n,bs,kind,pred", [(700, 64, "pot", False), (1000, 128, "int", True),
+                                            (1536, 256, "f32", False), (1300, 128, "sparse", False),
+                                            (900, 64, "f32", True)])
+def test_lookahead_schedule_matches_in_order(orc, n, bs, kind, pred):
+    """Two-stream lookahead (default) == one stream in round order == oracle."""
+    describe(f"single schedules n={n} bs={bs} {kind} pred={pred}")
+    W = _graph(kind, n, seed=n + bs)
+    D0, P0, _ = oracle_expect(orc, W, pred)
+    Da, Pa, sa = gpu_solve(W, pred, block_size=bs)
+    Db, Pb, sb = gpu_solve(W, pred, block_size=bs, schedule=1)
+    assert sa == 0 and sb == 0
+    assert first_mismatch(Da, D0) is None and first_mismatch(Db, D0) is None
+    if pred:
+        assert first_mismatch(Pa, P0) is None and first_mismatch(Pb, P0) is None
+
+
+def test_concurrent_solves_on_streams(orc):
+    """Solves enqueued on different streams at once (each with its own
+    auxiliary stream and work memory) all match the oracle."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe("single concurrent streams")
+    graphs = [_graph(k, n, seed=5 + n) for k, n in [("int", 900), ("pot", 777), ("f32", 1030), ("int", 513)]]
+    streams = [torch.cuda.Stream() for _ in graphs]
+    dev = [torch.from_numpy(W).cuda() for W in graphs]
+    preds = [torch.empty(W.shape, dtype=torch.int32, device="cuda") for W in graphs]
+    torch.cuda.synchronize()
+    for d, p, s in zip(dev, preds, streams):
+        apsp.solve(d, p, stream=s)
+    torch.cuda.synchronize()
+    for W, d, p in zip(graphs, dev, preds):
+        D0, P0, _ = oracle_expect(orc, W, True)
+        assert first_mismatch(d.cpu().numpy(), D0) is None
+        assert first_mismatch(p.cpu().numpy(), P0) is None
