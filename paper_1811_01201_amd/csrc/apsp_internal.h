@@ -70,6 +70,7 @@ void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, 
 struct ArI32 {
     using T = int32_t;
     static constexpr int VW = 4;
+    static constexpr bool kStrip = false;  // strip() is the identity
     // clamp-saturating add: never wraps, even with negative cycles
     __device__ __forceinline__ T add(T a, T b) const { return __builtin_elementwise_add_sat(a, b); }
     __device__ __forceinline__ T mn(T a, T b) const { return a < b ? a : b; }
@@ -91,6 +92,7 @@ struct ArI32 {
 struct ArF32 {
     using T = float;
     static constexpr int VW = 4;
+    static constexpr bool kStrip = false;
     __device__ __forceinline__ T add(T a, T b) const { return a + b; }
     __device__ __forceinline__ T mn(T a, T b) const { return __builtin_fminf(a, b); }
     __device__ __forceinline__ T strip(T a) const { return a; }
@@ -110,6 +112,7 @@ struct ArF32 {
 struct ArKey {
     using T = double;
     static constexpr int VW = 2;
+    static constexpr bool kStrip = true;
     int S;  // predecessor bits
     __device__ __forceinline__ T add(T a, T b) const { return a + b; }
     __device__ __forceinline__ T mn(T a, T b) const { return __builtin_fmin(a, b); }
@@ -138,6 +141,7 @@ constexpr int32_t kLexNone = 0x7fffffff;
 struct ArLexF32 {
     using T = DistPred;
     static constexpr int VW = 2;
+    static constexpr bool kStrip = false;
     __device__ __forceinline__ T add(T a, T b) const { return T{a.d + b.d, b.p}; }
     __device__ __forceinline__ T mn(T c, T s) const {
         const bool take = (s.d < c.d) | ((s.d == c.d) & (s.p < c.p));
@@ -178,14 +182,15 @@ __device__ __forceinline__ void st16(T *p, const T *in) {
 // the other and keeps the copy in flight across the computation.
 //
 // A chunks are stored packed (KC elements per row); the 16-byte pieces of
-// row r are XOR-swizzled by ((r >> 1) & 1) so the four rows a wavefront
-// reads at one k fall into distinct LDS bank groups.
+// row r are XOR-swizzled by ((r * KP) >> 3) & (KP - 1) (KP = pieces per
+// row) so the four rows a wavefront reads at one k fall into distinct LDS
+// bank groups (8 groups of 16 bytes).
 // ---------------------------------------------------------------------------
 template <class Ar, int MT, int NT, int KC, int TM, int TN>
 struct TileProductDMA {
     using T = typename Ar::T;
-    static_assert(sizeof(T) == 4, "16-byte pieces of 4-byte elements");
-    static constexpr int VW = 4;
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "16-byte pieces of 4- or 8-byte elements");
+    static constexpr int VW = 16 / (int)sizeof(T);
     static constexpr int TX = NT / TN;
     static constexpr int TY = MT / TM;
     static constexpr int NTH = TX * TY;
@@ -195,7 +200,7 @@ struct TileProductDMA {
     static constexpr int KP = KC / VW;               // 16-byte pieces per A row
     static constexpr int IA = MT * KC / VW / 64;     // wave copies per A chunk
     static constexpr int IB = KC * NT / VW / 64;     // wave copies per B chunk
-    static_assert(GSTRIDE == TX * VW && KP >= 2, "tile shape");
+    static_assert(GSTRIDE == TX * VW && KP >= 2 && (KP & (KP - 1)) == 0, "tile shape");
     static_assert(IA % NWAVES == 0 && IB % NWAVES == 0, "copies split evenly over wavefronts");
 
     struct Smem {
@@ -205,7 +210,7 @@ struct TileProductDMA {
         T b1[KC * NT];
     };
 
-    __device__ __forceinline__ static int swz(int row) { return (row >> 1) & 1; }
+    __device__ __forceinline__ static int swz(int row) { return ((row * KP) >> 3) & (KP - 1); }
 
     __device__ __forceinline__ static void copy_chunk(T *__restrict__ la, T *__restrict__ lb,
                                                       const T *__restrict__ Abase,
@@ -233,10 +238,17 @@ struct TileProductDMA {
         }
     }
 
-    // wait for this wavefront's copies (vmcnt 0), then for everyone's
-    __device__ __forceinline__ static void copies_done() {
+    // wait for this wavefront's copies (vmcnt 0), then for everyone's; in
+    // key mode the A chunk (left operands) then has its predecessor bits
+    // stripped in place, which the copy itself cannot do
+    __device__ __forceinline__ static void copies_done(T *__restrict__ la, const Ar &ar) {
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
         __syncthreads();
+        if constexpr (Ar::kStrip) {
+#pragma unroll
+            for (int e = threadIdx.x; e < MT * KC; e += NTH) la[e] = ar.strip(la[e]);
+            __syncthreads();
+        }
     }
 
     __device__ __forceinline__ static void compute(T (&c)[TM][TN], const T *__restrict__ As,
@@ -284,15 +296,15 @@ struct TileProductDMA {
                 ld16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
         const int nch = kcount / KC;  // even: kcount is a multiple of 2 KC
         copy_chunk(sm.a0, sm.b0, Abase, Bbase, ld);
-        copies_done();
+        copies_done(sm.a0, ar);
         for (int ch = 0; ch < nch; ch += 2) {
             copy_chunk(sm.a1, sm.b1, Abase + (ch + 1) * KC, Bbase + (uint32_t)((ch + 1) * KC) * ld, ld);
             compute(c, sm.a0, sm.b0, tx, ty, ar);
-            copies_done();
+            copies_done(sm.a1, ar);
             if (ch + 2 < nch)
                 copy_chunk(sm.a0, sm.b0, Abase + (ch + 2) * KC, Bbase + (uint32_t)((ch + 2) * KC) * ld, ld);
             compute(c, sm.a1, sm.b1, tx, ty, ar);
-            copies_done();
+            if (ch + 2 < nch) copies_done(sm.a0, ar);
         }
 #pragma unroll
         for (int m = 0; m < TM; ++m)

@@ -27,6 +27,9 @@
 #ifndef P3_DMA
 #define P3_DMA 1
 #endif
+#ifndef P3_WAVES8
+#define P3_WAVES8 1
+#endif
 
 namespace apsp {
 
@@ -59,8 +62,16 @@ phase1_kernel(void *X, int64_t ld, int64_t r0, Ar ar, Alt alt, const int32_t *__
 // [nt, 2 nt) the column panel; nt = number of P2W-wide tiles outside block r.
 template <class Ar, int BS, int P2W>
 struct P2 {
+#if P3_DMA
+    // 4-byte elements: LDS DMA; 8-byte keys strip A while staging it instead
+    using RowT = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, BS, P2W, 16, 8, 8>,
+                                    TileProduct<Ar, BS, P2W, 16, 8, 8>>;
+    using ColT = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, P2W, BS, 16, 8, 8>,
+                                    TileProduct<Ar, P2W, BS, 16, 8, 8>>;
+#else
     using RowT = TileProduct<Ar, BS, P2W, 16, 8, 8>;
     using ColT = TileProduct<Ar, P2W, BS, 16, 8, 8>;
+#endif
     static_assert(RowT::NTH == ColT::NTH, "both panel shapes use one block size");
     union Smem {
         typename RowT::Smem row;
@@ -179,12 +190,12 @@ __device__ __forceinline__ bool phase3_tile(int set, int r, int nt, int pb, int 
 
 template <class Ar, class Alt, int BS, int MT, int SET>
 __global__ void __launch_bounds__((MT / 8) * (MT / 8))
-__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? P3_WAVES : 1)))
+__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? (MT == 128 ? P3_WAVES : 2) : P3_WAVES8)))
 phase3_kernel(void *X, int64_t ld, int r, int per_xcd, Ar ar, Alt alt,
               const int32_t *__restrict__ mode, const int32_t *__restrict__ skip) {
     constexpr int set = SET;
 #if P3_DMA
-    using TP = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, MT, MT, P3_KC, 8, 8>,
+    using TP = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, MT, MT, 16, 8, 8>,
                                   TileProduct<Ar, MT, MT, 16, 8, 8>>;
 #else
     using TP = TileProduct<Ar, MT, MT, (sizeof(typename Ar::T) == 4 ? P3_KC : 16), 8, 8>;
@@ -194,7 +205,12 @@ phase3_kernel(void *X, int64_t ld, int r, int per_xcd, Ar ar, Alt alt,
     if (!phase3_tile(set, r, (int)(ld / MT), BS / MT, per_xcd, MT, crow, ccol)) return;
     const int64_t r0 = (int64_t)r * BS;
     if constexpr (!std::is_same_v<Alt, NoAlt>) {
+#if P3_DMA
+        using TQ = std::conditional_t<sizeof(typename Alt::T) == 4, TileProductDMA<Alt, MT, MT, 16, 8, 8>,
+                                      TileProduct<Alt, MT, MT, 16, 8, 8>>;
+#else
         using TQ = TileProduct<Alt, MT, MT, (sizeof(typename Alt::T) == 4 ? P3_KC : 16), 8, 8>;
+#endif
         __shared__ union {
             typename TP::Smem a;
             typename TQ::Smem b;
