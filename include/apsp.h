@@ -119,11 +119,14 @@ typedef struct {
                               on failure the solve is skipped and d_status gets
                               APSP_ERROR_INVALID_VALUE (dist/pred unchanged) */
     int32_t block_size;    /* 0 = automatic; else 64, 128 or 256 (256: distances only) */
-    int32_t use_graph;     /* nonzero: capture the round sequence once per shape into a
-                              hipGraph and replay it (fewer launches for small n) */
+    int32_t thread_tile;   /* 0 = automatic; 8 (8 x 8 register blocks, throughput) or
+                              4 (4 x 4, latency-bound small solves; block size 64 only) */
     int32_t schedule;      /* 0 = automatic: for n >= 4096, phase 3 of round r is split so that
                               phases 1-2 of round r+1 run beside most of it on a library-owned
                               second stream; 1 = one stream, rounds in order */
+    int32_t use_graph;     /* nonzero: capture the launch sequence once per shape into a
+                              hipGraph and replay it (fewer launch gaps for small n) */
+    int32_t reserved;      /* must be 0 */
     int32_t *d_status;     /* device int32 or NULL: receives APSP_SUCCESS,
                               APSP_ERROR_INVALID_VALUE or APSP_ERROR_NEGATIVE_CYCLE */
 } apsp_options_t;

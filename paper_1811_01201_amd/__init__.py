@@ -56,7 +56,8 @@ class Profile(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("thread_tile", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("d_status", ctypes.c_void_p)]
 
 
@@ -146,7 +147,7 @@ def _dtype_code(t):
 
 
 def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, status=None,
-          stream=None, check=True, schedule=0) -> int:
+          stream=None, check=True, schedule=0, thread_tile=0) -> int:
     """Solve APSP in place on a square device tensor.
 
     dist   : torch.Tensor [n, n] int32/float32 on the GPU, contiguous (weights in,
@@ -165,7 +166,7 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
         assert pred.dtype == torch.int32 and pred.is_cuda and pred.is_contiguous()
         assert tuple(pred.shape) == (n, n)
         pp = pred.data_ptr()
-    opt = Options(int(validate), int(block_size), int(use_graph), int(schedule),
+    opt = Options(int(validate), int(block_size), int(thread_tile), int(schedule), int(use_graph), 0,
                   status.data_ptr() if status is not None else None)
     st = lib().apsp_solve_ex(dist.data_ptr(), pp, n, _dtype_code(dist), _stream_ptr(stream),
                              ctypes.byref(opt))

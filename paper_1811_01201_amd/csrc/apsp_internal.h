@@ -505,52 +505,56 @@ __device__ __forceinline__ bool use_alt(const int32_t *mode) {
 
 // ---------------------------------------------------------------- phase 1
 // Closes the BS x BS diagonal block in place with BS sequential k-steps.
-// One workgroup; thread (ty, tx) keeps the TM1 x 8 block at rows ty*TM1..,
-// columns tx*8.. in registers.  Before step k the owners of column k and
-// row k publish them through LDS (double buffered by k parity, so one
-// barrier per step suffices).
-template <int BS>
+// One workgroup; thread (ty, tx) keeps the TM1 x TN1 block at rows
+// ty*TM1.., columns tx*TN1.. in registers.  Before step k the owners of
+// column k and row k publish them through LDS (double buffered by k parity,
+// so one barrier per step suffices).  TT = 8: 8 x 8 blocks (16 x 8 for
+// BS = 256); TT = 4: 4 x 4 blocks, 16x more threads per element for
+// latency-bound small solves.
+template <int BS, int TT = 8>
 struct P1Shape {
-    static constexpr int TM1 = BS >= 256 ? 16 : 8;
-    static constexpr int TX = BS / 8, TY = BS / TM1, NTH = TX * TY;
+    static constexpr int TM1 = (BS >= 256 && TT == 8) ? 16 : TT;
+    static constexpr int TN1 = TT;
+    static constexpr int TX = BS / TN1, TY = BS / TM1, NTH = TX * TY;
 };
 
+template <class Ar, int BS, int TT>
+using P1Regs = typename Ar::T[P1Shape<BS, TT>::TM1][P1Shape<BS, TT>::TN1];
+
 // The k-steps of a diagonal-block closure on a register-resident block:
-// thread (ty, tx) holds c = rows ty*TM1.., columns tx*8..; steps
-// 0 <= k < ksteps (ksteps a multiple of 16, at most BS).
-template <class Ar, int BS, bool WAVE>
-__device__ __forceinline__ void phase1_steps(typename Ar::T (&c)[P1Shape<BS>::TM1][8], int ksteps,
-                                             const Ar &ar, typename Ar::T (*colbuf)[BS],
+// steps 0 <= k < ksteps (ksteps a multiple of 16, at most BS).
+template <class Ar, int BS, bool WAVE, int TT = 8>
+__device__ __forceinline__ void phase1_steps(P1Regs<Ar, BS, TT> &c, int ksteps, const Ar &ar,
+                                             typename Ar::T (*colbuf)[BS],
                                              typename Ar::T (*rowbuf)[BS]) {
     using T = typename Ar::T;
-    constexpr int TM1 = P1Shape<BS>::TM1, TX = P1Shape<BS>::TX;
+    constexpr int TM1 = P1Shape<BS, TT>::TM1, TN1 = P1Shape<BS, TT>::TN1, TX = P1Shape<BS, TT>::TX;
     constexpr int VW = Ar::VW;
     const int tid = tile_tid<WAVE>(), tx = tid % TX, ty = tid / TX;
-    // 16 steps per iteration keep every register index static for both
-    // thread-tile heights (the owner of row k holds it at m = k mod TM1).
+    // 16 steps per iteration keep every register index static: the owner of
+    // column k holds it at n = k mod TN1, the owner of row k at m = k mod TM1.
     for (int kb = 0; kb < ksteps / 16; ++kb) {
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
-            const int k = kb * 16 + kk;
             const int buf = kk & 1;
-            if (tx == kb * 2 + kk / 8) {
+            if (tx == kb * (16 / TN1) + kk / TN1) {
 #pragma unroll
-                for (int m = 0; m < TM1; ++m) colbuf[buf][ty * TM1 + m] = ar.strip(c[m][kk % 8]);
+                for (int m = 0; m < TM1; ++m) colbuf[buf][ty * TM1 + m] = ar.strip(c[m][kk % TN1]);
             }
-            if (ty == k / TM1) {
+            if (ty == kb * (16 / TM1) + kk / TM1) {
 #pragma unroll
-                for (int n = 0; n < 8; ++n) rowbuf[buf][tx * 8 + n] = c[kk % TM1][n];
+                for (int n = 0; n < TN1; ++n) rowbuf[buf][tx * TN1 + n] = c[kk % TM1][n];
             }
             tile_sync<WAVE>();
-            T a[TM1], b[8];
+            T a[TM1], b[TN1];
 #pragma unroll
             for (int g = 0; g < TM1 / VW; ++g) ld16(&colbuf[buf][ty * TM1 + g * VW], &a[g * VW]);
 #pragma unroll
-            for (int g = 0; g < 8 / VW; ++g) ld16(&rowbuf[buf][tx * 8 + g * VW], &b[g * VW]);
+            for (int g = 0; g < TN1 / VW; ++g) ld16(&rowbuf[buf][tx * TN1 + g * VW], &b[g * VW]);
 #pragma unroll
             for (int m = 0; m < TM1; ++m)
 #pragma unroll
-                for (int n = 0; n < 8; ++n) {
+                for (int n = 0; n < TN1; ++n) {
                     // large blocks: keep each step's minima separate (fusing two
                     // steps into three-input minima costs a register per element)
                     if constexpr (TM1 > 8)
@@ -563,29 +567,30 @@ __device__ __forceinline__ void phase1_steps(typename Ar::T (&c)[P1Shape<BS>::TM
 }
 
 // Closes the BS x BS diagonal block at (r0, r0) of D in place.
-template <class Ar, int BS, bool WAVE = false>
+template <class Ar, int BS, bool WAVE = false, int TT = 8>
 __device__ __forceinline__ void phase1_body(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0,
                                             const Ar &ar, typename Ar::T (*colbuf)[BS],
                                             typename Ar::T (*rowbuf)[BS]) {
     using T = typename Ar::T;
-    constexpr int TM1 = P1Shape<BS>::TM1, TX = P1Shape<BS>::TX;
+    constexpr int TM1 = P1Shape<BS, TT>::TM1, TN1 = P1Shape<BS, TT>::TN1, TX = P1Shape<BS, TT>::TX;
     constexpr int VW = Ar::VW;
-    static_assert(!WAVE || P1Shape<BS>::NTH == 64, "a wavefront closes 64 x 64 blocks");
+    static_assert(!WAVE || P1Shape<BS, TT>::NTH == 64, "a wavefront closes 64 x 64 blocks");
+    static_assert(TM1 % VW == 0 && TN1 % VW == 0, "whole 16-byte pieces per thread");
     const int tid = tile_tid<WAVE>(), tx = tid % TX, ty = tid / TX;
     T *const base = D + r0 * ld + r0;
     const uint32_t ldu = (uint32_t)ld;
-    T c[TM1][8];
+    T c[TM1][TN1];
 #pragma unroll
     for (int m = 0; m < TM1; ++m)
 #pragma unroll
-        for (int g = 0; g < 8 / VW; ++g)
-            ld16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * 8 + g * VW), &c[m][g * VW]);
-    phase1_steps<Ar, BS, WAVE>(c, BS, ar, colbuf, rowbuf);
+        for (int g = 0; g < TN1 / VW; ++g)
+            ld16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * TN1 + g * VW), &c[m][g * VW]);
+    phase1_steps<Ar, BS, WAVE, TT>(c, BS, ar, colbuf, rowbuf);
 #pragma unroll
     for (int m = 0; m < TM1; ++m)
 #pragma unroll
-        for (int g = 0; g < 8 / VW; ++g)
-            st16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * 8 + g * VW), &c[m][g * VW]);
+        for (int g = 0; g < TN1 / VW; ++g)
+            st16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * TN1 + g * VW), &c[m][g * VW]);
 }
 
 }  // namespace apsp

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <tuple>
 #include <type_traits>
 #include <map>
 #include <mutex>
@@ -33,8 +34,8 @@
 
 namespace apsp {
 
-template <class Ar, class Alt, int BS>
-__global__ void __launch_bounds__(P1Shape<BS>::NTH)
+template <class Ar, class Alt, int BS, int TT>
+__global__ void __launch_bounds__((P1Shape<BS, TT>::NTH))
 phase1_kernel(void *X, int64_t ld, int64_t r0, Ar ar, Alt alt, const int32_t *__restrict__ mode,
               const int32_t *__restrict__ skip) {
     if (skip && *skip != APSP_SUCCESS) return;
@@ -44,12 +45,13 @@ phase1_kernel(void *X, int64_t ld, int64_t r0, Ar ar, Alt alt, const int32_t *__
     if constexpr (!std::is_same_v<Alt, NoAlt>) {
         if (use_alt<Ar, Alt>(mode)) {
             using T = typename Alt::T;
-            phase1_body<Alt, BS>((T *)X, ld, r0, alt, (T(*)[BS])lds, (T(*)[BS])(lds + 2 * BS * sizeof(T)));
+            phase1_body<Alt, BS, false, TT>((T *)X, ld, r0, alt, (T(*)[BS])lds,
+                                            (T(*)[BS])(lds + 2 * BS * sizeof(T)));
             return;
         }
     }
     using T = typename Ar::T;
-    phase1_body<Ar, BS>((T *)X, ld, r0, ar, (T(*)[BS])lds, (T(*)[BS])(lds + 2 * BS * sizeof(T)));
+    phase1_body<Ar, BS, false, TT>((T *)X, ld, r0, ar, (T(*)[BS])lds, (T(*)[BS])(lds + 2 * BS * sizeof(T)));
 }
 
 // ---------------------------------------------------------------- phase 2
@@ -60,17 +62,17 @@ phase1_kernel(void *X, int64_t ld, int64_t r0, Ar ar, Alt alt, const int32_t *__
 // Each tile spans the whole k-block along the direction it reads from
 // itself, so it can update in place.  Workgroups [0, nt) do the row panel,
 // [nt, 2 nt) the column panel; nt = number of P2W-wide tiles outside block r.
-template <class Ar, int BS, int P2W>
+template <class Ar, int BS, int P2W, int TT>
 struct P2 {
 #if P3_DMA
     // 4-byte elements: LDS DMA; 8-byte keys strip A while staging it instead
-    using RowT = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, BS, P2W, 16, 8, 8>,
-                                    TileProduct<Ar, BS, P2W, 16, 8, 8>>;
-    using ColT = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, P2W, BS, 16, 8, 8>,
-                                    TileProduct<Ar, P2W, BS, 16, 8, 8>>;
+    using RowT = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, BS, P2W, 16, TT, TT>,
+                                    TileProduct<Ar, BS, P2W, 16, TT, TT>>;
+    using ColT = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, P2W, BS, 16, TT, TT>,
+                                    TileProduct<Ar, P2W, BS, 16, TT, TT>>;
 #else
-    using RowT = TileProduct<Ar, BS, P2W, 16, 8, 8>;
-    using ColT = TileProduct<Ar, P2W, BS, 16, 8, 8>;
+    using RowT = TileProduct<Ar, BS, P2W, 16, TT, TT>;
+    using ColT = TileProduct<Ar, P2W, BS, 16, TT, TT>;
 #endif
     static_assert(RowT::NTH == ColT::NTH, "both panel shapes use one block size");
     union Smem {
@@ -102,24 +104,24 @@ constexpr int elem_size<char>() {
     return 0;
 }
 
-template <class Ar, class Alt, int BS, int P2W>
-__global__ void __launch_bounds__((BS / 8) * (P2W / 8))
+template <class Ar, class Alt, int BS, int P2W, int TT>
+__global__ void __launch_bounds__((BS / TT) * (P2W / TT))
 __attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? 2 : 1)))
 phase2_kernel(void *X, int64_t ld, int64_t r0, int nt, Ar ar, Alt alt,
               const int32_t *__restrict__ mode, const int32_t *__restrict__ skip) {
     if (skip && *skip != APSP_SUCCESS) return;
     if constexpr (!std::is_same_v<Alt, NoAlt>) {
         __shared__ union {
-            typename P2<Ar, BS, P2W>::Smem a;
-            typename P2<Alt, BS, P2W>::Smem b;
+            typename P2<Ar, BS, P2W, TT>::Smem a;
+            typename P2<Alt, BS, P2W, TT>::Smem b;
         } sm;
         if (use_alt<Ar, Alt>(mode))
-            P2<Alt, BS, P2W>::run(sm.b, (typename Alt::T *)X, ld, r0, nt, alt);
+            P2<Alt, BS, P2W, TT>::run(sm.b, (typename Alt::T *)X, ld, r0, nt, alt);
         else
-            P2<Ar, BS, P2W>::run(sm.a, (typename Ar::T *)X, ld, r0, nt, ar);
+            P2<Ar, BS, P2W, TT>::run(sm.a, (typename Ar::T *)X, ld, r0, nt, ar);
     } else {
-        __shared__ typename P2<Ar, BS, P2W>::Smem sm;
-        P2<Ar, BS, P2W>::run(sm, (typename Ar::T *)X, ld, r0, nt, ar);
+        __shared__ typename P2<Ar, BS, P2W, TT>::Smem sm;
+        P2<Ar, BS, P2W, TT>::run(sm, (typename Ar::T *)X, ld, r0, nt, ar);
     }
 }
 
@@ -188,17 +190,17 @@ __device__ __forceinline__ bool phase3_tile(int set, int r, int nt, int pb, int 
     return true;
 }
 
-template <class Ar, class Alt, int BS, int MT, int SET>
-__global__ void __launch_bounds__((MT / 8) * (MT / 8))
+template <class Ar, class Alt, int BS, int MT, int SET, int TT>
+__global__ void __launch_bounds__((MT / TT) * (MT / TT))
 __attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? (MT == 128 ? P3_WAVES : 2) : P3_WAVES8)))
 phase3_kernel(void *X, int64_t ld, int r, int per_xcd, Ar ar, Alt alt,
               const int32_t *__restrict__ mode, const int32_t *__restrict__ skip) {
     constexpr int set = SET;
 #if P3_DMA
-    using TP = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, MT, MT, 16, 8, 8>,
-                                  TileProduct<Ar, MT, MT, 16, 8, 8>>;
+    using TP = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, MT, MT, 16, TT, TT>,
+                                  TileProduct<Ar, MT, MT, 16, TT, TT>>;
 #else
-    using TP = TileProduct<Ar, MT, MT, (sizeof(typename Ar::T) == 4 ? P3_KC : 16), 8, 8>;
+    using TP = TileProduct<Ar, MT, MT, (sizeof(typename Ar::T) == 4 ? P3_KC : 16), TT, TT>;
 #endif
     if (skip && *skip != APSP_SUCCESS) return;
     int64_t crow, ccol;
@@ -206,10 +208,10 @@ phase3_kernel(void *X, int64_t ld, int r, int per_xcd, Ar ar, Alt alt,
     const int64_t r0 = (int64_t)r * BS;
     if constexpr (!std::is_same_v<Alt, NoAlt>) {
 #if P3_DMA
-        using TQ = std::conditional_t<sizeof(typename Alt::T) == 4, TileProductDMA<Alt, MT, MT, 16, 8, 8>,
-                                      TileProduct<Alt, MT, MT, 16, 8, 8>>;
+        using TQ = std::conditional_t<sizeof(typename Alt::T) == 4, TileProductDMA<Alt, MT, MT, 16, TT, TT>,
+                                      TileProduct<Alt, MT, MT, 16, TT, TT>>;
 #else
-        using TQ = TileProduct<Alt, MT, MT, (sizeof(typename Alt::T) == 4 ? P3_KC : 16), 8, 8>;
+        using TQ = TileProduct<Alt, MT, MT, (sizeof(typename Alt::T) == 4 ? P3_KC : 16), TT, TT>;
 #endif
         __shared__ union {
             typename TP::Smem a;
@@ -446,6 +448,8 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRecord> g_prof;
 
+thread_local bool t_capturing = false;  // launches are being recorded into a hipGraph
+
 struct ProfScope {
     ProfRecord rec{};
     hipStream_t s;
@@ -453,7 +457,7 @@ struct ProfScope {
     ProfScope(int kind, double updates, hipStream_t stream) : s(stream) {
         {
             std::lock_guard<std::mutex> lk(g_prof_mu);
-            on = g_prof_on;
+            on = g_prof_on && !t_capturing;
         }
         if (!on) return;
         rec.kind = kind;
@@ -516,7 +520,7 @@ apsp_status_t aux_stream(int dev, hipStream_t s, AuxStream **out) {
 //   caller: P1(0) P2(0) [panels] | wait(rest) P3x(r) P1(r+1) P2(r+1) [panels] | ...
 //   aux:    wait(panels) P3r(r) [rest] | ...
 // kCross(r+1) touches tiles last written by kRest(r), hence its wait.
-template <class Ar, class Alt, int BS>
+template <class Ar, class Alt, int BS, int TT>
 apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, const int32_t *mode,
                          hipStream_t s, const int32_t *skip, bool lookahead) {
     constexpr int MT = BS >= 128 ? 128 : 64;
@@ -535,29 +539,30 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     }
     auto p1 = [&](int r) {
         ProfScope ps(kPhase1, bs3, s);
-        hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS>), dim3(1), dim3(P1Shape<BS>::NTH), 0, s, X, ld,
-                           (int64_t)r * BS, ar, alt, mode, skip);
+        hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS, TT>), dim3(1), dim3(P1Shape<BS, TT>::NTH), 0, s, X,
+                           ld, (int64_t)r * BS, ar, alt, mode, skip);
     };
     auto p2 = [&](int r) {
         if (nt2 <= 0) return;
         ProfScope ps(kPhase2, 2.0 * bs3 * (ld / BS - 1), s);
-        hipLaunchKernelGGL((phase2_kernel<Ar, Alt, BS, P2W>), dim3(2 * nt2), dim3((BS / 8) * (P2W / 8)),
-                           0, s, X, ld, (int64_t)r * BS, nt2, ar, alt, mode, skip);
+        hipLaunchKernelGGL((phase2_kernel<Ar, Alt, BS, P2W, TT>), dim3(2 * nt2),
+                           dim3((BS / TT) * (P2W / TT)), 0, s, X, ld, (int64_t)r * BS, nt2, ar, alt, mode,
+                           skip);
     };
     auto p3 = [&](int r, int set, hipStream_t st) {
         const int64_t tiles = p3_count(set, nt, pb);
         if (tiles <= 0) return;
         const int per_xcd = (int)((tiles + 7) / 8);
         ProfScope ps(set == kCross ? kPhase3Cross : kPhase3, (double)tiles * MT * MT * BS, st);
-        const dim3 grid(8 * per_xcd), block((MT / 8) * (MT / 8));
+        const dim3 grid(8 * per_xcd), block((MT / TT) * (MT / TT));
         if (set == kAll)
-            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kAll>), grid, block, 0, st, X, ld, r, per_xcd,
-                               ar, alt, mode, skip);
+            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kAll, TT>), grid, block, 0, st, X, ld, r,
+                               per_xcd, ar, alt, mode, skip);
         else if (set == kRest)
-            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kRest>), grid, block, 0, st, X, ld, r,
+            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kRest, TT>), grid, block, 0, st, X, ld, r,
                                per_xcd, ar, alt, mode, skip);
         else
-            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kCross>), grid, block, 0, st, X, ld, r,
+            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kCross, TT>), grid, block, 0, st, X, ld, r,
                                per_xcd, ar, alt, mode, skip);
     };
     if (!aux) {
@@ -587,25 +592,34 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     return APSP_SUCCESS;
 }
 
+// Kernel configurations: (block size, thread tile).  Thread tile 4 is the
+// latency configuration for small n (64-wide blocks only).
 template <class Ar, class Alt = NoAlt>
-apsp_status_t run_rounds_bs(int bs, bool lookahead, void *X, int64_t ld, const Ar &ar, hipStream_t s,
-                            const int32_t *skip, const Alt &alt = Alt{}, const int32_t *mode = nullptr) {
+apsp_status_t run_rounds_bs(int bs, int tt, bool lookahead, void *X, int64_t ld, const Ar &ar,
+                            hipStream_t s, const int32_t *skip, const Alt &alt = Alt{},
+                            const int32_t *mode = nullptr) {
+    if (tt == 4) {
+        if (bs == 64) return run_rounds<Ar, Alt, 64, 4>(X, ld, ar, alt, mode, s, skip, lookahead);
+        return APSP_ERROR_INVALID_ARGUMENT;
+    }
     switch (bs) {
-        case 64: return run_rounds<Ar, Alt, 64>(X, ld, ar, alt, mode, s, skip, lookahead);
-        case 128: return run_rounds<Ar, Alt, 128>(X, ld, ar, alt, mode, s, skip, lookahead);
+        case 64: return run_rounds<Ar, Alt, 64, 8>(X, ld, ar, alt, mode, s, skip, lookahead);
+        case 128: return run_rounds<Ar, Alt, 128, 8>(X, ld, ar, alt, mode, s, skip, lookahead);
         case 256:
             if constexpr (sizeof(typename Ar::T) == 4)
-                return run_rounds<Ar, Alt, 256>(X, ld, ar, alt, mode, s, skip, lookahead);
+                return run_rounds<Ar, Alt, 256, 8>(X, ld, ar, alt, mode, s, skip, lookahead);
             return APSP_ERROR_INVALID_ARGUMENT;
         default: return APSP_ERROR_INVALID_ARGUMENT;
     }
 }
 
 int auto_block(int64_t n, bool pred) {
-    if (n <= 64) return 64;
+    if (n <= 4096) return 64;
     if (pred || n <= 4096) return 128;
     return 256;
 }
+
+int auto_tile(int64_t n, int bs) { return (bs == 64 && n <= 4096) ? 4 : 8; }
 
 // Work memory a solve needs beyond dist/pred (0 when it runs in place).
 size_t work_bytes(int64_t n, bool with_pred, int bs, bool aligned) {
@@ -622,6 +636,8 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
     APSP_HIP(hipGetDevice(&dev));
     const bool with_pred = pred != nullptr;
     const int bs = opt.block_size ? opt.block_size : auto_block(n, with_pred);
+    const int tt = opt.thread_tile ? opt.thread_tile : auto_tile(n, bs);
+    if (tt == 4 && bs != 64) return APSP_ERROR_INVALID_ARGUMENT;
     const bool lookahead = opt.schedule != 1;
     // caller-provided work memory (the server) or the per-stream cache
     auto workspace = [&](int d, hipStream_t st, size_t bytes, void **out) -> apsp_status_t {
@@ -656,9 +672,9 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         }
         apsp_status_t st;
         if constexpr (std::is_same_v<T, int32_t>)
-            st = run_rounds_bs<ArI32>(bs, lookahead, X, ld, ArI32{}, s, skip);
+            st = run_rounds_bs<ArI32>(bs, tt, lookahead, X, ld, ArI32{}, s, skip);
         else
-            st = run_rounds_bs<ArF32>(bs, lookahead, X, ld, ArF32{}, s, skip);
+            st = run_rounds_bs<ArF32>(bs, tt, lookahead, X, ld, ArF32{}, s, skip);
         if (st != APSP_SUCCESS) return st;
         hipLaunchKernelGGL((finalize_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, X, ld, dist, n,
                            status, skip);
@@ -679,9 +695,9 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         hipLaunchKernelGGL((pred_pack_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n, w,
                            ld, ar.S, mode, skip);
         if constexpr (std::is_same_v<T, float>)
-            st = run_rounds_bs<ArKey, ArLexF32>(bs, lookahead, w, ld, ar, s, skip, ArLexF32{}, mode);
+            st = run_rounds_bs<ArKey, ArLexF32>(bs, tt, lookahead, w, ld, ar, s, skip, ArLexF32{}, mode);
         else
-            st = run_rounds_bs<ArKey>(bs, lookahead, w, ld, ar, s, skip);
+            st = run_rounds_bs<ArKey>(bs, tt, lookahead, w, ld, ar, s, skip);
         if (st != APSP_SUCCESS) return st;
         hipLaunchKernelGGL((pred_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, w, ld, dist,
                            pred, n, ar.S, mode, status, skip);
@@ -696,11 +712,104 @@ size_t solve_work_bytes(int64_t n, apsp_dtype_t, bool with_pred) {
     return work_bytes(n, with_pred, auto_block(n, with_pred), true);
 }
 
+namespace {
+
+apsp_status_t solve_direct(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t s,
+                           const apsp_options_t &opt, void *ws, size_t ws_bytes) {
+    if (dtype == APSP_INT32) return solve_typed<int32_t>((int32_t *)dist, pred, n, s, opt, ws, ws_bytes);
+    return solve_typed<float>((float *)dist, pred, n, s, opt, ws, ws_bytes);
+}
+
+// hipGraph cache (apsp_options_t.use_graph): one executable graph per
+// (device, stream, shape, options, buffer addresses), replayed instead of
+// re-issuing the launch sequence.
+struct GraphKey {
+    int dev;
+    hipStream_t s;
+    int64_t n;
+    int dtype, validate, bs, tt, schedule;
+    void *dist, *pred, *status, *ws;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(dev, s, n, dtype, validate, bs, tt, schedule, dist, pred, status, ws) <
+               std::tie(o.dev, o.s, o.n, o.dtype, o.validate, o.bs, o.tt, o.schedule, o.dist, o.pred,
+                        o.status, o.ws);
+    }
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+constexpr size_t kMaxGraphs = 64;
+
+void drop_graphs_locked(int dev) {
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+        if (dev < 0 || it->first.dev == dev) {
+            hipGraphExecDestroy(it->second);
+            it = g_graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t s,
+                          const apsp_options_t &opt, void *ws, size_t ws_bytes) {
+    int dev = 0;
+    APSP_HIP(hipGetDevice(&dev));
+    const bool with_pred = pred != nullptr;
+    const int bs = opt.block_size ? opt.block_size : auto_block(n, with_pred);
+    const int tt = opt.thread_tile ? opt.thread_tile : auto_tile(n, bs);
+    // the work memory must exist (at its final address) before recording
+    void *w = ws;
+    const size_t need = work_bytes(n, with_pred, bs, ((uintptr_t)dist % 16) == 0);
+    if (!w && need > 0) {
+        apsp_status_t st = cached_workspace(dev, s, need, &w);
+        if (st != APSP_SUCCESS) return st;
+    }
+    if (opt.schedule != 1) {  // create the auxiliary stream outside the recording
+        AuxStream *aux = nullptr;
+        apsp_status_t st = aux_stream(dev, s, &aux);
+        if (st != APSP_SUCCESS) return st;
+    }
+    GraphKey key{dev,        s,   n,    (int)dtype, opt.validate, bs, tt, opt.schedule, dist, pred,
+                 opt.d_status, w};
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        if (g_graphs.size() >= kMaxGraphs) drop_graphs_locked(-1);
+        APSP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        t_capturing = true;
+        apsp_status_t st = solve_direct(dist, pred, n, dtype, s, opt, ws, ws_bytes);
+        t_capturing = false;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (st != APSP_SUCCESS) {
+            if (graph) hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            return APSP_ERROR_HIP;
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            return APSP_ERROR_HIP;
+        }
+        it = g_graphs.emplace(key, exec).first;
+    }
+    APSP_HIP(hipGraphLaunch(it->second, s));
+    return APSP_SUCCESS;
+}
+
+}  // namespace
+
 apsp_status_t solve_internal(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t s,
                              const apsp_options_t &opt, void *ws, size_t ws_bytes) {
     if (n == 0) return APSP_SUCCESS;
-    if (dtype == APSP_INT32) return solve_typed<int32_t>((int32_t *)dist, pred, n, s, opt, ws, ws_bytes);
-    return solve_typed<float>((float *)dist, pred, n, s, opt, ws, ws_bytes);
+    // graphs cannot be recorded on the legacy default stream
+    if (opt.use_graph && s != nullptr) return solve_graph(dist, pred, n, dtype, s, opt, ws, ws_bytes);
+    return solve_direct(dist, pred, n, dtype, s, opt, ws, ws_bytes);
 }
 
 }  // namespace apsp
@@ -740,8 +849,11 @@ apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t d
     if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.block_size != 0 && opt.block_size != 64 && opt.block_size != 128 && opt.block_size != 256)
         return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.thread_tile != 0 && opt.thread_tile != 4 && opt.thread_tile != 8) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.thread_tile == 4 && opt.block_size != 0 && opt.block_size != 64) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.block_size == 256 && pred) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.reserved != 0) return APSP_ERROR_INVALID_ARGUMENT;
     if (n == 0) return APSP_SUCCESS;
     if (!dist || ((uintptr_t)dist % 4) != 0 || ((uintptr_t)pred % 4) != 0)
         return APSP_ERROR_INVALID_ARGUMENT;
@@ -798,8 +910,12 @@ apsp_status_t apsp_release_workspace(void) {
     int dev = 0;
     APSP_HIP(hipGetDevice(&dev));
     sweep_retired(true);
-    std::lock_guard<std::mutex> lk(g_ws_mu);
     APSP_HIP(hipDeviceSynchronize());
+    {
+        std::lock_guard<std::mutex> lg(g_graph_mu);
+        drop_graphs_locked(dev);  // graphs refer to the work memory freed below
+    }
+    std::lock_guard<std::mutex> lk(g_ws_mu);
     for (auto it = g_ws.begin(); it != g_ws.end();) {
         if (it->first.first == dev) {
             if (it->second.ptr) APSP_HIP(hipFree(it->second.ptr));

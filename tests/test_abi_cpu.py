@@ -47,12 +47,16 @@ def test_host_side_argument_errors():
     assert apsp.solve_raw(None, None, 10, apsp.INT32, None) == apsp.INVALID_ARGUMENT
     assert apsp.solve_raw(ctypes.c_void_p(0x1002), None, 10, apsp.INT32, None) == apsp.INVALID_ARGUMENT
     assert apsp.solve_raw(fake, None, 0, apsp.INT32, None) == apsp.SUCCESS  # n = 0: nothing to do
-    bad_bs = apsp.Options(0, 96, 0, 0, None)
+    bad_bs = apsp.Options(0, 96, 0, 0, 0, 0, None)
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_bs) == apsp.INVALID_ARGUMENT
-    no_status = apsp.Options(1, 0, 0, 0, None)  # validate needs a status word
+    no_status = apsp.Options(1, 0, 0, 0, 0, 0, None)  # validate needs a status word
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, no_status) == apsp.INVALID_ARGUMENT
-    pred256 = apsp.Options(0, 256, 0, 0, None)
+    pred256 = apsp.Options(0, 256, 0, 0, 0, 0, None)
     assert apsp.solve_raw(fake, fake, 10, apsp.INT32, None, pred256) == apsp.INVALID_ARGUMENT
+    bad_tile = apsp.Options(0, 0, 6, 0, 0, 0, None)
+    assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_tile) == apsp.INVALID_ARGUMENT
+    tile4_bs128 = apsp.Options(0, 128, 4, 0, 0, 0, None)
+    assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, tile4_bs128) == apsp.INVALID_ARGUMENT
     assert L.apsp_status_string(3) == b"negative cycle"
     assert L.apsp_version() >= 100
 

@@ -45,16 +45,16 @@ def test_parity_auto_block(orc, n, kind, pred):
         assert first_mismatch(P, P0) is None, first_mismatch(P, P0)
 
 
-@pytest.mark.parametrize("bs", [64, 128, 256])
+@pytest.mark.parametrize("bs,tt", [(64, 4), (64, 8), (128, 8), (256, 8)])
 @pytest.mark.parametrize("n,kind", [(130, "int"), (300, "pot"), (512, "f32"), (700, "sparse")])
 @pytest.mark.parametrize("pred", [False, True])
-def test_parity_every_block_size(orc, bs, n, kind, pred):
+def test_parity_every_block_size(orc, bs, tt, n, kind, pred):
     if bs == 256 and pred:
         pytest.skip("predecessor solves use blocks of at most 128")
-    describe(f"single bs={bs} n={n} kind={kind} pred={pred}")
+    describe(f"single bs={bs} tt={tt} n={n} kind={kind} pred={pred}")
     W = _graph(kind, n, seed=77 + n)
     D0, P0, _ = oracle_expect(orc, W, pred)
-    D, P, st = gpu_solve(W, pred, block_size=bs)
+    D, P, st = gpu_solve(W, pred, block_size=bs, thread_tile=tt)
     assert st == 0
     assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
     if pred:
@@ -242,3 +242,37 @@ def test_concurrent_solves_on_streams(orc):
         D0, P0, _ = oracle_expect(orc, W, True)
         assert first_mismatch(d.cpu().numpy(), D0) is None
         assert first_mismatch(p.cpu().numpy(), P0) is None
+
+
+@pytest.mark.parametrize("n,kind,pred", [(1000, "int", False), (600, "f32", True), (4096, "pot", False)])
+def test_graph_replays_match_eager(orc, n, kind, pred):
+    """use_graph records the launch sequence once and replays it; every replay
+    (with other eager work and synchronisations in between) equals the eager
+    solve, and the eager solve equals the oracle where the oracle is cheap."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe(f"single graph replays n={n} {kind} pred={pred}")
+    W = _graph(kind, n, seed=31 + n)
+    De, Pe, se = gpu_solve(W, pred)
+    assert se == 0
+    if n <= 1024:
+        D0, P0, _ = oracle_expect(orc, W, pred)
+        assert first_mismatch(De, D0) is None
+    stream = torch.cuda.Stream()
+    pristine = torch.from_numpy(W).cuda()
+    d = torch.empty_like(pristine)
+    p = torch.empty(W.shape, dtype=torch.int32, device="cuda") if pred else None
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    other = torch.from_numpy(_graph("int", 300, seed=3)).cuda()
+    for rep in range(4):
+        with torch.cuda.stream(stream):
+            d.copy_(pristine)
+            apsp.solve(d, p, status=st, use_graph=True, stream=stream)
+        stream.synchronize()
+        assert int(st.item()) == 0
+        assert first_mismatch(d.cpu().numpy(), De) is None, rep
+        if pred:
+            assert first_mismatch(p.cpu().numpy(), Pe) is None, rep
+        apsp.solve(other.clone())  # eager work between replays
+        torch.cuda.synchronize()
