@@ -209,6 +209,38 @@ apsp_status_t apsp_batch_plan_execute(const apsp_batch_plan_t *plan, void *packe
                                       int32_t *packed_pred, int32_t *d_status, hipStream_t stream);
 apsp_status_t apsp_batch_plan_destroy(apsp_batch_plan_t *plan);
 
+/* As apsp_batch_plan_create, with the team configuration of each graph
+ * (n > 64) forced: team_config[b] = 0 wavefront-private 64 x 64 tiles with
+ * 8 x 8 registers per lane, 1 workgroup 64 x 64 tiles with 4 x 4 per thread,
+ * 2 workgroup 128 x 128 tiles with 8 x 8 per thread and 128-wide k-blocks,
+ * -1 = the tuning table's choice for the graph's size class.  NULL = all -1. */
+apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offsets, int32_t batch,
+                                        apsp_dtype_t dtype, int32_t want_pred, const int8_t *team_config,
+                                        apsp_batch_plan_t **out_plan);
+
+/* ------------------------------------------------------------- autotuning
+ *
+ * The batched launch picks a team configuration (tile size and per-thread
+ * register block, see apsp_batch_plan_create_ex) per graph from a table
+ * indexed by (dtype, predecessors, size class), size classes n in (64,128],
+ * (128,256], (256,384], (384,512], (512,1024].  The table starts from
+ * built-in defaults, is read from the JSON file named by the environment
+ * variable APSP_TUNE_TABLE on first use, and can be measured on the current
+ * device: apsp_batch_autotune builds one synthetic batch with
+ * graphs_per_class graphs in every size class (0 = CU count) and, class by
+ * class (coordinate descent, the other classes at their current choice),
+ * times the whole batch with each configuration for that class (reps timed
+ * executions, 0 = 3) and keeps the fastest.  ms_out[class * 3 + config]
+ * (when not NULL) receives the per-execution milliseconds of each trial.
+ * It allocates device memory and synchronises its own stream.
+ */
+apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t graphs_per_class,
+                                  int32_t reps, double *ms_out);
+/* Team configuration the table gives a graph of n vertices (-1: n <= 64, one wavefront). */
+int32_t apsp_batch_config(int64_t n, apsp_dtype_t dtype, int32_t want_pred);
+apsp_status_t apsp_tune_save(const char *path);
+apsp_status_t apsp_tune_load(const char *path);
+
 /* create + execute; the plan is freed by a later library call once the
  * stream has passed it (no synchronisation here). */
 apsp_status_t apsp_solve_batched(void *packed_dist, int32_t *packed_pred, const int32_t *ns,

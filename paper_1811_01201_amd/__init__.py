@@ -114,6 +114,11 @@ def _bind_optional(L):
         "apsp_server_stats": ([vp, vp], c_int),
         "apsp_server_destroy": ([vp], c_int),
         "apsp_probe_valu": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], c_int),
+        "apsp_batch_plan_create_ex": ([vp, vp, i32, c_int, i32, vp, ctypes.POINTER(vp)], c_int),
+        "apsp_batch_autotune": ([c_int, i32, i32, i32, ctypes.POINTER(ctypes.c_double)], c_int),
+        "apsp_batch_config": ([i64, c_int, i32], i32),
+        "apsp_tune_save": ([ctypes.c_char_p], c_int),
+        "apsp_tune_load": ([ctypes.c_char_p], c_int),
     }
     for name, (args, res) in table.items():
         f = getattr(L, name, None)
@@ -218,7 +223,7 @@ class BatchPlan:
     ns / offsets: host sequences (graph sizes, element offsets of each graph
     in the packed buffers; offsets multiples of 4)."""
 
-    def __init__(self, ns, offsets, dtype: str = "int32", want_pred: bool = False):
+    def __init__(self, ns, offsets, dtype: str = "int32", want_pred: bool = False, team_config=None):
         import numpy as np
         self._ns = np.ascontiguousarray(ns, dtype=np.int32)
         self._offsets = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -227,8 +232,13 @@ class BatchPlan:
         self.dtype = INT32 if dtype in ("int32", INT32) else FLOAT32
         self.want_pred = bool(want_pred)
         self._plan = ctypes.c_void_p()
-        st = lib().apsp_batch_plan_create(self._ns.ctypes.data, self._offsets.ctypes.data, self.batch,
-                                          self.dtype, int(self.want_pred), ctypes.byref(self._plan))
+        cfg = None
+        if team_config is not None:
+            self._cfg = np.ascontiguousarray(np.broadcast_to(team_config, self._ns.shape), dtype=np.int8)
+            cfg = self._cfg.ctypes.data
+        st = lib().apsp_batch_plan_create_ex(self._ns.ctypes.data, self._offsets.ctypes.data, self.batch,
+                                             self.dtype, int(self.want_pred), cfg,
+                                             ctypes.byref(self._plan))
         if st != SUCCESS:
             raise APSPError(st, "apsp_batch_plan_create")
 
@@ -377,3 +387,41 @@ class Server:
 
     def __exit__(self, *exc):
         self.destroy()
+
+
+TEAM_CONFIGS = ("wave_tiles_64", "group_tiles_64", "group_tiles_128")
+SIZE_CLASSES = (128, 256, 384, 512, 1024)
+
+
+def batch_autotune(dtype="int32", want_pred=False, graphs_per_class=0, reps=0) -> dict:
+    """Time every batched team configuration per size class on the current
+    device and keep the fastest in the library's table.  Returns
+    {class_upper_bound: {config_name: ms, ..., "best": name}}."""
+    ms = (ctypes.c_double * (len(SIZE_CLASSES) * 3))()
+    dt = INT32 if dtype in ("int32", INT32) else FLOAT32
+    st = lib().apsp_batch_autotune(dt, int(want_pred), int(graphs_per_class), int(reps), ms)
+    if st != SUCCESS:
+        raise APSPError(st, "apsp_batch_autotune")
+    out = {}
+    for c, hi in enumerate(SIZE_CLASSES):
+        row = {TEAM_CONFIGS[k]: ms[c * 3 + k] for k in range(3)}
+        row["best"] = TEAM_CONFIGS[lib().apsp_batch_config(hi, dt, int(want_pred))]
+        out[hi] = row
+    return out
+
+
+def batch_config(n, dtype="int32", want_pred=False) -> int:
+    dt = INT32 if dtype in ("int32", INT32) else FLOAT32
+    return int(lib().apsp_batch_config(int(n), dt, int(want_pred)))
+
+
+def tune_save(path: str) -> None:
+    st = lib().apsp_tune_save(path.encode())
+    if st != SUCCESS:
+        raise APSPError(st, "apsp_tune_save")
+
+
+def tune_load(path: str) -> None:
+    st = lib().apsp_tune_load(path.encode())
+    if st != SUCCESS:
+        raise APSPError(st, "apsp_tune_load")

@@ -17,6 +17,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -30,6 +34,7 @@ struct BatchMeta {
     const int32_t *order;    // graph ids, largest n first
     const int32_t *ns;       // n of each graph
     const int64_t *offsets;  // element offset of each graph in the packed buffers
+    const int8_t *cfg;       // team configuration of each graph
     int32_t batch;
     int32_t n_team;          // order[0, n_team) have n > 64
     int64_t scratch_elems;   // work-matrix elements per workgroup
@@ -37,6 +42,7 @@ struct BatchMeta {
 
 constexpr int kBatchBS = 64;
 constexpr int kBatchThreads = 256;
+enum TeamCfg { kWaveTiles64 = 0, kGroupTiles64 = 1, kGroupTiles128 = 2 };
 
 // ------------------------------------------------ input/output conversion
 template <class Ar, class Tin>
@@ -104,22 +110,46 @@ __device__ __forceinline__ bool from_work(const Ar &ar, typename Ar::T v, int64_
 }
 
 // ------------------------------------------------------------ team path
+// Team configurations (chosen per graph; see the plan's size classes):
+//   kWaveTiles64   64-wide k-blocks; each wavefront owns whole 64 x 64 tiles
+//                  (8 x 8 registers per lane, no workgroup barrier inside a
+//                  tile); wavefront 0 closes the diagonal block
+//   kGroupTiles64  64-wide k-blocks; the workgroup works on one 64 x 64 tile
+//                  at a time (4 x 4 registers per thread) and closes the
+//                  diagonal block together (4 x 4 per thread)
+//   kGroupTiles128 128-wide k-blocks; 128 x 128 workgroup tiles (8 x 8 per
+//                  thread), diagonal block closed by the workgroup
 template <class Ar>
 using BTile = TileProduct<Ar, kBatchBS, kBatchBS, (sizeof(typename Ar::T) == 4 ? 16 : 8), 8, 8, true>;
-
 template <class Ar>
-struct alignas(16) TeamSmem {
-    typename BTile<Ar>::Smem tile[kBatchThreads / 64];
+using GTile64 = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, 64, 64, 16, 4, 4>,
+                                   TileProduct<Ar, 64, 64, 16, 4, 4>>;
+template <class Ar>
+using GTile128 = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, 128, 128, 16, 8, 8>,
+                                    TileProduct<Ar, 128, 128, 16, 8, 8>>;
+
+template <int CFG>
+struct TeamShape {
+    static constexpr int BS = CFG == kGroupTiles128 ? 128 : 64;
 };
 
-template <class Ar, class Tin>
+template <class Ar>
+union alignas(16) TeamSmem {
+    typename BTile<Ar>::Smem wave[kBatchThreads / 64];
+    typename GTile64<Ar>::Smem g64;
+    typename GTile128<Ar>::Smem g128;
+    typename Ar::T p1[4 * 128];  // phase-1 publication buffers
+};
+
+template <class Ar, class Tin, int CFG>
 __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__restrict__ pred,
                            int32_t *__restrict__ status, int g, int64_t n, int64_t off,
                            typename Ar::T *__restrict__ X, TeamSmem<Ar> &sm) {
     using T = typename Ar::T;
+    constexpr int BS = TeamShape<CFG>::BS;
     Ar ar = ar0;
     const int tid = threadIdx.x, wave = tid >> 6;
-    const int64_t ldp = (n + kBatchBS - 1) / kBatchBS * kBatchBS;
+    const int64_t ldp = (n + BS - 1) / BS * BS;
     if constexpr (std::is_same_v<Ar, ArKey>) {
         int S = 1;
         while ((int64_t(1) << S) < ldp + 1) ++S;
@@ -132,32 +162,64 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
         X[e] = to_work(ar, w, inside, i, j);
     }
     __syncthreads();
-    const int R = (int)(ldp / kBatchBS);
+    const int R = (int)(ldp / BS);
     const int nt = R - 1;
+    T(*buf)[BS] = reinterpret_cast<T(*)[BS]>(sm.p1);
     for (int r = 0; r < R; ++r) {
-        const int64_t r0 = (int64_t)r * kBatchBS;
-        if (wave == 0) {
-            T(*buf)[kBatchBS] = reinterpret_cast<T(*)[kBatchBS]>(&sm.tile[0]);
-            phase1_body<Ar, kBatchBS, true>(X, ldp, r0, ar, buf, buf + 2);
+        const int64_t r0 = (int64_t)r * BS;
+        // phase 1
+        if constexpr (CFG == kWaveTiles64) {
+            if (wave == 0) phase1_body<Ar, 64, true, 8>(X, ldp, r0, ar, buf, buf + 2);
+        } else if constexpr (CFG == kGroupTiles64) {
+            phase1_body<Ar, 64, false, 4>(X, ldp, r0, ar, buf, buf + 2);
+        } else {
+            phase1_body<Ar, 128, false, 8>(X, ldp, r0, ar, buf, buf + 2);
         }
         __syncthreads();
-        for (int t = wave; t < 2 * nt; t += kBatchThreads / 64) {
-            const bool is_row = t < nt;
-            int tt = is_row ? t : t - nt;
-            tt += (tt >= r) ? 1 : 0;
-            const int64_t o = (int64_t)tt * kBatchBS;
-            if (is_row)
-                BTile<Ar>::run(sm.tile[wave], X, ldp, r0, o, r0, kBatchBS, ar);
-            else
-                BTile<Ar>::run(sm.tile[wave], X, ldp, o, r0, r0, kBatchBS, ar);
+        // phase 2: block row r (tiles t < nt) and block column r
+        if constexpr (CFG == kWaveTiles64) {
+            for (int t = wave; t < 2 * nt; t += kBatchThreads / 64) {
+                const bool is_row = t < nt;
+                int q = is_row ? t : t - nt;
+                q += (q >= r) ? 1 : 0;
+                const int64_t o = (int64_t)q * BS;
+                if (is_row)
+                    BTile<Ar>::run(sm.wave[wave], X, ldp, r0, o, r0, BS, ar);
+                else
+                    BTile<Ar>::run(sm.wave[wave], X, ldp, o, r0, r0, BS, ar);
+            }
+        } else {
+            for (int t = 0; t < 2 * nt; ++t) {
+                const bool is_row = t < nt;
+                int q = is_row ? t : t - nt;
+                q += (q >= r) ? 1 : 0;
+                const int64_t o = (int64_t)q * BS;
+                const int64_t crow = is_row ? r0 : o, ccol = is_row ? o : r0;
+                if constexpr (CFG == kGroupTiles64)
+                    GTile64<Ar>::run(sm.g64, X, ldp, crow, ccol, r0, BS, ar);
+                else
+                    GTile128<Ar>::run(sm.g128, X, ldp, crow, ccol, r0, BS, ar);
+            }
         }
         __syncthreads();
-        for (int t = wave; t < nt * nt; t += kBatchThreads / 64) {
-            int ti = t / nt, tj = t - (t / nt) * nt;
-            ti += (ti >= r) ? 1 : 0;
-            tj += (tj >= r) ? 1 : 0;
-            BTile<Ar>::run(sm.tile[wave], X, ldp, (int64_t)ti * kBatchBS, (int64_t)tj * kBatchBS, r0,
-                           kBatchBS, ar);
+        // phase 3: every other tile
+        if constexpr (CFG == kWaveTiles64) {
+            for (int t = wave; t < nt * nt; t += kBatchThreads / 64) {
+                int ti = t / nt, tj = t - (t / nt) * nt;
+                ti += (ti >= r) ? 1 : 0;
+                tj += (tj >= r) ? 1 : 0;
+                BTile<Ar>::run(sm.wave[wave], X, ldp, (int64_t)ti * BS, (int64_t)tj * BS, r0, BS, ar);
+            }
+        } else {
+            for (int t = 0; t < nt * nt; ++t) {
+                int ti = t / nt, tj = t - (t / nt) * nt;
+                ti += (ti >= r) ? 1 : 0;
+                tj += (tj >= r) ? 1 : 0;
+                if constexpr (CFG == kGroupTiles64)
+                    GTile64<Ar>::run(sm.g64, X, ldp, (int64_t)ti * BS, (int64_t)tj * BS, r0, BS, ar);
+                else
+                    GTile128<Ar>::run(sm.g128, X, ldp, (int64_t)ti * BS, (int64_t)tj * BS, r0, BS, ar);
+            }
         }
         __syncthreads();
     }
@@ -169,6 +231,22 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
     neg = __syncthreads_or(neg);
     if (status && tid == 0) status[g] = neg ? APSP_ERROR_NEGATIVE_CYCLE : APSP_SUCCESS;
     __syncthreads();
+}
+
+template <class Ar, class Tin>
+__device__ void team_dispatch(int cfg, const Ar &ar, Tin *__restrict__ dist, int32_t *__restrict__ pred,
+                              int32_t *__restrict__ status, int g, int64_t n, int64_t off,
+                              typename Ar::T *__restrict__ X, TeamSmem<Ar> &sm) {
+#ifdef BATCH_ONLY_CFG
+    team_solve<Ar, Tin, BATCH_ONLY_CFG>(ar, dist, pred, status, g, n, off, X, sm);
+    return;
+#endif
+    if (cfg == kGroupTiles64)
+        team_solve<Ar, Tin, kGroupTiles64>(ar, dist, pred, status, g, n, off, X, sm);
+    else if (cfg == kGroupTiles128)
+        team_solve<Ar, Tin, kGroupTiles128>(ar, dist, pred, status, g, n, off, X, sm);
+    else
+        team_solve<Ar, Tin, kWaveTiles64>(ar, dist, pred, status, g, n, off, X, sm);
 }
 
 // ------------------------------------------------------ wavefront path
@@ -245,14 +323,15 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
             }
             use_alt = __syncthreads_or(lex);
         }
+        const int cfg = meta.cfg[g];
         if constexpr (kDual) {
             if (use_alt) {
-                team_solve<Alt, Tin>(alt, dist, pred, status, g, n, off, (typename Alt::T *)my_scratch,
-                                     sm.b);
+                team_dispatch<Alt, Tin>(cfg, alt, dist, pred, status, g, n, off,
+                                        (typename Alt::T *)my_scratch, sm.b);
                 continue;
             }
         }
-        team_solve<Ar, Tin>(ar, dist, pred, status, g, n, off, (typename Ar::T *)my_scratch, sm.a);
+        team_dispatch<Ar, Tin>(cfg, ar, dist, pred, status, g, n, off, (typename Ar::T *)my_scratch, sm.a);
     }
     // small graphs: every wavefront on its own
     const int wave = tid >> 6, lane = tid & 63;
@@ -277,13 +356,13 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
         if constexpr (kDual) {
             if (use_alt) {
                 using TA = typename Alt::T;
-                TA(*buf)[kBatchBS] = reinterpret_cast<TA(*)[kBatchBS]>(&sm.b.tile[wave]);
+                TA(*buf)[kBatchBS] = reinterpret_cast<TA(*)[kBatchBS]>(&sm.b.wave[wave]);
                 wave_solve<Alt, Tin>(alt, dist, pred, status, g, n, off, buf, buf + 2);
                 continue;
             }
         }
         using TR = typename Ar::T;
-        TR(*buf)[kBatchBS] = reinterpret_cast<TR(*)[kBatchBS]>(&sm.a.tile[wave]);
+        TR(*buf)[kBatchBS] = reinterpret_cast<TR(*)[kBatchBS]>(&sm.a.wave[wave]);
         wave_solve<Ar, Tin>(ar, dist, pred, status, g, n, off, buf, buf + 2);
     }
     __syncthreads();
@@ -356,6 +435,7 @@ apsp_status_t launch(const BatchLaunch &L, void *dist, int32_t *pred, int32_t *s
     m.order = (const int32_t *)L.meta;
     m.ns = m.order + L.batch;
     m.offsets = (const int64_t *)((const char *)L.meta + (size_t)L.batch * 8);
+    m.cfg = (const int8_t *)((const char *)L.meta + (size_t)L.batch * 16);
     m.batch = L.batch;
     m.n_team = L.n_team;
     m.scratch_elems = L.scratch_elems;
@@ -392,6 +472,148 @@ void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, 
     while (n_team < batch && ns[order[n_team]] > kBatchBS) ++n_team;
 }
 
+// ------------------------------------------------------- tuning table
+// Team configuration per (dtype, predecessors, size class); size classes
+// are n in (64,128], (128,256], (256,384], (384,512], (512,1024].
+constexpr int kClasses = 5;
+constexpr int kClassHi[kClasses] = {128, 256, 384, 512, 1024};
+std::mutex g_tune_mu;
+int8_t g_tune[2][2][kClasses] = {
+    // int32: distances, predecessors
+    {{kGroupTiles64, kGroupTiles64, kWaveTiles64, kWaveTiles64, kWaveTiles64},
+     {kGroupTiles64, kGroupTiles64, kWaveTiles64, kWaveTiles64, kWaveTiles64}},
+    // float32
+    {{kGroupTiles64, kGroupTiles64, kWaveTiles64, kWaveTiles64, kWaveTiles64},
+     {kGroupTiles64, kGroupTiles64, kWaveTiles64, kWaveTiles64, kWaveTiles64}}};
+bool g_tune_env_checked = false;
+
+int size_class(int64_t n) {
+    for (int c = 0; c < kClasses; ++c)
+        if (n <= kClassHi[c]) return c;
+    return kClasses - 1;
+}
+
+int team_bs(int cfg) { return cfg == kGroupTiles128 ? 128 : 64; }
+
+apsp_status_t tune_load_locked(const char *path);
+
+int8_t batch_config(int64_t n, apsp_dtype_t dtype, bool pred) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_env_checked) {
+        g_tune_env_checked = true;
+        if (const char *env = std::getenv("APSP_TUNE_TABLE")) tune_load_locked(env);
+    }
+    return g_tune[dtype == APSP_FLOAT32][pred ? 1 : 0][size_class(n)];
+}
+
+// JSON form of the table:
+//   {"version": 1, "classes": [128, 256, 384, 512, 1024],
+//    "configs": ["wave_tiles_64", "group_tiles_64", "group_tiles_128"],
+//    "table": {"int32": {"dist": [c0..c4], "pred": [..]}, "float32": {...}}}
+apsp_status_t tune_load_locked(const char *path) {
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return APSP_ERROR_INVALID_ARGUMENT;
+    std::string text;
+    char chunk[4096];
+    size_t got;
+    while ((got = std::fread(chunk, 1, sizeof chunk, f)) > 0) text.append(chunk, got);
+    std::fclose(f);
+    int8_t t[2][2][kClasses];
+    const char *dts[2] = {"\"int32\"", "\"float32\""};
+    const char *modes[2] = {"\"dist\"", "\"pred\""};
+    for (int d = 0; d < 2; ++d) {
+        const size_t pd = text.find(dts[d]);
+        if (pd == std::string::npos) return APSP_ERROR_INVALID_VALUE;
+        for (int m = 0; m < 2; ++m) {
+            const size_t pm = text.find(modes[m], pd);
+            const size_t lb = pm == std::string::npos ? pm : text.find('[', pm);
+            if (lb == std::string::npos) return APSP_ERROR_INVALID_VALUE;
+            const char *q = text.c_str() + lb + 1;
+            for (int c = 0; c < kClasses; ++c) {
+                char *end = nullptr;
+                const long v = std::strtol(q, &end, 10);
+                if (end == q || v < kWaveTiles64 || v > kGroupTiles128) return APSP_ERROR_INVALID_VALUE;
+                t[d][m][c] = (int8_t)v;
+                q = end;
+                while (*q == ' ' || *q == ',' || *q == '\n') ++q;
+            }
+        }
+    }
+    std::memcpy(g_tune, t, sizeof t);
+    return APSP_SUCCESS;
+}
+
+apsp_status_t tune_save_locked(const char *path) {
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return APSP_ERROR_INVALID_ARGUMENT;
+    std::fprintf(f, "{\"version\": 1, \"classes\": [128, 256, 384, 512, 1024],\n");
+    std::fprintf(f, " \"configs\": [\"wave_tiles_64\", \"group_tiles_64\", \"group_tiles_128\"],\n");
+    std::fprintf(f, " \"table\": {");
+    const char *dts[2] = {"int32", "float32"};
+    for (int d = 0; d < 2; ++d) {
+        std::fprintf(f, "%s\"%s\": {", d ? ", " : "", dts[d]);
+        for (int m = 0; m < 2; ++m) {
+            std::fprintf(f, "%s\"%s\": [", m ? ", " : "", m ? "pred" : "dist");
+            for (int c = 0; c < kClasses; ++c) std::fprintf(f, "%s%d", c ? ", " : "", (int)g_tune[d][m][c]);
+            std::fprintf(f, "]");
+        }
+        std::fprintf(f, "}");
+    }
+    std::fprintf(f, "}}\n");
+    return std::fclose(f) == 0 ? APSP_SUCCESS : APSP_ERROR_INVALID_ARGUMENT;
+}
+
+// Synthetic batch for tuning: graph b (one block each) gets edges with
+// probability 1/2, weights 1..1000, from an integer hash of (b, i, j).
+template <class T>
+__global__ void tune_fill_kernel(T *buf, const int64_t *offs, const int32_t *ns, int32_t B) {
+    for (int32_t b = blockIdx.x; b < B; b += gridDim.x) {
+        const int64_t n = ns[b];
+        T *g = buf + offs[b];
+        for (int64_t e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int64_t i = e / n, j = e - i * n;
+            uint32_t h = (uint32_t)(b * 2654435761u) ^ (uint32_t)(i * 40503u) ^ (uint32_t)(j * 2246822519u);
+            h ^= h >> 15;
+            h *= 2246822519u;
+            h ^= h >> 13;
+            T w;
+            if (i == j)
+                w = T(0);
+            else if (h & 1)
+                w = T(1 + (h >> 1) % 1000);
+            else if constexpr (std::is_same_v<T, int32_t>)
+                w = kInf32;
+            else
+                w = __builtin_inff();
+            g[e] = w;
+        }
+    }
+}
+
+// Host image of a batch's device metadata:
+//   order[B] int32 | ns[B] int32 | offsets[B] int64 | cfg[B] int8
+// with the team configuration of every graph (forced or from the table),
+// and the work-matrix elements one workgroup needs.
+void batch_meta(const int32_t *ns, const int64_t *offsets, int32_t B, apsp_dtype_t dtype, bool pred,
+                const int8_t *forced, std::vector<char> &bytes, int32_t &n_team, int64_t &scratch_elems) {
+    std::vector<int32_t> order;
+    batch_order(ns, B, order, n_team);
+    bytes.assign(std::max<size_t>((size_t)B * 17 + 16, 32), 0);
+    std::copy(order.begin(), order.end(), (int32_t *)bytes.data());
+    std::copy(ns, ns + B, (int32_t *)bytes.data() + B);
+    std::copy(offsets, offsets + B, (int64_t *)(bytes.data() + (size_t)B * 8));
+    int8_t *cfg = (int8_t *)(bytes.data() + (size_t)B * 16);
+    scratch_elems = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        int8_t c = forced && forced[b] >= 0 ? forced[b] : batch_config(ns[b], dtype, pred);
+        cfg[b] = c;
+        if (ns[b] > kBatchBS) {
+            const int64_t bs = team_bs(c), ldp = (ns[b] + bs - 1) / bs * bs;
+            scratch_elems = std::max(scratch_elems, ldp * ldp);
+        }
+    }
+}
+
 // wait == true: block until every retired plan can be freed.
 void sweep_retired(bool wait) {
     std::lock_guard<std::mutex> lk(g_retired_mu);
@@ -410,20 +632,22 @@ void sweep_retired(bool wait) {
 
 extern "C" {
 
-apsp_status_t apsp_batch_plan_create(const int32_t *ns, const int64_t *offsets, int32_t batch,
-                                     apsp_dtype_t dtype, int32_t want_pred, apsp_batch_plan_t **out_plan) {
+apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offsets, int32_t batch,
+                                        apsp_dtype_t dtype, int32_t want_pred, const int8_t *team_config,
+                                        apsp_batch_plan_t **out_plan) {
     if (!out_plan) return APSP_ERROR_INVALID_ARGUMENT;
     sweep_retired(false);
     *out_plan = nullptr;
     if (batch < 0 || (batch > 0 && (!ns || !offsets))) return APSP_ERROR_INVALID_ARGUMENT;
     if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
-    int64_t max_n = 0, max_end = 0;
+    int64_t max_end = 0;
     std::vector<std::pair<int64_t, int64_t>> spans;
     spans.reserve(batch);
     for (int32_t b = 0; b < batch; ++b) {
         if (ns[b] < 1 || ns[b] > 1024 || offsets[b] < 0 || offsets[b] % 4 != 0)
             return APSP_ERROR_INVALID_ARGUMENT;
-        max_n = std::max<int64_t>(max_n, ns[b]);
+        if (team_config && (team_config[b] < -1 || team_config[b] > kGroupTiles128))
+            return APSP_ERROR_INVALID_ARGUMENT;
         const int64_t end = offsets[b] + (int64_t)ns[b] * ns[b];
         max_end = std::max(max_end, end);
         spans.push_back({offsets[b], end});
@@ -444,20 +668,10 @@ apsp_status_t apsp_batch_plan_create(const int32_t *ns, const int64_t *offsets, 
     }
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
-
-    std::vector<int32_t> order;
-    batch_order(ns, batch, order, p->n_team);
-    const int64_t ldp_max = std::max<int64_t>(kBatchBS, (max_n + kBatchBS - 1) / kBatchBS * kBatchBS);
-    p->scratch_elems = p->n_team > 0 ? ldp_max * ldp_max : 0;
+    std::vector<char> host;
+    batch_meta(ns, offsets, batch, dtype, p->want_pred, team_config, host, p->n_team, p->scratch_elems);
     p->grid = std::max(1, 2 * cus);
-
     const size_t elem = p->want_pred ? 8 : 4;
-    // device metadata: order[batch] int32 | ns[batch] int32 | offsets[batch] int64
-    const size_t meta_bytes = (size_t)batch * 16;
-    std::vector<char> host(std::max<size_t>(meta_bytes, 16));
-    std::copy(order.begin(), order.end(), (int32_t *)host.data());
-    std::copy(ns, ns + batch, (int32_t *)host.data() + batch);
-    std::copy(offsets, offsets + batch, (int64_t *)(host.data() + (size_t)batch * 8));
     if (hipMalloc(&p->dev_meta, host.size()) != hipSuccess ||
         hipMalloc((void **)&p->counters, 4 * sizeof(int32_t)) != hipSuccess ||
         (p->scratch_elems > 0 &&
@@ -474,6 +688,11 @@ apsp_status_t apsp_batch_plan_create(const int32_t *ns, const int64_t *offsets, 
     return APSP_SUCCESS;
 }
 
+apsp_status_t apsp_batch_plan_create(const int32_t *ns, const int64_t *offsets, int32_t batch,
+                                     apsp_dtype_t dtype, int32_t want_pred, apsp_batch_plan_t **out_plan) {
+    return apsp_batch_plan_create_ex(ns, offsets, batch, dtype, want_pred, nullptr, out_plan);
+}
+
 apsp_status_t apsp_batch_plan_execute(const apsp_batch_plan_t *plan, void *packed_dist,
                                       int32_t *packed_pred, int32_t *d_status, hipStream_t stream) {
     if (!plan) return APSP_ERROR_INVALID_ARGUMENT;
@@ -488,20 +707,131 @@ apsp_status_t apsp_batch_plan_execute(const apsp_batch_plan_t *plan, void *packe
 
 apsp_status_t apsp_batch_plan_destroy(apsp_batch_plan_t *plan) { return plan_free(plan); }
 
-apsp_status_t apsp_solve_batched(void *packed_dist, int32_t *packed_pred, const int32_t *ns,
-                                 const int64_t *offsets, int32_t batch, apsp_dtype_t dtype,
-                                 hipStream_t stream) {
-    sweep_retired(false);
-    apsp_batch_plan_t *plan = nullptr;
-    apsp_status_t st =
-        apsp_batch_plan_create(ns, offsets, batch, dtype, packed_pred != nullptr ? 1 : 0, &plan);
-    if (st != APSP_SUCCESS) return st;
-    st = apsp_batch_plan_execute(plan, packed_dist, packed_pred, nullptr, stream);
-    if (st != APSP_SUCCESS) {
-        plan_free(plan);
-        return st;
+int32_t apsp_batch_config(int64_t n, apsp_dtype_t dtype, int32_t want_pred) {
+    if (n <= kBatchBS) return -1;  // solved by one wavefront in registers
+    return batch_config(n, dtype, want_pred != 0);
+}
+
+apsp_status_t apsp_tune_load(const char *path) {
+    if (!path) return APSP_ERROR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_env_checked = true;
+    return tune_load_locked(path);
+}
+
+apsp_status_t apsp_tune_save(const char *path) {
+    if (!path) return APSP_ERROR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return tune_save_locked(path);
+}
+
+apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t graphs_per_class,
+                                  int32_t reps, double *ms_out) {
+    if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
+    if (graphs_per_class < 0 || reps < 0) return APSP_ERROR_INVALID_ARGUMENT;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess) return APSP_ERROR_HIP;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int32_t per = graphs_per_class ? graphs_per_class : cus;
+    const int R = reps ? reps : 3;
+    const int d = dtype == APSP_FLOAT32, m = want_pred ? 1 : 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (!g_tune_env_checked) {
+            g_tune_env_checked = true;
+            if (const char *env = std::getenv("APSP_TUNE_TABLE")) tune_load_locked(env);
+        }
     }
-    return retire(plan, stream);
+    // one mixed batch: `per` graphs spread over every size class, so the
+    // measurement sees the classes interact (shared CUs, caches, queue order)
+    const int32_t B = per * kClasses;
+    std::vector<int32_t> ns(B), cls(B);
+    std::vector<int64_t> offs(B);
+    int64_t total = 0;
+    for (int c = 0, b = 0; c < kClasses; ++c) {
+        const int lo = c == 0 ? kBatchBS + 1 : kClassHi[c - 1] + 1, hi = kClassHi[c];
+        for (int32_t q = 0; q < per; ++q, ++b) {
+            ns[b] = lo + (int32_t)(((int64_t)q * (hi - lo + 1)) / per);
+            cls[b] = c;
+            offs[b] = total;
+            total += ((int64_t)ns[b] * ns[b] + 3) / 4 * 4;
+        }
+    }
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return APSP_ERROR_HIP;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    void *dist = nullptr, *pred = nullptr, *meta = nullptr;
+    apsp_status_t result = APSP_SUCCESS;
+    if (hipMalloc(&dist, (size_t)total * 4) != hipSuccess ||
+        (want_pred && hipMalloc(&pred, (size_t)total * 4) != hipSuccess) ||
+        hipMalloc(&meta, (size_t)B * 12) != hipSuccess)
+        result = APSP_ERROR_OUT_OF_MEMORY;
+    if (result == APSP_SUCCESS) {
+        hipMemcpy(meta, offs.data(), (size_t)B * 8, hipMemcpyHostToDevice);
+        hipMemcpy((char *)meta + (size_t)B * 8, ns.data(), (size_t)B * 4, hipMemcpyHostToDevice);
+        const int32_t *dns = (const int32_t *)((char *)meta + (size_t)B * 8);
+        if (dtype == APSP_INT32)
+            hipLaunchKernelGGL(tune_fill_kernel<int32_t>, dim3(std::min(B, 4096)), dim3(256), 0, s,
+                               (int32_t *)dist, (const int64_t *)meta, dns, B);
+        else
+            hipLaunchKernelGGL(tune_fill_kernel<float>, dim3(std::min(B, 4096)), dim3(256), 0, s,
+                               (float *)dist, (const int64_t *)meta, dns, B);
+    }
+    int8_t choice[kClasses];
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        std::memcpy(choice, g_tune[d][m], sizeof choice);
+    }
+    auto time_batch = [&](const int8_t *ch, double &ms_per) -> apsp_status_t {
+        std::vector<int8_t> forced(B);
+        for (int32_t b = 0; b < B; ++b) forced[b] = ch[cls[b]];
+        apsp_batch_plan_t *plan = nullptr;
+        apsp_status_t st =
+            apsp_batch_plan_create_ex(ns.data(), offs.data(), B, dtype, want_pred, forced.data(), &plan);
+        if (st != APSP_SUCCESS) return st;
+        st = apsp_batch_plan_execute(plan, dist, (int32_t *)pred, nullptr, s);  // warm-up
+        hipEventRecord(e0, s);
+        for (int r = 0; r < R && st == APSP_SUCCESS; ++r)
+            st = apsp_batch_plan_execute(plan, dist, (int32_t *)pred, nullptr, s);
+        hipEventRecord(e1, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            st = APSP_ERROR_HIP;
+        plan_free(plan);
+        ms_per = (double)ms / R;
+        return st;
+    };
+    // coordinate descent: one class at a time, the others at their current choice
+    for (int c = 0; c < kClasses && result == APSP_SUCCESS; ++c) {
+        double best_ms = 1e300;
+        int best = choice[c];
+        for (int cfg = kWaveTiles64; cfg <= kGroupTiles128 && result == APSP_SUCCESS; ++cfg) {
+            int8_t trial[kClasses];
+            std::memcpy(trial, choice, sizeof trial);
+            trial[c] = (int8_t)cfg;
+            double ms = 0.0;
+            result = time_batch(trial, ms);
+            if (ms_out) ms_out[c * 3 + cfg] = ms;
+            if (result == APSP_SUCCESS && ms < best_ms) {
+                best_ms = ms;
+                best = cfg;
+            }
+        }
+        choice[c] = (int8_t)best;
+    }
+    if (result == APSP_SUCCESS) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        std::memcpy(g_tune[d][m], choice, sizeof choice);
+    }
+    hipFree(dist);
+    hipFree(pred);
+    hipFree(meta);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamDestroy(s);
+    return result;
 }
 
 }  // extern "C"

@@ -266,7 +266,11 @@ void apsp_server::launch_group(std::vector<Request *> &batch) {
     const size_t dist_bytes = round_up((size_t)total * 4, 256);
     const size_t pred_bytes = g->want_pred ? dist_bytes : 0;
     const size_t status_bytes = round_up((size_t)B * 4, 256);
-    const size_t meta_bytes = round_up((size_t)B * 16, 256);
+    std::vector<char> meta_host;
+    int32_t n_team = 0;
+    int64_t need_scratch = 0;
+    batch_meta(ns.data(), offs.data(), B, g->dtype, g->want_pred, nullptr, meta_host, n_team, need_scratch);
+    const size_t meta_bytes = round_up(meta_host.size(), 256);
     g->pred_off_bytes = (int64_t)dist_bytes;
     g->status_off_bytes = (int64_t)(dist_bytes + pred_bytes);
     g->bytes = dist_bytes + pred_bytes + status_bytes + meta_bytes;
@@ -277,22 +281,17 @@ void apsp_server::launch_group(std::vector<Request *> &batch) {
         bytes_in_use -= (int64_t)(r->resident + r->transient);  // accounted by the group instead
         r->resident = r->transient = 0;
     }
-    std::vector<int32_t> order;
-    int32_t n_team = 0;
-    batch_order(ns.data(), B, order, n_team);
-    apsp_status_t st = APSP_SUCCESS;
+    apsp_status_t st = need_scratch > batch_scratch_elems ? APSP_ERROR_INVALID_ARGUMENT : APSP_SUCCESS;
     hipStream_t s = batch_stream;
-    if (hipHostMalloc(&g->h_meta, meta_bytes) != hipSuccess) st = APSP_ERROR_OUT_OF_MEMORY;
+    if (st == APSP_SUCCESS && hipHostMalloc(&g->h_meta, meta_bytes) != hipSuccess) st = APSP_ERROR_OUT_OF_MEMORY;
     if (st == APSP_SUCCESS) {
-        std::memcpy(g->h_meta, order.data(), (size_t)B * 4);
-        std::memcpy((char *)g->h_meta + (size_t)B * 4, ns.data(), (size_t)B * 4);
-        std::memcpy((char *)g->h_meta + (size_t)B * 8, offs.data(), (size_t)B * 8);
+        std::memcpy(g->h_meta, meta_host.data(), meta_host.size());
         if (hipMallocAsync(&g->d_arena, g->bytes, s) != hipSuccess) st = APSP_ERROR_OUT_OF_MEMORY;
     }
     char *arena = (char *)g->d_arena;
     const void *meta = arena + dist_bytes + pred_bytes + status_bytes;
     if (st == APSP_SUCCESS &&
-        hipMemcpyAsync((void *)meta, g->h_meta, (size_t)B * 16, hipMemcpyHostToDevice, s) != hipSuccess)
+        hipMemcpyAsync((void *)meta, g->h_meta, meta_host.size(), hipMemcpyHostToDevice, s) != hipSuccess)
         st = APSP_ERROR_HIP;
     for (int32_t b = 0; b < B && st == APSP_SUCCESS; ++b) {
         Request *r = batch[b];
@@ -409,7 +408,8 @@ apsp_status_t apsp_server_create(const apsp_server_config_t *config, apsp_server
         return APSP_ERROR_HIP;
     }
     if (cfg.batch_max_n > 0) {
-        const int64_t ldp = std::max<int64_t>(64, (cfg.batch_max_n + 63) / 64 * 64);
+        // work matrices of up to 128-padded batch_max_n (every team configuration fits)
+        const int64_t ldp = std::max<int64_t>(128, (cfg.batch_max_n + 127) / 128 * 128);
         sv->batch_grid = 2 * sv->cus;
         sv->batch_scratch_elems = ldp * ldp;
         const size_t bytes = (size_t)sv->batch_grid * sv->batch_scratch_elems * 8;

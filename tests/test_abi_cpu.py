@@ -103,3 +103,27 @@ def test_batch_plan_host_argument_errors():
     assert L.apsp_batch_plan_create(ns.ctypes.data, offs.ctypes.data, 2, 5, 0,
                                     ctypes.byref(plan)) == apsp.INVALID_ARGUMENT
     assert L.apsp_batch_plan_execute(None, None, None, None, None) == apsp.INVALID_ARGUMENT
+
+
+def test_tuning_table_roundtrip(tmp_path):
+    """The batched tuning table saves to JSON and loads back (host only)."""
+    p = tmp_path / "t.json"
+    apsp.tune_save(str(p))
+    text = p.read_text()
+    import json
+    doc = json.loads(text)
+    assert doc["classes"] == [128, 256, 384, 512, 1024]
+    assert set(doc["table"]) == {"int32", "float32"}
+    doc["table"]["float32"]["pred"] = [2, 1, 0, 2, 1]
+    p.write_text(json.dumps(doc))
+    apsp.tune_load(str(p))
+    assert [apsp.batch_config(n, "float32", True) for n in (100, 200, 300, 500, 900)] == [2, 1, 0, 2, 1]
+    assert apsp.batch_config(64, "int32") == -1
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"table": {"int32": {"dist": [0, 7, 0, 0, 0]}}}')
+    with pytest.raises(apsp.APSPError):
+        apsp.tune_load(str(bad))
+    with pytest.raises(apsp.APSPError):
+        apsp.tune_load(str(tmp_path / "missing.json"))
+    apsp.tune_load(str(p))  # a valid table stays in force after failed loads
+    assert apsp.batch_config(500, "float32", True) == 2

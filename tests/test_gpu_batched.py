@@ -160,3 +160,48 @@ def test_batched_full_workload_sampled(orc):
         o = int(bt.offsets[b])
         assert (D[o:o + n * n:n + 1] == 0).all()
     plan.destroy()
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("kind,pred", [("int", False), ("f32", True), ("pot", True), ("half", True)])
+def test_every_team_configuration_matches_oracle(orc, cfg, kind, pred):
+    """Each team configuration (tile size / register block) forced for every
+    graph gives the oracle's result."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe(f"batched cfg={cfg} kind={kind} pred={pred}")
+    sizes = [65, 100, 128, 129, 200, 256, 257, 300, 383, 512, 600, 1024, 30]
+    graphs = _graphs(kind, sizes, seed=500 + cfg)
+    dtype = np.int32 if kind in ("int", "pot") else np.float32
+    buf, ns, offs = _pack(graphs, dtype)
+    plan = apsp.BatchPlan(ns, offs, "int32" if dtype == np.int32 else "float32", want_pred=pred,
+                          team_config=cfg)
+    d = torch.from_numpy(buf.copy()).cuda()
+    p = torch.full(d.shape, -7, dtype=torch.int32, device="cuda") if pred else None
+    plan.execute(d, p)
+    torch.cuda.synchronize()
+    D = d.cpu().numpy()
+    P = p.cpu().numpy() if pred else None
+    for b, W in enumerate(graphs):
+        n = W.shape[0]
+        o = int(offs[b])
+        D0, P0, _ = orc.fw(W, pred=pred)
+        if dtype == np.float32:
+            D0 = D0.astype(np.float32)
+        assert first_mismatch(D[o:o + n * n].reshape(n, n), D0) is None, (cfg, n)
+        if pred:
+            assert first_mismatch(P[o:o + n * n].reshape(n, n), P0) is None, (cfg, n)
+    plan.destroy()
+
+
+def test_autotune_fills_table():
+    import paper_1811_01201_amd as apsp
+    describe("batched autotune")
+    rep = apsp.batch_autotune("int32", False, graphs_per_class=16, reps=1)
+    assert sorted(rep) == list(apsp.SIZE_CLASSES)
+    for hi, row in rep.items():
+        times = [row[c] for c in apsp.TEAM_CONFIGS]
+        assert all(t > 0 for t in times)
+        # coordinate descent: the kept choice is the fastest trial for its class
+        assert row["best"] == apsp.TEAM_CONFIGS[int(np.argmin(times))]
