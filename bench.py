@@ -181,35 +181,14 @@ def serving_leg(count: int):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=32768, help="override the graph size (quick runs)")
-    ap.add_argument("--block-size", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--skip-batched", action="store_true")
-    ap.add_argument("--skip-serving", action="store_true")
-    ap.add_argument("--batched-replays", type=int, default=10)
-    ap.add_argument("--serving-requests", type=int, default=400)
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures a single GPU: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def single_leg(args, n):
+    """Timed single-graph solves; returns (host weights, JSON fields)."""
     import torch
 
     import paper_1811_01201_amd as apsp
+    from paper_1811_01201_amd import profiling
     import synth
 
-    n = args.n
-    torch.cuda.set_device(0)
-    apsp.lib()  # fails loudly without the HIP library
     log(f"[bench] generating n={n} potential-weight graph")
     W = synth.potential_int32(n, p=0.1, seed=synth.BASE_SEED + 2)
     pristine = torch.from_numpy(W).cuda()
@@ -269,8 +248,65 @@ def main():
     phases = {k: {"launches": v["launches"], "ms_per_step": round(v["total_ms"] / args.steps, 3)}
               for k, v in prof.items() if v["launches"]}
 
+    traffic = None
+    bs = args.block_size or (256 if n > 4096 else 128)
+    tr = profiling.read_traffic_file(os.path.join(ROOT, "profiles", f"phase3_int32_n{n}_traffic.txt"))
+    if tr and tr.get("source_sha256") == profiling.kernel_source_hash() and not args.block_size:
+        traffic = int(float(tr["traffic_bytes_per_launch"]))
+        m = n - 2 * bs  # a launch of the remaining-block set under the two-stream schedule
+        algo = m * m * 8 + 2 * m * bs * 4
+        roofline["traffic_kernel"] = tr.get("kernel")
+        roofline["traffic_algorithmic_bytes"] = algo
+        roofline["traffic_vs_algorithmic"] = round(traffic / algo, 3)
+    roofline["traffic"] = traffic
     del work, pristine
     torch.cuda.empty_cache()
+    return W, {"value": round(gops, 2), "ms_per_step": round(ms_per_step, 3), "wall_s": round(wall, 3),
+               "roofline": roofline, "phases": phases}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768, help="override the graph size (quick runs)")
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-single", action="store_true", help="batched/serving legs only")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--batched-replays", type=int, default=10)
+    ap.add_argument("--serving-requests", type=int, default=400)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures a single GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1811_01201_amd as apsp
+
+    n = args.n
+    torch.cuda.set_device(0)
+    apsp.lib()  # fails loudly without the HIP library
+    out = {
+        "metric": "min-plus GOPS (2n^3/t) vs VALU peak at n=32768; batched solves/s + p99 latency",
+        "value": None, "unit": "GOPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {
+            "workload": f"single directed graph n={n}, edge prob 0.1, int32 weights b+pi(i)-pi(j) "
+                        f"(b uniform [1,1000], pi(v)=floor(100v/(n-1))), distances only",
+            "n": n, "block_size": args.block_size or "auto", "parallelism": "single GPU"},
+    }
+    W = None
+    if not args.skip_single:
+        W, single = single_leg(args, n)
+        out.update(single)
     batched = None
     if not args.skip_batched:
         log("[bench] batched leg")
@@ -281,39 +317,14 @@ def main():
         serving = serving_leg(args.serving_requests)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and W is not None:
         log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s budget)")
         cpu = cpu_baseline(W, args.cpu_seconds)
 
-    out = {
-        "metric": "min-plus GOPS (2n^3/t) vs VALU peak at n=32768; batched solves/s + p99 latency",
-        "value": round(gops, 2),
-        "unit": "GOPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "wall_s": round(wall, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"single directed graph n={n}, edge prob 0.1, int32 weights b+pi(i)-pi(j) "
-                        f"(b uniform [1,1000], pi(v)=floor(100v/(n-1))), distances only",
-            "n": n,
-            "block_size": args.block_size or "auto",
-            "parallelism": "single GPU",
-        },
-        "roofline": roofline,
-        "phases": phases,
-        "cpu_baseline": cpu,
-        "batched": batched,
-        "serving": serving,
-    }
+    out["cpu_baseline"] = cpu
+    out["batched"] = batched
+    out["serving"] = serving
     print(json.dumps(out), flush=True)
-    del np
 
 
 if __name__ == "__main__":

@@ -834,4 +834,20 @@ apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t
     return result;
 }
 
+apsp_status_t apsp_solve_batched(void *packed_dist, int32_t *packed_pred, const int32_t *ns,
+                                 const int64_t *offsets, int32_t batch, apsp_dtype_t dtype,
+                                 hipStream_t stream) {
+    sweep_retired(false);
+    apsp_batch_plan_t *plan = nullptr;
+    apsp_status_t st =
+        apsp_batch_plan_create(ns, offsets, batch, dtype, packed_pred != nullptr ? 1 : 0, &plan);
+    if (st != APSP_SUCCESS) return st;
+    st = apsp_batch_plan_execute(plan, packed_dist, packed_pred, nullptr, stream);
+    if (st != APSP_SUCCESS) {
+        plan_free(plan);
+        return st;
+    }
+    return retire(plan, stream);
+}
+
 }  // extern "C"
