@@ -136,6 +136,8 @@ def main(argv=None):
                 print(f"    {name:28s} {v:.6g}")
     else:
         res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes)
+        if a.out and len(res["kernels"]) != 1:
+            raise SystemExit(f"--kernel must select one kernel for --out, got {sorted(res['kernels'])}")
         lines = [f"# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE",
                  f"# command: {a.command}" if a.command else "# command: (not recorded)",
                  f"copy_kernel={res['copy_kernel']}", f"copy_bytes={a.copy_bytes:.0f}",
