@@ -73,6 +73,7 @@ void batch_meta(const int32_t *ns, const int64_t *offsets, int32_t B, apsp_dtype
 struct ArI32 {
     using T = int32_t;
     static constexpr int VW = 4;
+    static constexpr int kP1Rows256 = 16;  // 512 threads x 16 x 8 (8 x 8 spills at 1024 threads)
     static constexpr bool kStrip = false;  // strip() is the identity
     // clamp-saturating add: never wraps, even with negative cycles
     __device__ __forceinline__ T add(T a, T b) const { return __builtin_elementwise_add_sat(a, b); }
@@ -92,12 +93,27 @@ struct ArI32 {
     }
 };
 
+// Floating-point minima are written as the bare instruction: fmin() with
+// IEEE semantics makes the compiler quiet signalling NaNs first (one
+// v_max per loop-carried operand), and no operand here is ever NaN.
+__device__ __forceinline__ float vmin_f32(float a, float b) {
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double vmin_f64(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 struct ArF32 {
     using T = float;
     static constexpr int VW = 4;
+    static constexpr int kP1Rows256 = 8;  // 1024 threads x 8 x 8 (16 x 8 leaves the block in scratch)
     static constexpr bool kStrip = false;
     __device__ __forceinline__ T add(T a, T b) const { return a + b; }
-    __device__ __forceinline__ T mn(T a, T b) const { return __builtin_fminf(a, b); }
+    __device__ __forceinline__ T mn(T a, T b) const { return vmin_f32(a, b); }
     __device__ __forceinline__ T strip(T a) const { return a; }
     __device__ __forceinline__ T relax2(T c, T a0, T b0, T a1, T b1) const {
         const T s0 = a0 + b0, s1 = a1 + b1;
@@ -115,10 +131,11 @@ struct ArF32 {
 struct ArKey {
     using T = double;
     static constexpr int VW = 2;
+    static constexpr int kP1Rows256 = 16;  // unused: predecessor solves use BS <= 128
     static constexpr bool kStrip = true;
     int S;  // predecessor bits
     __device__ __forceinline__ T add(T a, T b) const { return a + b; }
-    __device__ __forceinline__ T mn(T a, T b) const { return __builtin_fmin(a, b); }
+    __device__ __forceinline__ T mn(T a, T b) const { return vmin_f64(a, b); }
     __device__ __forceinline__ T strip(T a) const {
         return __builtin_ldexp(__builtin_floor(__builtin_ldexp(a, -S)), S);
     }
@@ -144,6 +161,7 @@ constexpr int32_t kLexNone = 0x7fffffff;
 struct ArLexF32 {
     using T = DistPred;
     static constexpr int VW = 2;
+    static constexpr int kP1Rows256 = 16;  // unused: predecessor solves use BS <= 128
     static constexpr bool kStrip = false;
     __device__ __forceinline__ T add(T a, T b) const { return T{a.d + b.d, b.p}; }
     __device__ __forceinline__ T mn(T c, T s) const {
@@ -497,6 +515,7 @@ struct TileProduct {
 // otherwise), so the launch sequence does not depend on the data.
 struct NoAlt {
     using T = char;
+    static constexpr int kP1Rows256 = 16;
 };
 template <class Ar, class Alt>
 __device__ __forceinline__ bool use_alt(const int32_t *mode) {
@@ -512,17 +531,24 @@ __device__ __forceinline__ bool use_alt(const int32_t *mode) {
 // ty*TM1.., columns tx*TN1.. in registers.  Before step k the owners of
 // column k and row k publish them through LDS (double buffered by k parity,
 // so one barrier per step suffices).  TT = 8: 8 x 8 blocks (16 x 8 for
-// BS = 256); TT = 4: 4 x 4 blocks, 16x more threads per element for
-// latency-bound small solves.
-template <int BS, int TT = 8>
+// BS = 256 when the policy asks for it, see kP1Rows256); TT = 4: 4 x 4
+// blocks, 16x more threads per element for latency-bound small solves.
+template <int BS, int TT = 8, int ROWS256 = 16>
 struct P1Shape {
-    static constexpr int TM1 = (BS >= 256 && TT == 8) ? 16 : TT;
+    static constexpr int TM1 = (BS >= 256 && TT == 8) ? ROWS256 : TT;
     static constexpr int TN1 = TT;
     static constexpr int TX = BS / TN1, TY = BS / TM1, NTH = TX * TY;
+    // the one workgroup's waves spread over the CU's 4 SIMDs: asking for
+    // exactly that occupancy gives each wave the whole register budget
+    static constexpr int kWavesPerSimd = NTH / 256 > 0 ? NTH / 256 : 1;
 };
 
+// Shape used by policy Ar (rows per thread at BS = 256 are a per-type choice).
 template <class Ar, int BS, int TT>
-using P1Regs = typename Ar::T[P1Shape<BS, TT>::TM1][P1Shape<BS, TT>::TN1];
+using P1S = P1Shape<BS, TT, Ar::kP1Rows256>;
+
+template <class Ar, int BS, int TT>
+using P1Regs = typename Ar::T[P1S<Ar, BS, TT>::TM1][P1S<Ar, BS, TT>::TN1];
 
 // The k-steps of a diagonal-block closure on a register-resident block:
 // steps 0 <= k < ksteps (ksteps a multiple of 16, at most BS).
@@ -531,7 +557,7 @@ __device__ __forceinline__ void phase1_steps(P1Regs<Ar, BS, TT> &c, int ksteps, 
                                              typename Ar::T (*colbuf)[BS],
                                              typename Ar::T (*rowbuf)[BS]) {
     using T = typename Ar::T;
-    constexpr int TM1 = P1Shape<BS, TT>::TM1, TN1 = P1Shape<BS, TT>::TN1, TX = P1Shape<BS, TT>::TX;
+    constexpr int TM1 = P1S<Ar, BS, TT>::TM1, TN1 = P1S<Ar, BS, TT>::TN1, TX = P1S<Ar, BS, TT>::TX;
     constexpr int VW = Ar::VW;
     const int tid = tile_tid<WAVE>(), tx = tid % TX, ty = tid / TX;
     // 16 steps per iteration keep every register index static: the owner of
@@ -575,9 +601,9 @@ __device__ __forceinline__ void phase1_body(typename Ar::T *__restrict__ D, int6
                                             const Ar &ar, typename Ar::T (*colbuf)[BS],
                                             typename Ar::T (*rowbuf)[BS]) {
     using T = typename Ar::T;
-    constexpr int TM1 = P1Shape<BS, TT>::TM1, TN1 = P1Shape<BS, TT>::TN1, TX = P1Shape<BS, TT>::TX;
+    constexpr int TM1 = P1S<Ar, BS, TT>::TM1, TN1 = P1S<Ar, BS, TT>::TN1, TX = P1S<Ar, BS, TT>::TX;
     constexpr int VW = Ar::VW;
-    static_assert(!WAVE || P1Shape<BS, TT>::NTH == 64, "a wavefront closes 64 x 64 blocks");
+    static_assert(!WAVE || P1S<Ar, BS, TT>::NTH == 64, "a wavefront closes 64 x 64 blocks");
     static_assert(TM1 % VW == 0 && TN1 % VW == 0, "whole 16-byte pieces per thread");
     const int tid = tile_tid<WAVE>(), tx = tid % TX, ty = tid / TX;
     T *const base = D + r0 * ld + r0;

@@ -29,15 +29,21 @@
 #define P3_DMA 1
 #endif
 #ifndef P3_WAVES8
-#define P3_WAVES8 1
+#define P3_WAVES8 2
+#endif
+#ifndef P3_KEY_DMA
+#define P3_KEY_DMA 1
 #endif
 
 namespace apsp {
 
 template <class Ar, class Alt, int BS, int TT>
-__global__ void __launch_bounds__((P1Shape<BS, TT>::NTH))
+__global__ void __launch_bounds__((P1S<Ar, BS, TT>::NTH))
+__attribute__((amdgpu_waves_per_eu(P1S<Ar, BS, TT>::kWavesPerSimd, P1S<Ar, BS, TT>::kWavesPerSimd)))
 phase1_kernel(void *X, int64_t ld, int64_t r0, Ar ar, Alt alt, const int32_t *__restrict__ mode,
               const int32_t *__restrict__ skip) {
+    static_assert(std::is_same_v<Alt, NoAlt> || P1S<Ar, BS, TT>::NTH == P1S<Alt, BS, TT>::NTH,
+                  "both policies close the block with the same workgroup");
     if (skip && *skip != APSP_SUCCESS) return;
     constexpr int E = sizeof(typename Ar::T) > sizeof(typename Alt::T) ? sizeof(typename Ar::T)
                                                                         : sizeof(typename Alt::T);
@@ -197,7 +203,7 @@ phase3_kernel(void *X, int64_t ld, int r, int per_xcd, Ar ar, Alt alt,
               const int32_t *__restrict__ mode, const int32_t *__restrict__ skip) {
     constexpr int set = SET;
 #if P3_DMA
-    using TP = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, MT, MT, 16, TT, TT>,
+    using TP = std::conditional_t<sizeof(typename Ar::T) == 4 || P3_KEY_DMA, TileProductDMA<Ar, MT, MT, 16, TT, TT>,
                                   TileProduct<Ar, MT, MT, 16, TT, TT>>;
 #else
     using TP = TileProduct<Ar, MT, MT, (sizeof(typename Ar::T) == 4 ? P3_KC : 16), TT, TT>;
@@ -539,7 +545,7 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     }
     auto p1 = [&](int r) {
         ProfScope ps(kPhase1, bs3, s);
-        hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS, TT>), dim3(1), dim3(P1Shape<BS, TT>::NTH), 0, s, X,
+        hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS, TT>), dim3(1), dim3(P1S<Ar, BS, TT>::NTH), 0, s, X,
                            ld, (int64_t)r * BS, ar, alt, mode, skip);
     };
     auto p2 = [&](int r) {
