@@ -126,9 +126,17 @@ typedef struct {
                               second stream; 1 = one stream, rounds in order */
     int32_t use_graph;     /* nonzero: capture the launch sequence once per shape into a
                               hipGraph and replay it (fewer launch gaps for small n) */
-    int32_t reserved;      /* must be 0 */
+    int32_t arith;         /* int32 distance solves only (ignored otherwise): 0 = automatic
+                              (float32 arithmetic above n = 4096), 1 = int32 arithmetic,
+                              2 = float32 arithmetic at any n.  float32 arithmetic holds
+                              the integers exactly while every operand stays below 2^23 in
+                              magnitude, which the kernels check; if one does not, the
+                              device redoes the solve in int32 arithmetic.  Either way the
+                              result is the exact int32 result. */
     int32_t *d_status;     /* device int32 or NULL: receives APSP_SUCCESS,
                               APSP_ERROR_INVALID_VALUE or APSP_ERROR_NEGATIVE_CYCLE */
+    int32_t *d_arith;      /* device int32 or NULL: receives 1 if the result came from float32
+                              arithmetic, 0 if from int32 arithmetic */
 } apsp_options_t;
 
 /* apsp_solve with options (NULL options = defaults = apsp_solve). */
@@ -164,8 +172,9 @@ apsp_status_t apsp_profile_begin(void);
 apsp_status_t apsp_profile_end(apsp_profile_t *out);
 
 /* Measures the device's 32-bit VALU throughput (lane-instructions per
- * second) with the instruction mix of the min-plus kernels (clamp-saturating
- * add, three-input minimum), every CU busy; synchronises the device.  The
+ * second) with the instruction mix of the min-plus kernels (two plain adds
+ * and one three-input minimum per two relaxations, 8 independent
+ * accumulators per lane), every CU busy; synchronises the device.  The
  * benchmark reports kernel rates against this measured peak beside the
  * datasheet one (256 CUs x 64 lanes x 2.4 GHz). */
 apsp_status_t apsp_probe_valu(double *lane_instr_per_s, double *elapsed_ms);

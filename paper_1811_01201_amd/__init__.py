@@ -57,8 +57,8 @@ class Profile(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("thread_tile", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("d_status", ctypes.c_void_p)]
+                ("use_graph", ctypes.c_int32), ("arith", ctypes.c_int32),
+                ("d_status", ctypes.c_void_p), ("d_arith", ctypes.c_void_p)]
 
 
 _lib = None
@@ -152,7 +152,7 @@ def _dtype_code(t):
 
 
 def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, status=None,
-          stream=None, check=True, schedule=0, thread_tile=0) -> int:
+          stream=None, check=True, schedule=0, thread_tile=0, arith=0, arith_used=None) -> int:
     """Solve APSP in place on a square device tensor.
 
     dist   : torch.Tensor [n, n] int32/float32 on the GPU, contiguous (weights in,
@@ -160,6 +160,10 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
     pred   : optional torch.Tensor [n, n] int32 on the same device (output).
     status : optional torch.Tensor [1] int32 on the device, receives the
              data-dependent status (required with validate=True).
+    arith  : int32 distance solves: 0 automatic, 1 int32 arithmetic, 2 float32
+             arithmetic (exact, checked, int32 redo when needed).
+    arith_used : optional torch.Tensor [1] int32 on the device, receives 1 if the
+             result came from float32 arithmetic, else 0.
     Returns the host status of the enqueue (raises APSPError unless check=False).
     """
     assert dist.dim() == 2 and dist.shape[0] == dist.shape[1], "dist must be square"
@@ -171,8 +175,9 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
         assert pred.dtype == torch.int32 and pred.is_cuda and pred.is_contiguous()
         assert tuple(pred.shape) == (n, n)
         pp = pred.data_ptr()
-    opt = Options(int(validate), int(block_size), int(thread_tile), int(schedule), int(use_graph), 0,
-                  status.data_ptr() if status is not None else None)
+    opt = Options(int(validate), int(block_size), int(thread_tile), int(schedule), int(use_graph), int(arith),
+                  status.data_ptr() if status is not None else None,
+                  arith_used.data_ptr() if arith_used is not None else None)
     st = lib().apsp_solve_ex(dist.data_ptr(), pp, n, _dtype_code(dist), _stream_ptr(stream),
                              ctypes.byref(opt))
     if check and st != SUCCESS:

@@ -80,7 +80,7 @@ __device__ __forceinline__ bool from_work(const Ar &ar, typename Ar::T v, int64_
     Tin out;
     if constexpr (std::is_same_v<Ar, ArI32>) {
         out = v >= kFakeThreshold ? kInf32 : v;
-        neg = (i == j) && v < 0;
+        neg = ((i == j) && v < 0) || v < kWrapWitness;
     } else if constexpr (std::is_same_v<Ar, ArF32>) {
         out = v;
         neg = (i == j) && v < 0.0f;

@@ -17,6 +17,16 @@ constexpr int32_t kInf32 = APSP_INF_INT32;
 // reachable distances stay within +-2^28 (weight bound), while any sum that
 // involved the INF sentinel stays above INF - 2 * 2^28 > 2^29.
 constexpr int32_t kFakeThreshold = 1 << 29;
+// int32 sums are plain (wrapping) adds.  Under the weight bound no sum can
+// overflow: every stored value lies in [-2^28, INF] and every sum in
+// [-2^29, 2 INF].  Only a negative cycle drives values further down, and a
+// wrapped sum needs an operand below -2^30.  Stored values never increase
+// (each update is a minimum), and before any value drops below -2^29 the
+// padding rows and columns hold values >= 0, so the first such value, and
+// with it a witness below this bound, lands on a real (i, j) and stays
+// there: a result below kWrapWitness means a negative cycle, and so does a
+// negative diagonal when nothing wrapped.
+constexpr int32_t kWrapWitness = -(1 << 29);
 constexpr int kMaxN = 65536;
 
 // Largest |w| accepted for int32 weights (and for exact key arithmetic on
@@ -74,9 +84,11 @@ struct ArI32 {
     using T = int32_t;
     static constexpr int VW = 4;
     static constexpr int kP1Rows256 = 16;  // 512 threads x 16 x 8 (8 x 8 spills at 1024 threads)
+    static constexpr bool kWatch = false;
     static constexpr bool kStrip = false;  // strip() is the identity
-    // clamp-saturating add: never wraps, even with negative cycles
-    __device__ __forceinline__ T add(T a, T b) const { return __builtin_elementwise_add_sat(a, b); }
+    // plain add (v_add_u32 issues at twice the rate of the clamped form on
+    // gfx950); see kWrapWitness for why wrapping cannot go unnoticed
+    __device__ __forceinline__ T add(T a, T b) const { return (T)((uint32_t)a + (uint32_t)b); }
     __device__ __forceinline__ T mn(T a, T b) const { return a < b ? a : b; }
     __device__ __forceinline__ T strip(T a) const { return a; }
     __device__ __forceinline__ T relax2(T c, T a0, T b0, T a1, T b1) const {
@@ -111,6 +123,7 @@ struct ArF32 {
     using T = float;
     static constexpr int VW = 4;
     static constexpr int kP1Rows256 = 8;  // 1024 threads x 8 x 8 (16 x 8 leaves the block in scratch)
+    static constexpr bool kWatch = false;
     static constexpr bool kStrip = false;
     __device__ __forceinline__ T add(T a, T b) const { return a + b; }
     __device__ __forceinline__ T mn(T a, T b) const { return vmin_f32(a, b); }
@@ -128,10 +141,44 @@ struct ArF32 {
     }
 };
 
+// float32 arithmetic on integer-valued data: int32 weights converted to
+// float32 (INF -> +inf).  While every operand of an addition is an integer
+// of magnitude below 2^23, every sum is an integer below 2^24, exact in
+// float32, so the results are those of int32 arithmetic bit for bit.  The
+// operands of phase 3 are the outputs of phase 2, and those of phases 1 and
+// 2 are the values phase 1 publishes, phase 1's outputs and phase 2's
+// accumulator inputs: those kernels watch exactly these values (kWatch) and
+// set *big when one reaches 2^23; the solve then redoes the graph in int32
+// arithmetic.  Worth it because gfx950 issues v_add_f32 at twice the rate
+// of v_add_u32 in this instruction mix.
+struct ArF32W : ArF32 {
+    static constexpr bool kWatch = true;
+    int32_t *big;
+    __device__ __forceinline__ bool is_big(float v) const {
+        return v != __builtin_inff() && __builtin_fabsf(v) >= 8388608.0f;  // 2^23
+    }
+    __device__ __forceinline__ void raise() const { *big = 1; }
+};
+
+// Any value of a register block that would be unsafe as a later operand
+// (watching policies only; false otherwise).
+template <class Ar, int TM, int TN>
+__device__ __forceinline__ bool any_big(const Ar &ar, const typename Ar::T (&c)[TM][TN]) {
+    bool big = false;
+    if constexpr (Ar::kWatch) {
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+#pragma unroll
+            for (int n = 0; n < TN; ++n) big |= ar.is_big(c[m][n]);
+    }
+    return big;
+}
+
 struct ArKey {
     using T = double;
     static constexpr int VW = 2;
     static constexpr int kP1Rows256 = 16;  // unused: predecessor solves use BS <= 128
+    static constexpr bool kWatch = false;
     static constexpr bool kStrip = true;
     int S;  // predecessor bits
     __device__ __forceinline__ T add(T a, T b) const { return a + b; }
@@ -162,6 +209,7 @@ struct ArLexF32 {
     using T = DistPred;
     static constexpr int VW = 2;
     static constexpr int kP1Rows256 = 16;  // unused: predecessor solves use BS <= 128
+    static constexpr bool kWatch = false;
     static constexpr bool kStrip = false;
     __device__ __forceinline__ T add(T a, T b) const { return T{a.d + b.d, b.p}; }
     __device__ __forceinline__ T mn(T c, T s) const {
@@ -300,6 +348,8 @@ struct TileProductDMA {
         }
     }
 
+    // WATCH: check the tile's inputs and outputs with the policy (see ArF32W)
+    template <bool WATCH = false>
     __device__ __forceinline__ static void run(Smem &sm, T *__restrict__ D, int64_t ld64, int64_t crow,
                                                int64_t ccol, int64_t k0, int kcount, const Ar &ar) {
         const int tid = threadIdx.x;
@@ -315,6 +365,8 @@ struct TileProductDMA {
 #pragma unroll
             for (int g = 0; g < GN; ++g)
                 ld16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
+        bool big = false;
+        if constexpr (WATCH) big = any_big(ar, c);
         const int nch = kcount / KC;  // even: kcount is a multiple of 2 KC
         copy_chunk(sm.a0, sm.b0, Abase, Bbase, ld);
         copies_done(sm.a0, ar);
@@ -326,6 +378,9 @@ struct TileProductDMA {
                 copy_chunk(sm.a0, sm.b0, Abase + (ch + 2) * KC, Bbase + (uint32_t)((ch + 2) * KC) * ld, ld);
             compute(c, sm.a1, sm.b1, tx, ty, ar);
             if (ch + 2 < nch) copies_done(sm.a0, ar);
+        }
+        if constexpr (WATCH && Ar::kWatch) {
+            if (big || any_big(ar, c)) ar.raise();
         }
 #pragma unroll
         for (int m = 0; m < TM; ++m)
@@ -450,6 +505,7 @@ struct TileProduct {
         }
     }
 
+    template <bool WATCH = false>
     __device__ __forceinline__ static void run(Smem &sm, T *__restrict__ D, int64_t ld64, int64_t crow,
                                                int64_t ccol, int64_t k0, int kcount, const Ar &ar) {
         const int tid = tile_tid<WAVE>();
@@ -465,6 +521,8 @@ struct TileProduct {
 #pragma unroll
             for (int g = 0; g < GN; ++g)
                 ld16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
+        bool big = false;
+        if constexpr (WATCH) big = any_big(ar, c);
 
         T ra[PA][VW], rb[PB][VW];
         const int nch = kcount / KC;
@@ -500,6 +558,9 @@ struct TileProduct {
             if (more) store_chunk(sm, buf ^ 1, ar, ra, rb);
             tile_sync<WAVE>();
         }
+        if constexpr (WATCH && Ar::kWatch) {
+            if (big || any_big(ar, c)) ar.raise();
+        }
 #pragma unroll
         for (int m = 0; m < TM; ++m)
 #pragma unroll
@@ -516,6 +577,7 @@ struct TileProduct {
 struct NoAlt {
     using T = char;
     static constexpr int kP1Rows256 = 16;
+    static constexpr bool kWatch = false;
 };
 template <class Ar, class Alt>
 __device__ __forceinline__ bool use_alt(const int32_t *mode) {
@@ -552,11 +614,14 @@ using P1Regs = typename Ar::T[P1S<Ar, BS, TT>::TM1][P1S<Ar, BS, TT>::TN1];
 
 // The k-steps of a diagonal-block closure on a register-resident block:
 // steps 0 <= k < ksteps (ksteps a multiple of 16, at most BS).
+// Returns true if a watching policy (kWatch) saw a published value that is
+// unsafe as an operand; always false otherwise.
 template <class Ar, int BS, bool WAVE, int TT = 8>
-__device__ __forceinline__ void phase1_steps(P1Regs<Ar, BS, TT> &c, int ksteps, const Ar &ar,
+__device__ __forceinline__ bool phase1_steps(P1Regs<Ar, BS, TT> &c, int ksteps, const Ar &ar,
                                              typename Ar::T (*colbuf)[BS],
                                              typename Ar::T (*rowbuf)[BS]) {
     using T = typename Ar::T;
+    bool big = false;
     constexpr int TM1 = P1S<Ar, BS, TT>::TM1, TN1 = P1S<Ar, BS, TT>::TN1, TX = P1S<Ar, BS, TT>::TX;
     constexpr int VW = Ar::VW;
     const int tid = tile_tid<WAVE>(), tx = tid % TX, ty = tid / TX;
@@ -568,11 +633,18 @@ __device__ __forceinline__ void phase1_steps(P1Regs<Ar, BS, TT> &c, int ksteps, 
             const int buf = kk & 1;
             if (tx == kb * (16 / TN1) + kk / TN1) {
 #pragma unroll
-                for (int m = 0; m < TM1; ++m) colbuf[buf][ty * TM1 + m] = ar.strip(c[m][kk % TN1]);
+                for (int m = 0; m < TM1; ++m) {
+                    const T v = ar.strip(c[m][kk % TN1]);
+                    if constexpr (Ar::kWatch) big |= ar.is_big(v);
+                    colbuf[buf][ty * TM1 + m] = v;
+                }
             }
             if (ty == kb * (16 / TM1) + kk / TM1) {
 #pragma unroll
-                for (int n = 0; n < TN1; ++n) rowbuf[buf][tx * TN1 + n] = c[kk % TM1][n];
+                for (int n = 0; n < TN1; ++n) {
+                    if constexpr (Ar::kWatch) big |= ar.is_big(c[kk % TM1][n]);
+                    rowbuf[buf][tx * TN1 + n] = c[kk % TM1][n];
+                }
             }
             tile_sync<WAVE>();
             T a[TM1], b[TN1];
@@ -593,6 +665,7 @@ __device__ __forceinline__ void phase1_steps(P1Regs<Ar, BS, TT> &c, int ksteps, 
                 }
         }
     }
+    return big;
 }
 
 // Closes the BS x BS diagonal block at (r0, r0) of D in place.
@@ -614,7 +687,10 @@ __device__ __forceinline__ void phase1_body(typename Ar::T *__restrict__ D, int6
 #pragma unroll
         for (int g = 0; g < TN1 / VW; ++g)
             ld16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * TN1 + g * VW), &c[m][g * VW]);
-    phase1_steps<Ar, BS, WAVE, TT>(c, BS, ar, colbuf, rowbuf);
+    const bool big = phase1_steps<Ar, BS, WAVE, TT>(c, BS, ar, colbuf, rowbuf);
+    if constexpr (Ar::kWatch) {
+        if (big || any_big(ar, c)) ar.raise();
+    }
 #pragma unroll
     for (int m = 0; m < TM1; ++m)
 #pragma unroll

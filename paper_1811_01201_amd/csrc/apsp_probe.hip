@@ -1,45 +1,49 @@
 // VALU throughput probe: the denominator the benchmark compares the
 // phase-3 kernel against, measured on the device at its actual clock.
 //
-// Every thread runs `iters` iterations of a fixed block of 16 VALU
-// instructions (8 clamp-saturating adds and 8 three-input minima, the
-// instruction mix of the min-plus kernels) over 8 independent register
-// chains; the grid fills every CU with 8 wavefronts.  lane-instructions per
-// second = threads * iters * 16 / elapsed.
+// Every thread runs `iters` iterations of the phase-3 inner step on 8
+// independent accumulators: per accumulator two plain 32-bit adds of
+// operands that do not depend on it, then one three-input minimum,
+// c = min3(c, a0 + b0, a1 + b1), i.e. two (i,j,k) relaxations per three
+// instructions, exactly the instruction mix of the min-plus kernels.  The
+// grid fills every CU with 8 wavefronts.
+// relaxations per second = threads * iters * 16 / elapsed.
 #include <hip/hip_runtime.h>
 
 #include "apsp_internal.h"
 
 namespace apsp {
 
+#define APSP_PROBE_STEP(C, S0, S1)                 \
+    "v_add_u32_e32 " S0 ", %[a0], %[b0]\n\t"      \
+    "v_add_u32_e32 " S1 ", %[a1], %[b1]\n\t"      \
+    "v_min3_i32 " C ", " C ", " S0 ", " S1 "\n\t"
+
 __global__ void __launch_bounds__(256) valu_probe_kernel(int32_t *out, int iters, int32_t seed) {
-    int32_t a0 = seed + threadIdx.x, a1 = a0 + 1, a2 = a0 + 2, a3 = a0 + 3;
-    int32_t a4 = a0 + 4, a5 = a0 + 5, a6 = a0 + 6, a7 = a0 + 7;
-    const int32_t c = seed ^ 0x55;
+    int32_t c0 = seed + threadIdx.x, c1 = c0 + 1, c2 = c0 + 2, c3 = c0 + 3;
+    int32_t c4 = c0 + 4, c5 = c0 + 5, c6 = c0 + 6, c7 = c0 + 7;
+    int32_t a0 = seed ^ 0x55, a1 = seed ^ 0x33, b0 = seed + 7, b1 = seed - 9;
+    int32_t t0, t1, t2, t3, t4, t5, t6, t7, t8, t9, t10, t11, t12, t13, t14, t15;
     for (int i = 0; i < iters; ++i) {
-        asm volatile(
-            "v_add_i32 %0, %0, %8 clamp\n\t"
-            "v_add_i32 %1, %1, %8 clamp\n\t"
-            "v_add_i32 %2, %2, %8 clamp\n\t"
-            "v_add_i32 %3, %3, %8 clamp\n\t"
-            "v_add_i32 %4, %4, %8 clamp\n\t"
-            "v_add_i32 %5, %5, %8 clamp\n\t"
-            "v_add_i32 %6, %6, %8 clamp\n\t"
-            "v_add_i32 %7, %7, %8 clamp\n\t"
-            "v_min3_i32 %0, %0, %1, %8\n\t"
-            "v_min3_i32 %1, %1, %2, %8\n\t"
-            "v_min3_i32 %2, %2, %3, %8\n\t"
-            "v_min3_i32 %3, %3, %4, %8\n\t"
-            "v_min3_i32 %4, %4, %5, %8\n\t"
-            "v_min3_i32 %5, %5, %6, %8\n\t"
-            "v_min3_i32 %6, %6, %7, %8\n\t"
-            "v_min3_i32 %7, %7, %0, %8"
-            : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
-            : "v"(c));
+        asm volatile(APSP_PROBE_STEP("%[c0]", "%[t0]", "%[t1]") APSP_PROBE_STEP("%[c1]", "%[t2]", "%[t3]")
+                     APSP_PROBE_STEP("%[c2]", "%[t4]", "%[t5]") APSP_PROBE_STEP("%[c3]", "%[t6]", "%[t7]")
+                     APSP_PROBE_STEP("%[c4]", "%[t8]", "%[t9]") APSP_PROBE_STEP("%[c5]", "%[t10]", "%[t11]")
+                     APSP_PROBE_STEP("%[c6]", "%[t12]", "%[t13]")
+                     APSP_PROBE_STEP("%[c7]", "%[t14]", "%[t15]")
+                     : [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2), [c3] "+v"(c3), [c4] "+v"(c4),
+                       [c5] "+v"(c5), [c6] "+v"(c6), [c7] "+v"(c7), [t0] "=&v"(t0), [t1] "=&v"(t1),
+                       [t2] "=&v"(t2), [t3] "=&v"(t3), [t4] "=&v"(t4), [t5] "=&v"(t5), [t6] "=&v"(t6),
+                       [t7] "=&v"(t7), [t8] "=&v"(t8), [t9] "=&v"(t9), [t10] "=&v"(t10),
+                       [t11] "=&v"(t11), [t12] "=&v"(t12), [t13] "=&v"(t13), [t14] "=&v"(t14),
+                       [t15] "=&v"(t15)
+                     : [a0] "v"(a0), [a1] "v"(a1), [b0] "v"(b0), [b1] "v"(b1));
+        a0 += 1;  // keeps the adds' operands changing between iterations
     }
-    const int32_t r = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
+    const int32_t r = c0 ^ c1 ^ c2 ^ c3 ^ c4 ^ c5 ^ c6 ^ c7;
     if (r == 0x7fffffff) out[0] = r;  // keeps the chains live; practically never taken
 }
+
+#undef APSP_PROBE_STEP
 
 }  // namespace apsp
 
@@ -68,7 +72,7 @@ extern "C" apsp_status_t apsp_probe_valu(double *lane_instr_per_s, double *elaps
     hipEventDestroy(e1);
     hipFree(out);
     if (e != hipSuccess || ms <= 0.f) return APSP_ERROR_HIP;
-    *lane_instr_per_s = (double)blocks * threads * iters * 16.0 / (ms * 1e-3);
+    *lane_instr_per_s = (double)blocks * threads * iters * 24.0 / (ms * 1e-3);
     if (elapsed_ms) *elapsed_ms = ms;
     return APSP_SUCCESS;
 }

@@ -97,10 +97,11 @@ struct P2 {
         const int rb = (int)(r0 / P2W);
         const int tt = t + (t >= rb ? per_block : 0);  // skip the diagonal block's tiles
         const int64_t off = (int64_t)tt * P2W;
+        // the panels are phase 3's operands: a watching policy checks them
         if (is_row)
-            RowT::run(sm.row, D, ld, r0, off, r0, BS, ar);
+            RowT::template run<Ar::kWatch>(sm.row, D, ld, r0, off, r0, BS, ar);
         else
-            ColT::run(sm.col, D, ld, off, r0, r0, BS, ar);
+            ColT::template run<Ar::kWatch>(sm.col, D, ld, off, r0, r0, BS, ar);
     }
 };
 
@@ -283,7 +284,8 @@ __global__ void pad_in_kernel(const T *__restrict__ W, int64_t n, T *__restrict_
 
 // Distance-only wrap-up: map int32 sums that carried the sentinel back to
 // INF, copy to the caller's buffer when a padded work matrix was used, and
-// report a negative diagonal (negative cycle).
+// report a negative cycle (a negative diagonal, or an int32 value below
+// kWrapWitness).
 template <class T>
 __global__ void finalize_kernel(const T *__restrict__ X, int64_t ld, T *__restrict__ out, int64_t n,
                                 int32_t *__restrict__ status, const int32_t *__restrict__ skip) {
@@ -295,12 +297,82 @@ __global__ void finalize_kernel(const T *__restrict__ X, int64_t ld, T *__restri
         const int64_t i = e / n, j = e - i * n;
         T v = X[i * ld + j];
         if constexpr (std::is_same_v<T, int32_t>) {
+            if (v < kWrapWitness) neg = true;
             if (v >= kFakeThreshold) v = kInf32;
         }
         if (i == j && v < T(0)) neg = true;
         out[e] = v;
     }
     if (neg && status) *status = APSP_ERROR_NEGATIVE_CYCLE;
+}
+
+// int32 distance solves in float32 arithmetic (policy ArF32W).  words[0]:
+// set when a watched value reached 2^23 (the float32 result may then be
+// inexact and is discarded); words[1]: gate of the int32 pass that follows
+// (APSP_SUCCESS = run it, anything else = skip).
+__global__ void f32w_init_kernel(int32_t *words) {
+    words[0] = 0;
+    words[1] = 1;
+}
+
+// Converts the caller's int32 weights into the ld x ld float32 work matrix
+// (INF -> +inf, padding vertices isolated); weights of magnitude >= 2^23 set
+// words[0] right away.
+__global__ void f32w_in_kernel(const int32_t *__restrict__ W, int64_t n, float *__restrict__ X, int64_t ld,
+                               int32_t *__restrict__ words, const int32_t *__restrict__ skip) {
+    if (skip && *skip != APSP_SUCCESS) return;
+    const int64_t total = ld * ld;
+    bool big = false;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ld, j = e - i * ld;
+        float v;
+        if (i < n && j < n) {
+            const int32_t w = W[i * n + j];
+            if (w == kInf32) {
+                v = __builtin_inff();
+            } else {
+                v = (float)w;
+                big |= (w >= (1 << 23) || w <= -(1 << 23));
+            }
+        } else {
+            v = (i == j) ? 0.0f : __builtin_inff();
+        }
+        X[e] = v;
+    }
+    if (big) words[0] = 1;
+}
+
+// If no watcher fired, the float32 result is the exact int32 result:
+// write it back (+inf -> INF) and report a negative diagonal.
+__global__ void f32w_out_kernel(const float *__restrict__ X, int64_t ld, int32_t *__restrict__ out, int64_t n,
+                                int32_t *__restrict__ status, const int32_t *__restrict__ words,
+                                const int32_t *__restrict__ skip) {
+    if (skip && *skip != APSP_SUCCESS) return;
+    if (words[0]) return;
+    const int64_t total = n * n;
+    bool neg = false;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e - i * n;
+        const float v = X[i * ld + j];
+        if (i == j && v < 0.0f) neg = true;
+        out[e] = (v == __builtin_inff()) ? kInf32 : (int32_t)v;
+    }
+    if (neg && status) *status = APSP_ERROR_NEGATIVE_CYCLE;
+}
+
+// Opens the int32 pass when the float32 pass was not exact; reports the
+// arithmetic that produced the result (1 = float32, 0 = int32).
+__global__ void f32w_gate_kernel(int32_t *words, const int32_t *__restrict__ skip, int32_t *arith_used) {
+    const bool ok = !(skip && *skip != APSP_SUCCESS);
+    const bool redo = ok && words[0] != 0;
+    words[1] = redo ? APSP_SUCCESS : 1;
+    if (arith_used) *arith_used = (ok && !redo) ? 1 : 0;
+}
+
+__global__ void store_word_kernel(int32_t *p, int32_t v) {
+    if (p) *p = v;
 }
 
 // Predecessor solves.  mode == nullptr or *mode == 0: key mode,
@@ -465,7 +537,7 @@ struct ProfScope {
     ProfScope(int kind, double updates, hipStream_t stream) : s(stream) {
         {
             std::lock_guard<std::mutex> lk(g_prof_mu);
-            on = g_prof_on && !t_capturing;
+            on = g_prof_on && !t_capturing && kind >= 0;
         }
         if (!on) return;
         rec.kind = kind;
@@ -534,7 +606,7 @@ apsp_status_t aux_stream(int dev, hipStream_t s, AuxStream **out) {
 // in (2 measured best: about 1.4 % at n = 32768, 6 % at n = 16384).
 template <class Ar, class Alt, int BS, int TT>
 apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, const int32_t *mode,
-                         hipStream_t s, const int32_t *skip, bool lookahead) {
+                         hipStream_t s, const int32_t *skip, bool lookahead, bool prof) {
     constexpr int MT = BS >= 128 ? 128 : 64;
     constexpr int P2W = 64;
     const int R = (int)(ld / BS);
@@ -550,13 +622,13 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
         if (st != APSP_SUCCESS) return st;
     }
     auto p1 = [&](int r) {
-        ProfScope ps(kPhase1, bs3, s);
+        ProfScope ps(prof ? kPhase1 : -1, bs3, s);
         hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS, TT>), dim3(1), dim3(P1S<Ar, BS, TT>::NTH), 0, s, X,
                            ld, (int64_t)r * BS, ar, alt, mode, skip);
     };
     auto p2 = [&](int r) {
         if (nt2 <= 0) return;
-        ProfScope ps(kPhase2, 2.0 * bs3 * (ld / BS - 1), s);
+        ProfScope ps(prof ? kPhase2 : -1, 2.0 * bs3 * (ld / BS - 1), s);
         hipLaunchKernelGGL((phase2_kernel<Ar, Alt, BS, P2W, TT>), dim3(2 * nt2),
                            dim3((BS / TT) * (P2W / TT)), 0, s, X, ld, (int64_t)r * BS, nt2, ar, alt, mode,
                            skip);
@@ -565,7 +637,7 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
         const int64_t tiles = seq_end - seq0;
         if (tiles <= 0) return;
         const int per_xcd = (int)((tiles + 7) / 8);
-        ProfScope ps(set == kCross ? kPhase3Cross : kPhase3, (double)tiles * MT * MT * BS, st);
+        ProfScope ps(!prof ? -1 : set == kCross ? kPhase3Cross : kPhase3, (double)tiles * MT * MT * BS, st);
         const dim3 grid(8 * per_xcd), block((MT / TT) * (MT / TT));
         const int a = (int)seq0, b = (int)seq_end;
         if (set == kAll)
@@ -618,17 +690,17 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
 template <class Ar, class Alt = NoAlt>
 apsp_status_t run_rounds_bs(int bs, int tt, bool lookahead, void *X, int64_t ld, const Ar &ar,
                             hipStream_t s, const int32_t *skip, const Alt &alt = Alt{},
-                            const int32_t *mode = nullptr) {
+                            const int32_t *mode = nullptr, bool prof = true) {
     if (tt == 4) {
-        if (bs == 64) return run_rounds<Ar, Alt, 64, 4>(X, ld, ar, alt, mode, s, skip, lookahead);
+        if (bs == 64) return run_rounds<Ar, Alt, 64, 4>(X, ld, ar, alt, mode, s, skip, lookahead, prof);
         return APSP_ERROR_INVALID_ARGUMENT;
     }
     switch (bs) {
-        case 64: return run_rounds<Ar, Alt, 64, 8>(X, ld, ar, alt, mode, s, skip, lookahead);
-        case 128: return run_rounds<Ar, Alt, 128, 8>(X, ld, ar, alt, mode, s, skip, lookahead);
+        case 64: return run_rounds<Ar, Alt, 64, 8>(X, ld, ar, alt, mode, s, skip, lookahead, prof);
+        case 128: return run_rounds<Ar, Alt, 128, 8>(X, ld, ar, alt, mode, s, skip, lookahead, prof);
         case 256:
             if constexpr (sizeof(typename Ar::T) == 4)
-                return run_rounds<Ar, Alt, 256, 8>(X, ld, ar, alt, mode, s, skip, lookahead);
+                return run_rounds<Ar, Alt, 256, 8>(X, ld, ar, alt, mode, s, skip, lookahead, prof);
             return APSP_ERROR_INVALID_ARGUMENT;
         default: return APSP_ERROR_INVALID_ARGUMENT;
     }
@@ -642,10 +714,19 @@ int auto_block(int64_t n, bool pred) {
 
 int auto_tile(int64_t n, int bs) { return (bs == 64 && n <= 4096) ? 4 : 8; }
 
+// int32 distance solves run in float32 arithmetic (exact while watched,
+// else redone in int32) when asked to, or automatically above n = 4096,
+// where phase 3 dominates and the skipped int32 launches cost little.
+bool use_f32w(int64_t n, apsp_dtype_t dtype, bool with_pred, int arith) {
+    if (dtype != APSP_INT32 || with_pred || arith == 1) return false;
+    return arith == 2 || n > 4096;
+}
+
 // Work memory a solve needs beyond dist/pred (0 when it runs in place).
-size_t work_bytes(int64_t n, bool with_pred, int bs, bool aligned) {
+size_t work_bytes(int64_t n, bool with_pred, int bs, bool aligned, bool f32w) {
     const int64_t ld = (n + bs - 1) / bs * bs;
     if (with_pred) return (size_t)(ld * ld) * 8 + 256;
+    if (f32w) return (size_t)(ld * ld) * 4 + 256;
     if (ld == n && aligned) return 0;
     return (size_t)(ld * ld) * 4;
 }
@@ -680,6 +761,43 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         skip = status;
     }
     constexpr T inf = std::is_same_v<T, int32_t> ? T(kInf32) : T(__builtin_huge_valf());
+    const bool f32w = std::is_same_v<T, int32_t> && use_f32w(n, APSP_INT32, with_pred, opt.arith);
+    if (!f32w && opt.d_arith) hipLaunchKernelGGL(store_word_kernel, dim3(1), dim3(1), 0, s, opt.d_arith, 0);
+    if constexpr (std::is_same_v<T, int32_t>) {
+        if (f32w) {
+            // float32 pass (exact while watched), then an int32 pass that the
+            // device runs only if a watcher fired; both use one work buffer
+            const size_t mat = (size_t)(ld * ld) * 4;
+            void *w = nullptr;
+            apsp_status_t st = workspace(dev, s, mat + 256, &w);
+            if (st != APSP_SUCCESS) return st;
+            float *Xf = (float *)w;
+            int32_t *words = (int32_t *)((char *)w + mat);
+            hipLaunchKernelGGL(f32w_init_kernel, dim3(1), dim3(1), 0, s, words);
+            hipLaunchKernelGGL(f32w_in_kernel, dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n, Xf, ld, words,
+                               skip);
+            ArF32W arw;
+            arw.big = words;
+            st = run_rounds_bs<ArF32W>(bs, tt, lookahead, Xf, ld, arw, s, skip);
+            if (st != APSP_SUCCESS) return st;
+            hipLaunchKernelGGL(f32w_out_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, Xf, ld, dist, n, status,
+                               words, skip);
+            hipLaunchKernelGGL(f32w_gate_kernel, dim3(1), dim3(1), 0, s, words, skip, opt.d_arith);
+            const int32_t *gate = words + 1;
+            int32_t *Xi = dist;
+            if (!((ld == n) && ((uintptr_t)dist % 16 == 0))) {
+                Xi = (int32_t *)w;  // the float32 matrix is no longer needed
+                hipLaunchKernelGGL((pad_in_kernel<int32_t>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n,
+                                   Xi, ld, kInf32, gate);
+            }
+            st = run_rounds_bs<ArI32>(bs, tt, lookahead, Xi, ld, ArI32{}, s, gate, NoAlt{}, nullptr, false);
+            if (st != APSP_SUCCESS) return st;
+            hipLaunchKernelGGL((finalize_kernel<int32_t>), dim3(grid_for(n * n)), dim3(256), 0, s, Xi, ld, dist,
+                               n, status, gate);
+            APSP_HIP(hipGetLastError());
+            return APSP_SUCCESS;
+        }
+    }
     if (!with_pred) {
         T *X = dist;
         const bool inplace = (ld == n) && ((uintptr_t)dist % 16 == 0);
@@ -729,8 +847,8 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
 
 }  // namespace
 
-size_t solve_work_bytes(int64_t n, apsp_dtype_t, bool with_pred) {
-    return work_bytes(n, with_pred, auto_block(n, with_pred), true);
+size_t solve_work_bytes(int64_t n, apsp_dtype_t dtype, bool with_pred) {
+    return work_bytes(n, with_pred, auto_block(n, with_pred), true, use_f32w(n, dtype, with_pred, 0));
 }
 
 namespace {
@@ -748,12 +866,12 @@ struct GraphKey {
     int dev;
     hipStream_t s;
     int64_t n;
-    int dtype, validate, bs, tt, schedule;
-    void *dist, *pred, *status, *ws;
+    int dtype, validate, bs, tt, schedule, arith;
+    void *dist, *pred, *status, *ws, *arith_used;
     bool operator<(const GraphKey &o) const {
-        return std::tie(dev, s, n, dtype, validate, bs, tt, schedule, dist, pred, status, ws) <
-               std::tie(o.dev, o.s, o.n, o.dtype, o.validate, o.bs, o.tt, o.schedule, o.dist, o.pred,
-                        o.status, o.ws);
+        return std::tie(dev, s, n, dtype, validate, bs, tt, schedule, arith, dist, pred, status, ws,
+                        arith_used) < std::tie(o.dev, o.s, o.n, o.dtype, o.validate, o.bs, o.tt, o.schedule,
+                                               o.arith, o.dist, o.pred, o.status, o.ws, o.arith_used);
     }
 };
 std::mutex g_graph_mu;
@@ -780,7 +898,8 @@ apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dty
     const int tt = opt.thread_tile ? opt.thread_tile : auto_tile(n, bs);
     // the work memory must exist (at its final address) before recording
     void *w = ws;
-    const size_t need = work_bytes(n, with_pred, bs, ((uintptr_t)dist % 16) == 0);
+    const size_t need = work_bytes(n, with_pred, bs, ((uintptr_t)dist % 16) == 0,
+                                   use_f32w(n, dtype, with_pred, opt.arith));
     if (!w && need > 0) {
         apsp_status_t st = cached_workspace(dev, s, need, &w);
         if (st != APSP_SUCCESS) return st;
@@ -790,8 +909,8 @@ apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dty
         apsp_status_t st = aux_stream(dev, s, &aux);
         if (st != APSP_SUCCESS) return st;
     }
-    GraphKey key{dev,        s,   n,    (int)dtype, opt.validate, bs, tt, opt.schedule, dist, pred,
-                 opt.d_status, w};
+    GraphKey key{dev,  s,    n,    (int)dtype,   opt.validate, bs, tt, opt.schedule, opt.arith,
+                 dist, pred, opt.d_status, w, opt.d_arith};
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
@@ -874,7 +993,7 @@ apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t d
     if (opt.thread_tile == 4 && opt.block_size != 0 && opt.block_size != 64) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.block_size == 256 && pred) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.reserved != 0) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.arith < 0 || opt.arith > 2) return APSP_ERROR_INVALID_ARGUMENT;
     if (n == 0) return APSP_SUCCESS;
     if (!dist || ((uintptr_t)dist % 4) != 0 || ((uintptr_t)pred % 4) != 0)
         return APSP_ERROR_INVALID_ARGUMENT;

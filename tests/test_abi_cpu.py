@@ -57,6 +57,8 @@ def test_host_side_argument_errors():
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_tile) == apsp.INVALID_ARGUMENT
     tile4_bs128 = apsp.Options(0, 128, 4, 0, 0, 0, None)
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, tile4_bs128) == apsp.INVALID_ARGUMENT
+    bad_arith = apsp.Options(0, 0, 0, 0, 0, 3, None)
+    assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_arith) == apsp.INVALID_ARGUMENT
     assert L.apsp_status_string(3) == b"negative cycle"
     assert L.apsp_version() >= 100
 

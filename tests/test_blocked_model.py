@@ -6,8 +6,10 @@ The GPU library reaches the oracle's result in a different order:
 * phase 2 written as a min-plus product against the already closed
   diagonal block instead of an in-place k-sequential sweep;
 * phase 3 as a min-plus product of the column and row panels;
-* int32 sums formed by plain wrapping-free addition, with every value that
-  ends at or above 2^29 mapped back to INF afterwards.
+* int32 sums formed by plain addition, with every value that ends at or
+  above 2^29 mapped back to INF afterwards; in 32-bit wrapping arithmetic
+  a negative cycle is still reported (a negative diagonal, or a value below
+  -2^29, without which no sum can wrap).
 
 These tests check, on small graphs, that each of those choices gives
 exactly the oracle's distances and canonical predecessors, for many block
@@ -141,3 +143,86 @@ def test_plain_add_threshold_large_potential(orc):
     D, _ = blocked(W, 32, rng, saturating=False)
     assert np.array_equal(D, D0)
     assert (D0 == INF32).any()
+
+
+def blocked_wrapping(W, bs, rng):
+    """Distances-only blocked schedule in wrapping int32 arithmetic on a
+    matrix padded to a multiple of bs with isolated vertices, as the GPU
+    runs it.  Returns (D padded, negative-cycle flag as the GPU's wrap-up
+    computes it, whether any sum wrapped)."""
+    n = W.shape[0]
+    ld = (n + bs - 1) // bs * bs
+    D = np.full((ld, ld), INF32, dtype=np.int32)
+    np.fill_diagonal(D, 0)
+    D[:n, :n] = W
+    wrapped = False
+
+    def upd(C, A, B):
+        nonlocal wrapped
+        for k in range(A.shape[1]):
+            with np.errstate(over="ignore"):
+                S = A[:, k:k + 1] + B[k:k + 1, :]          # int32, wraps
+            exact = A[:, k:k + 1].astype(np.int64) + B[k:k + 1, :].astype(np.int64)
+            wrapped |= bool((S.astype(np.int64) != exact).any())
+            np.minimum(C, S, out=C)
+
+    R = ld // bs
+    blk = [slice(r * bs, (r + 1) * bs) for r in range(R)]
+    for r in range(R):
+        K = blk[r]
+        for k in range(bs):  # phase 1, k sequential
+            kk = K.start + k
+            upd(D[K, K], D[K, kk:kk + 1].copy(), D[kk:kk + 1, K].copy())
+        others = [q for q in range(R) if q != r]
+        rng.shuffle(others)
+        for q in others:
+            J = blk[q]
+            upd(D[K, J], D[K, K], D[K, J].copy())
+            upd(D[J, K], D[J, K].copy(), D[K, K])
+        for a in others:
+            for b in others:
+                upd(D[blk[a], blk[b]], D[blk[a], K], D[K, blk[b]])
+    real = D[:n, :n]
+    neg = bool((np.diag(real) < 0).any() or (real < -(1 << 29)).any())
+    return D, neg, wrapped
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_wrapping_adds_detect_every_negative_cycle(orc, seed):
+    """Plain wrapping int32 adds: within the weight bound every result equals
+    the oracle; with negative cycles (also ones deep enough to wrap) the
+    wrap-up still reports them: a negative diagonal, or a value below
+    -2^29, which a wrap cannot happen without."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 40))
+    bs = int(rng.integers(2, 9))
+    bound = (2 ** 28 - 1) // (n - 1)
+    kind = seed % 3
+    if kind == 0:    # within the bound, negative weights, no negative cycle
+        W = synth.potential_int32(n, p=0.3, seed=seed)
+    elif kind == 1:  # one shallow negative cycle
+        W = pins.random_graph(rng, n, 0.3, 1, 50)
+        W[0, 1], W[1, 0] = 3, -4
+    else:            # dense weights at the bound, many deep negative cycles
+        W = rng.integers(-bound, bound + 1, size=(n, n)).astype(np.int32)
+        np.fill_diagonal(W, 0)
+    D0, _, st = orc.fw(W)
+    D, neg, wrapped = blocked_wrapping(W, bs, rng)
+    assert neg == (st == oracle.NEGATIVE_CYCLE)
+    if st == oracle.OK:
+        out = np.where(D[:n, :n] >= (1 << 29), INF32, D[:n, :n])
+        assert np.array_equal(out, D0)
+        assert not wrapped
+    if kind == 2:
+        assert neg
+
+
+def test_wrapping_model_does_wrap():
+    """The deep negative-cycle case above really exercises wrapping."""
+    rng = np.random.default_rng(3)
+    n, bs = 32, 4
+    bound = (2 ** 28 - 1) // (n - 1)
+    W = np.full((n, n), -bound, dtype=np.int32)
+    np.fill_diagonal(W, 0)
+    _, neg, wrapped = blocked_wrapping(W, bs, rng)
+    assert wrapped and neg

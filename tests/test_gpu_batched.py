@@ -106,6 +106,19 @@ def test_batched_replay_and_negative_cycle_status(orc):
         assert np.array_equal(D[o:o + n * n].reshape(n, n), D0)
 
 
+def test_batched_deep_negative_cycle_reported():
+    """Negative cycles deep enough to wrap 32-bit sums, next to normal graphs."""
+    describe("batched deep negative cycle")
+    graphs = _graphs("int", [40, 300, 90, 500], seed=9)
+    for b in (0, 1, 3):
+        n = graphs[b].shape[0]
+        W = np.full((n, n), -((2 ** 28 - 1) // (n - 1)), dtype=np.int32)
+        np.fill_diagonal(W, 0)
+        graphs[b] = W
+    outs, ns, offs = _run(graphs, np.int32, False)
+    assert list(outs[0][2]) == [3, 3, 0, 3]
+
+
 def test_batched_equals_single_and_one_shot():
     import torch
 

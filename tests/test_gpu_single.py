@@ -135,6 +135,103 @@ def test_negative_cycle_reported(orc, pred, dtype):
     assert st == 3
 
 
+def _deep_negative(n):
+    """Every off-diagonal weight at minus the bound: negative cycles deep
+    enough that plain 32-bit sums wrap long before the solve ends."""
+    W = np.full((n, n), -synth_weight_bound(n), dtype=np.int32)
+    np.fill_diagonal(W, 0)
+    return W
+
+
+def synth_weight_bound(n):
+    return (2 ** 28 - 1) // (n - 1)
+
+
+@pytest.mark.parametrize("n,bs,tt", [(300, 64, 4), (300, 64, 8), (300, 128, 8), (520, 256, 8), (4096, 0, 0)])
+def test_deep_negative_cycle_with_wrapping_sums_reported(n, bs, tt):
+    describe(f"single deep negative cycle n={n} bs={bs} tt={tt}")
+    W = _deep_negative(n)
+    _, _, st = gpu_solve(W, block_size=bs, thread_tile=tt)
+    assert st == 3
+
+
+def _solve_arith(W, arith, **kw):
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    d = torch.from_numpy(np.ascontiguousarray(W)).cuda()
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    used = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    apsp.solve(d, status=st, arith=arith, arith_used=used, **kw)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), int(st.item()), int(used.item())
+
+
+@pytest.mark.parametrize("n,bs,tt", [(1, 0, 0), (63, 64, 4), (200, 64, 8), (257, 128, 8), (600, 256, 8),
+                                     (1000, 0, 0), (5000, 0, 0)])
+@pytest.mark.parametrize("kind", ["int", "sparse", "pot"])
+def test_float32_arithmetic_exact_for_int32(orc, n, bs, tt, kind):
+    """int32 distances computed in float32 arithmetic: bit-exact, and the
+    device reports that the float32 result was used."""
+    describe(f"single f32 arithmetic n={n} bs={bs} tt={tt} {kind}")
+    W = _graph(kind, n, seed=n + 17)
+    D, st, used = _solve_arith(W, 2, block_size=bs, thread_tile=tt)
+    assert st == 0 and used == 1
+    if n <= 1000:
+        D0, _, _ = orc.fw(W)
+        assert first_mismatch(D, D0) is None
+    else:
+        for src in (0, n // 2, n - 1):
+            dr, _, s = orc.row(W, src)
+            assert s == 0 and np.array_equal(D[src], dr)
+    D1, _, used1 = _solve_arith(W, 1, block_size=bs, thread_tile=tt)
+    assert used1 == 0 and np.array_equal(D, D1)
+
+
+@pytest.mark.parametrize("case", ["big_weights", "long_paths", "big_negative"])
+@pytest.mark.parametrize("n,bs", [(20, 64), (150, 64), (700, 256)])
+def test_float32_arithmetic_falls_back_to_int32(orc, case, n, bs):
+    """Operands that reach 2^23 make the device redo the solve in int32:
+    still exact, and reported as int32 arithmetic."""
+    describe(f"single f32 fallback {case} n={n} bs={bs}")
+    rng = np.random.default_rng(n)
+    bound = (2 ** 28 - 1) // (n - 1)
+    if case == "big_weights":      # some single weights above 2^23 (only possible for small n)
+        lo = min(bound, 2 ** 23 + 5)
+        W = pins.random_graph(rng, n, 0.3, max(1, lo - 1000), max(lo, bound))
+    elif case == "long_paths":     # weights below 2^23, path lengths above it
+        W = pins.random_graph(rng, n, 0.05, max(1, bound // 2), bound)
+    else:                          # negative weights below -2^22, no negative cycle (potentials)
+        pot = (np.arange(n, dtype=np.int64) * (bound // 3) // max(1, n - 1))
+        B = pins.random_graph(rng, n, 0.2, 1, max(2, bound // 3))
+        fin = B != INF32
+        W = np.where(fin, B + pot[:, None] - pot[None, :], INF32)
+        np.fill_diagonal(W, 0)
+        W = W.astype(np.int32)
+    D0, _, st0 = orc.fw(W)
+    assert st0 == oracle.OK
+    D, st, used = _solve_arith(W, 2, block_size=bs)
+    assert st == 0
+    assert first_mismatch(D, D0) is None
+    if case == "big_weights" and (np.abs(W[W != INF32]) >= 2 ** 23).any():
+        assert used == 0
+
+
+@pytest.mark.parametrize("deep", [False, True])
+def test_float32_arithmetic_negative_cycle(deep):
+    describe(f"single f32 arithmetic negative cycle deep={deep}")
+    n = 600
+    if deep:
+        W = _deep_negative(n)
+    else:
+        W = synth.single_int32(n, p=0.05, seed=12)
+        W[10, 150], W[150, 10] = 5, -9
+    _, st, used = _solve_arith(W, 2, block_size=256)
+    assert st == 3
+    if deep:
+        assert used == 0
+
+
 def test_pred_chains_reproduce_distances():
     describe("single pred chains n=333")
     n = 333
@@ -175,9 +272,11 @@ def test_full_size_n32768_potential_sampled_rows(orc):
     W = synth.potential_int32(n, p=0.1, seed=synth.BASE_SEED + 2)
     d = torch.from_numpy(W).cuda()
     st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
-    apsp.solve(d, status=st)
+    used = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    apsp.solve(d, status=st, arith_used=used)
     torch.cuda.synchronize()
     assert int(st.item()) == 0
+    assert int(used.item()) == 1  # the float32 arithmetic held (exact)
     for src in [0, 12345, n - 1]:
         dr, _, s = orc.row(W, src)
         assert s == 0
