@@ -25,13 +25,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.32e12 32-bit VALU lane-cycles/s.
-# Two k-steps of one element are two plain 32-bit adds and one three-input
-# minimum; the adds issue at twice the rate of the minimum on gfx950
-# (measured: v_add_u32 / v_add_f32 ~1.5-1.7x, v_min3 1x), so one relaxation
-# costs one lane-cycle: 2 metric ops per lane-cycle.
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.32e12 lane-cycles/s; the
+# datasheet's 157.3 TFLOP/s float32 vector rate (an FMA counts 2 flops) is
+# 78.6e12 float32 VALU lane-instructions/s, two per lane-cycle.  Two k-steps
+# of one element take 3 instructions (2 float32 adds + 1 three-input
+# minimum): 1.5 instructions per (i,j,k) relaxation, 2 metric ops each.
 VALU_LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
-PEAK_OPS = VALU_LANE_CYCLES_PER_S * 2.0               # 78.6e12 min-plus ops/s
+F32_VALU_INSTR_PER_S = 157.3e12 / 2.0
+PEAK_OPS = F32_VALU_INSTR_PER_S / 1.5 * 2.0            # 104.9e12 min-plus ops/s
 PEAK_ADD_MIN = VALU_LANE_CYCLES_PER_S                  # 39.3e12 (add + min at one instruction per cycle)
 
 
@@ -197,9 +198,11 @@ def single_leg(args, n):
     work = torch.empty_like(pristine)
     torch.cuda.synchronize()
 
+    arith_used = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+
     def step():
         work.copy_(pristine)
-        apsp.solve(work, block_size=args.block_size)
+        apsp.solve(work, block_size=args.block_size, arith=args.arith, arith_used=arith_used)
 
     for i in range(args.warmup):
         log(f"[bench] warmup {i + 1}/{args.warmup}")
@@ -243,7 +246,7 @@ def single_leg(args, n):
         "traffic": None,
     }
     probe = apsp.probe_valu()
-    # the probe runs the kernel's own instruction mix (3 instructions per 2 relaxations)
+    # the probe runs the kernel's own instruction mix (3 float32 instructions per 2 relaxations)
     measured_peak = probe["lane_instr_per_s"] * 2.0 / 1.5
     roofline["peak_measured"] = round(measured_peak / 1e12, 3)
     roofline["frac_vs_measured_peak"] = round(achieved * 1e12 / measured_peak, 4)
@@ -261,9 +264,12 @@ def single_leg(args, n):
         roofline["traffic_algorithmic_bytes"] = algo
         roofline["traffic_vs_algorithmic"] = round(traffic / algo, 3)
     roofline["traffic"] = traffic
+    roofline["arithmetic"] = ("float32 on integer values: exact, every operand below 2^23 checked on the device"
+                              if int(arith_used.item()) == 1 else "int32")
     del work, pristine
     torch.cuda.empty_cache()
     return W, {"value": round(gops, 2), "ms_per_step": round(ms_per_step, 3), "wall_s": round(wall, 3),
+               "dtype": "f32" if int(arith_used.item()) == 1 else "int32",
                "roofline": roofline, "phases": phases}
 
 
@@ -274,6 +280,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=32768, help="override the graph size (quick runs)")
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--arith", type=int, default=0, help="0 automatic, 1 int32, 2 float32 (exact, checked)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-single", action="store_true", help="batched/serving legs only")

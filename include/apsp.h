@@ -172,11 +172,12 @@ apsp_status_t apsp_profile_begin(void);
 apsp_status_t apsp_profile_end(apsp_profile_t *out);
 
 /* Measures the device's 32-bit VALU throughput (lane-instructions per
- * second) with the instruction mix of the min-plus kernels (two plain adds
- * and one three-input minimum per two relaxations, 8 independent
- * accumulators per lane), every CU busy; synchronises the device.  The
- * benchmark reports kernel rates against this measured peak beside the
- * datasheet one (256 CUs x 64 lanes x 2.4 GHz). */
+ * second) with the instruction mix of the min-plus kernels (two float32
+ * adds and one three-input float32 minimum per two relaxations, 8
+ * independent accumulators per lane), every CU busy; synchronises the
+ * device.  The benchmark reports kernel rates against this measured peak
+ * beside the datasheet one (157.3 TFLOP/s float32 vector = 78.6e12 VALU
+ * instructions per second). */
 apsp_status_t apsp_probe_valu(double *lane_instr_per_s, double *elapsed_ms);
 
 /* Release the calling device's internal workspace and cached graphs.

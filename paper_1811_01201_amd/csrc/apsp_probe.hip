@@ -2,8 +2,8 @@
 // phase-3 kernel against, measured on the device at its actual clock.
 //
 // Every thread runs `iters` iterations of the phase-3 inner step on 8
-// independent accumulators: per accumulator two plain 32-bit adds of
-// operands that do not depend on it, then one three-input minimum,
+// independent accumulators: per accumulator two float32 adds of operands
+// that do not depend on it, then one three-input float32 minimum,
 // c = min3(c, a0 + b0, a1 + b1), i.e. two (i,j,k) relaxations per three
 // instructions, exactly the instruction mix of the min-plus kernels.  The
 // grid fills every CU with 8 wavefronts.
@@ -15,15 +15,15 @@
 namespace apsp {
 
 #define APSP_PROBE_STEP(C, S0, S1)                 \
-    "v_add_u32_e32 " S0 ", %[a0], %[b0]\n\t"      \
-    "v_add_u32_e32 " S1 ", %[a1], %[b1]\n\t"      \
-    "v_min3_i32 " C ", " C ", " S0 ", " S1 "\n\t"
+    "v_add_f32_e32 " S0 ", %[a0], %[b0]\n\t"      \
+    "v_add_f32_e32 " S1 ", %[a1], %[b1]\n\t"      \
+    "v_min3_f32 " C ", " C ", " S0 ", " S1 "\n\t"
 
 __global__ void __launch_bounds__(256) valu_probe_kernel(int32_t *out, int iters, int32_t seed) {
-    int32_t c0 = seed + threadIdx.x, c1 = c0 + 1, c2 = c0 + 2, c3 = c0 + 3;
-    int32_t c4 = c0 + 4, c5 = c0 + 5, c6 = c0 + 6, c7 = c0 + 7;
-    int32_t a0 = seed ^ 0x55, a1 = seed ^ 0x33, b0 = seed + 7, b1 = seed - 9;
-    int32_t t0, t1, t2, t3, t4, t5, t6, t7, t8, t9, t10, t11, t12, t13, t14, t15;
+    float c0 = (float)(seed + (int)threadIdx.x), c1 = c0 + 1, c2 = c0 + 2, c3 = c0 + 3;
+    float c4 = c0 + 4, c5 = c0 + 5, c6 = c0 + 6, c7 = c0 + 7;
+    float a0 = (float)(seed ^ 0x55), a1 = (float)(seed ^ 0x33), b0 = (float)(seed + 7), b1 = (float)(seed - 9);
+    float t0, t1, t2, t3, t4, t5, t6, t7, t8, t9, t10, t11, t12, t13, t14, t15;
     for (int i = 0; i < iters; ++i) {
         asm volatile(APSP_PROBE_STEP("%[c0]", "%[t0]", "%[t1]") APSP_PROBE_STEP("%[c1]", "%[t2]", "%[t3]")
                      APSP_PROBE_STEP("%[c2]", "%[t4]", "%[t5]") APSP_PROBE_STEP("%[c3]", "%[t6]", "%[t7]")
@@ -37,10 +37,10 @@ __global__ void __launch_bounds__(256) valu_probe_kernel(int32_t *out, int iters
                        [t11] "=&v"(t11), [t12] "=&v"(t12), [t13] "=&v"(t13), [t14] "=&v"(t14),
                        [t15] "=&v"(t15)
                      : [a0] "v"(a0), [a1] "v"(a1), [b0] "v"(b0), [b1] "v"(b1));
-        a0 += 1;  // keeps the adds' operands changing between iterations
+        a0 += 1.0f;  // keeps the adds' operands changing between iterations
     }
-    const int32_t r = c0 ^ c1 ^ c2 ^ c3 ^ c4 ^ c5 ^ c6 ^ c7;
-    if (r == 0x7fffffff) out[0] = r;  // keeps the chains live; practically never taken
+    const float r = c0 + c1 + c2 + c3 + c4 + c5 + c6 + c7;
+    if (r == 12345.25f) out[0] = 1;  // keeps the chains live; practically never taken
 }
 
 #undef APSP_PROBE_STEP
