@@ -24,12 +24,13 @@ def _pack(graphs, dtype):
     return buf, ns, offsets
 
 
-def _run(graphs, dtype, pred, reps=1):
+def _run(graphs, dtype, pred, reps=1, team_config=None):
     import torch
 
     import paper_1811_01201_amd as apsp
     buf, ns, offs = _pack(graphs, dtype)
-    plan = apsp.BatchPlan(ns, offs, "int32" if dtype == np.int32 else "float32", want_pred=pred)
+    plan = apsp.BatchPlan(ns, offs, "int32" if dtype == np.int32 else "float32", want_pred=pred,
+                          team_config=team_config)
     outs = []
     for _ in range(reps):
         d = torch.from_numpy(buf.copy()).cuda()
@@ -117,6 +118,40 @@ def test_batched_deep_negative_cycle_reported():
         graphs[b] = W
     outs, ns, offs = _run(graphs, np.int32, False)
     assert list(outs[0][2]) == [3, 3, 0, 3]
+
+
+@pytest.mark.parametrize("cfg", [None, 0, 1, 2])
+def test_batched_large_weights_exact(orc, cfg):
+    """Weights near the int32 bound, long paths and large negative weights
+    (potentials), mixed with ordinary graphs, in every team configuration:
+    every graph exact."""
+    describe(f"batched large weights cfg={cfg}")
+    rng = np.random.default_rng(21)
+    graphs = []
+    for n, case in [(20, "big"), (40, "plain"), (150, "long"), (300, "plain"), (70, "neg"), (33, "long"),
+                    (129, "big"), (500, "plain")]:
+        bound = (2 ** 28 - 1) // (n - 1)
+        if case == "plain":
+            W = synth.int32_rows(n, 0.3, 1, 1000, 5, g=n)
+        elif case == "big":
+            W = pins.random_graph(rng, n, 0.3, max(1, bound - 1000), bound)
+        elif case == "long":
+            W = pins.random_graph(rng, n, 0.08, bound // 2, bound)
+        else:
+            pot = np.arange(n, dtype=np.int64) * (bound // 3) // (n - 1)
+            B = pins.random_graph(rng, n, 0.2, 1, bound // 3)
+            W = np.where(B != INF32, B + pot[:, None] - pot[None, :], INF32).astype(np.int32)
+            np.fill_diagonal(W, 0)
+        graphs.append(W)
+    team = None if cfg is None else [cfg] * len(graphs)
+    outs, ns, offs = _run(graphs, np.int32, False, team_config=team)
+    D, _, st = outs[0]
+    for b, W in enumerate(graphs):
+        n = W.shape[0]
+        o = int(offs[b])
+        D0, _, st0 = orc.fw(W)
+        assert st0 == 0 and st[b] == 0
+        assert first_mismatch(D[o:o + n * n].reshape(n, n), D0) is None, (b, n)
 
 
 def test_batched_equals_single_and_one_shot():
