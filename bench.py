@@ -235,7 +235,7 @@ def single_leg(args, n):
     achieved = per_launch_ops / (avg_ms / 1e3) / 1e12
     roofline = {
         "bound": "alu",
-        "kernel": "phase3_kernel (remaining-block min-plus products, 128x128 tiles)",
+        "kernel": "phase3_kernel kRest (remaining-block min-plus products, 128x128 tiles, 2 launches per round)",
         "achieved": round(achieved, 3),
         "peak": round(PEAK_OPS / 1e12, 3),
         "unit": "Tops/s (2 ops per (i,j,k) relaxation)",
@@ -253,15 +253,18 @@ def single_leg(args, n):
     phases = {k: {"launches": v["launches"], "ms_per_step": round(v["total_ms"] / args.steps, 3)}
               for k, v in prof.items() if v["launches"]}
 
-    traffic = None
+    # algorithmic HBM bytes of one launch: its C elements read and written
+    # once (8 bytes), plus the panel rows and columns they need, once
     bs = args.block_size or (256 if n > 4096 else 128)
+    m = n - 2 * bs
+    c_elems = p3["updates"] / max(1, p3["launches"]) / bs
+    algo = int(c_elems * 8 + (c_elems / m + m) * bs * 4)
+    roofline["algorithmic_bytes_per_launch"] = algo
+    traffic = None
     tr = profiling.read_traffic_file(os.path.join(ROOT, "profiles", f"phase3_int32_n{n}_traffic.txt"))
     if tr and tr.get("source_sha256") == profiling.kernel_source_hash() and not args.block_size:
         traffic = int(float(tr["traffic_bytes_per_launch"]))
-        m = n - 2 * bs  # a launch of the remaining-block set under the two-stream schedule
-        algo = m * m * 8 + 2 * m * bs * 4
         roofline["traffic_kernel"] = tr.get("kernel")
-        roofline["traffic_algorithmic_bytes"] = algo
         roofline["traffic_vs_algorithmic"] = round(traffic / algo, 3)
     roofline["traffic"] = traffic
     roofline["arithmetic"] = ("float32 on integer values: exact, every operand below 2^23 checked on the device"

@@ -79,15 +79,38 @@ def counters(paths):
     return out
 
 
+def largest_dispatch(path, kernel_pred, counter):
+    """(kernel, value) of the dispatch with the largest `counter` among the
+    kernels kernel_pred accepts."""
+    best = (None, -1.0)
+    per = collections.defaultdict(float)
+    names = {}
+    for r in csv.DictReader(open(path)):
+        k = short_name(r["Kernel_Name"])
+        if r["Counter_Name"] != counter or not kernel_pred(k):
+            continue
+        per[r["Dispatch_Id"]] += float(r["Counter_Value"])
+        names[r["Dispatch_Id"]] = k
+    for d, v in per.items():
+        if v > best[1]:
+            best = (names[d], v)
+    return best
+
+
 def traffic(fetch_csv, write_csv, kernel_regex, copy_bytes):
+    """Per-launch HBM bytes of the kernels matching kernel_regex.  The scale
+    comes from the largest copy dispatch of each run (the input restore of
+    copy_bytes); smaller copies of the same kernel (scalars read back) are
+    ignored."""
     f = counters([fetch_csv])
     w = counters([write_csv])
-    copy = [k for k in f if "copyBuffer" in k or "copy" in k.lower()]
-    if not copy:
+    is_copy = lambda k: "copyBuffer" in k
+    ck, fetch_kib = largest_dispatch(fetch_csv, is_copy, "FETCH_SIZE")
+    _, write_kib = largest_dispatch(write_csv, is_copy, "WRITE_SIZE")
+    if ck is None or fetch_kib <= 0 or write_kib <= 0:
         raise SystemExit("no copy kernel in the counter run")
-    ck = copy[0]
-    f_scale = copy_bytes / (f[ck]["FETCH_SIZE"] * 1024.0)
-    w_scale = copy_bytes / (w[ck]["WRITE_SIZE"] * 1024.0)
+    f_scale = copy_bytes / (fetch_kib * 1024.0)
+    w_scale = copy_bytes / (write_kib * 1024.0)
     rx = re.compile(kernel_regex)
     ks = [k for k in f if rx.search(k)]
     res = {}
