@@ -82,7 +82,10 @@ __device__ __forceinline__ bool from_work(const Ar &ar, typename Ar::T v, int64_
         out = v >= kFakeThreshold ? kInf32 : v;
         neg = ((i == j) && v < 0) || v < kWrapWitness;
     } else if constexpr (std::is_same_v<Ar, ArF32>) {
-        out = v;
+        if constexpr (std::is_same_v<Tin, int32_t>)  // int32 weights solved in float32 (exact)
+            out = (v == __builtin_inff()) ? kInf32 : (int32_t)v;
+        else
+            out = v;
         neg = (i == j) && v < 0.0f;
     } else if constexpr (std::is_same_v<Ar, ArKey>) {
         if (v == __builtin_inf()) {
@@ -285,10 +288,31 @@ __device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
     if (status && lane == 0) status[g] = neg ? APSP_ERROR_NEGATIVE_CYCLE : APSP_SUCCESS;
 }
 
+// ------------------------------------------- per-graph policy choice
+// A graph takes the second policy Alt when one of its weights rules out the
+// first:
+//   float32 weights with predecessors (ArKey / ArLexF32): a finite weight
+//     that is not an integer within the bound (keys would not be exact);
+//   int32 distances (ArF32 / ArI32): a negative weight or one with
+//     |w| (n - 1) >= 2^23.  Otherwise every operand the blocked schedule
+//     adds is a restricted shortest-path length below 2^23 in magnitude, so
+//     every float32 sum is an exact integer below 2^24 and the float32
+//     solve equals the int32 one; float32 adds issue at twice the rate.
+template <class Ar, class Alt, class Tin>
+__device__ __forceinline__ bool rules_out(Tin w, int64_t n) {
+    if constexpr (std::is_same_v<Ar, ArF32> && std::is_same_v<Alt, ArI32>) {
+        return w != kInf32 && (w < 0 || (int64_t)w * (n - 1) >= (int64_t(1) << 23));
+    } else {
+        const float bound = (float)weight_bound(n);
+        const float f = (float)w;
+        return f != __builtin_inff() && (f != __builtin_floorf(f) || __builtin_fabsf(f) > bound);
+    }
+}
+
 // ------------------------------------------------------------- the kernel
 // counters[0]: next team graph, [1]: next wavefront graph, [2]: finished
-// workgroups.  mode_alt: float32 predecessor solves pick the pair policy
-// for graphs whose weights are not all integers within the bound.
+// workgroups.  With a second policy Alt, each graph is checked first and
+// solved with Alt when rules_out says so.
 template <class Tin, class Ar, class Alt>
 __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(2)))
 batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pred,
@@ -314,14 +338,9 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
         const int64_t n = meta.ns[g], off = meta.offsets[g];
         bool use_alt = false;
         if constexpr (kDual) {
-            const float bound = (float)weight_bound(n);
-            bool lex = false;
-            for (int64_t e = tid; e < n * n; e += kBatchThreads) {
-                const float w = (float)dist[off + e];
-                if (w != __builtin_inff() && (w != __builtin_floorf(w) || __builtin_fabsf(w) > bound))
-                    lex = true;
-            }
-            use_alt = __syncthreads_or(lex);
+            bool out = false;
+            for (int64_t e = tid; e < n * n; e += kBatchThreads) out |= rules_out<Ar, Alt>(dist[off + e], n);
+            use_alt = __syncthreads_or(out);
         }
         const int cfg = meta.cfg[g];
         if constexpr (kDual) {
@@ -344,14 +363,9 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
         const int64_t n = meta.ns[g], off = meta.offsets[g];
         bool use_alt = false;
         if constexpr (kDual) {
-            const float bound = (float)weight_bound(n);
-            bool lex = false;
-            for (int64_t e = lane; e < n * n; e += 64) {
-                const float w = (float)dist[off + e];
-                if (w != __builtin_inff() && (w != __builtin_floorf(w) || __builtin_fabsf(w) > bound))
-                    lex = true;
-            }
-            use_alt = __any(lex);
+            bool out = false;
+            for (int64_t e = lane; e < n * n; e += 64) out |= rules_out<Ar, Alt>(dist[off + e], n);
+            use_alt = __any(out);
         }
         if constexpr (kDual) {
             if (use_alt) {
@@ -458,7 +472,7 @@ apsp_status_t batched_launch(const BatchLaunch &L, apsp_dtype_t dtype, bool want
     if (L.batch == 0) return APSP_SUCCESS;
     if (dtype == APSP_INT32) {
         if (want_pred) return launch<int32_t>(L, dist, pred, status, s, ArKey{7}, NoAlt{});
-        return launch<int32_t>(L, dist, nullptr, status, s, ArI32{}, NoAlt{});
+        return launch<int32_t>(L, dist, nullptr, status, s, ArF32{}, ArI32{});
     }
     if (want_pred) return launch<float>(L, dist, pred, status, s, ArKey{7}, ArLexF32{});
     return launch<float>(L, dist, nullptr, status, s, ArF32{}, NoAlt{});
