@@ -246,6 +246,11 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
  */
 apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t graphs_per_class,
                                   int32_t reps, double *ms_out);
+/* As apsp_batch_autotune, on a synthetic batch with the caller's graph sizes
+ * (host ns[batch], 1 <= ns[b] <= 1024): tunes the classes the workload
+ * actually has, in its own mix.  Classes without graphs keep their entry. */
+apsp_status_t apsp_batch_autotune_sizes(const int32_t *ns, int32_t batch, apsp_dtype_t dtype,
+                                        int32_t want_pred, int32_t reps, double *ms_out);
 /* Team configuration the table gives a graph of n vertices (-1: n <= 64, one wavefront). */
 int32_t apsp_batch_config(int64_t n, apsp_dtype_t dtype, int32_t want_pred);
 apsp_status_t apsp_tune_save(const char *path);

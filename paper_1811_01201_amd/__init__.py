@@ -116,6 +116,7 @@ def _bind_optional(L):
         "apsp_probe_valu": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], c_int),
         "apsp_batch_plan_create_ex": ([vp, vp, i32, c_int, i32, vp, ctypes.POINTER(vp)], c_int),
         "apsp_batch_autotune": ([c_int, i32, i32, i32, ctypes.POINTER(ctypes.c_double)], c_int),
+        "apsp_batch_autotune_sizes": ([vp, i32, c_int, i32, i32, ctypes.POINTER(ctypes.c_double)], c_int),
         "apsp_batch_config": ([i64, c_int, i32], i32),
         "apsp_tune_save": ([ctypes.c_char_p], c_int),
         "apsp_tune_load": ([ctypes.c_char_p], c_int),
@@ -398,13 +399,20 @@ TEAM_CONFIGS = ("wave_tiles_64", "group_tiles_64", "group_tiles_128")
 SIZE_CLASSES = (128, 256, 384, 512, 1024)
 
 
-def batch_autotune(dtype="int32", want_pred=False, graphs_per_class=0, reps=0) -> dict:
+def batch_autotune(dtype="int32", want_pred=False, graphs_per_class=0, reps=0, ns=None) -> dict:
     """Time every batched team configuration per size class on the current
-    device and keep the fastest in the library's table.  Returns
-    {class_upper_bound: {config_name: ms, ..., "best": name}}."""
+    device and keep the fastest in the library's table.  With ns (graph
+    sizes of the intended workload) the synthetic batch has exactly those
+    sizes.  Returns {class_upper_bound: {config_name: ms, ..., "best": name}}
+    (ms 0 for classes that were not timed)."""
     ms = (ctypes.c_double * (len(SIZE_CLASSES) * 3))()
     dt = INT32 if dtype in ("int32", INT32) else FLOAT32
-    st = lib().apsp_batch_autotune(dt, int(want_pred), int(graphs_per_class), int(reps), ms)
+    if ns is None:
+        st = lib().apsp_batch_autotune(dt, int(want_pred), int(graphs_per_class), int(reps), ms)
+    else:
+        import numpy as np
+        arr = np.ascontiguousarray(ns, dtype=np.int32)
+        st = lib().apsp_batch_autotune_sizes(arr.ctypes.data, int(arr.size), dt, int(want_pred), int(reps), ms)
     if st != SUCCESS:
         raise APSPError(st, "apsp_batch_autotune")
     out = {}

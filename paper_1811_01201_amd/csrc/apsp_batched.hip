@@ -739,14 +739,15 @@ apsp_status_t apsp_tune_save(const char *path) {
     return tune_save_locked(path);
 }
 
-apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t graphs_per_class,
-                                  int32_t reps, double *ms_out) {
-    if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
-    if (graphs_per_class < 0 || reps < 0) return APSP_ERROR_INVALID_ARGUMENT;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess) return APSP_ERROR_HIP;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int32_t per = graphs_per_class ? graphs_per_class : cus;
+}  // extern "C"
+
+namespace {
+
+// Coordinate descent over the size classes present in `sizes` (graphs of
+// those sizes, synthetic weights): one class at a time, the others at
+// their current choice, the whole batch timed for each configuration.
+apsp_status_t autotune_on(const std::vector<int32_t> &sizes, apsp_dtype_t dtype, int32_t want_pred, int32_t reps,
+                          double *ms_out) {
     const int R = reps ? reps : 3;
     const int d = dtype == APSP_FLOAT32, m = want_pred ? 1 : 0;
     {
@@ -756,20 +757,16 @@ apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t
             if (const char *env = std::getenv("APSP_TUNE_TABLE")) tune_load_locked(env);
         }
     }
-    // one mixed batch: `per` graphs spread over every size class, so the
-    // measurement sees the classes interact (shared CUs, caches, queue order)
-    const int32_t B = per * kClasses;
-    std::vector<int32_t> ns(B), cls(B);
+    const int32_t B = (int32_t)sizes.size();
+    std::vector<int32_t> ns(sizes), cls(B);
     std::vector<int64_t> offs(B);
+    bool present[kClasses] = {};
     int64_t total = 0;
-    for (int c = 0, b = 0; c < kClasses; ++c) {
-        const int lo = c == 0 ? kBatchBS + 1 : kClassHi[c - 1] + 1, hi = kClassHi[c];
-        for (int32_t q = 0; q < per; ++q, ++b) {
-            ns[b] = lo + (int32_t)(((int64_t)q * (hi - lo + 1)) / per);
-            cls[b] = c;
-            offs[b] = total;
-            total += ((int64_t)ns[b] * ns[b] + 3) / 4 * 4;
-        }
+    for (int32_t b = 0; b < B; ++b) {
+        cls[b] = ns[b] <= kBatchBS ? -1 : size_class(ns[b]);  // n <= 64: one wavefront, no team
+        if (cls[b] >= 0) present[cls[b]] = true;
+        offs[b] = total;
+        total += ((int64_t)ns[b] * ns[b] + 3) / 4 * 4;
     }
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return APSP_ERROR_HIP;
@@ -800,7 +797,7 @@ apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t
     }
     auto time_batch = [&](const int8_t *ch, double &ms_per) -> apsp_status_t {
         std::vector<int8_t> forced(B);
-        for (int32_t b = 0; b < B; ++b) forced[b] = ch[cls[b]];
+        for (int32_t b = 0; b < B; ++b) forced[b] = cls[b] >= 0 ? ch[cls[b]] : (int8_t)-1;
         apsp_batch_plan_t *plan = nullptr;
         apsp_status_t st =
             apsp_batch_plan_create_ex(ns.data(), offs.data(), B, dtype, want_pred, forced.data(), &plan);
@@ -819,6 +816,7 @@ apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t
     };
     // coordinate descent: one class at a time, the others at their current choice
     for (int c = 0; c < kClasses && result == APSP_SUCCESS; ++c) {
+        if (!present[c]) continue;
         double best_ms = 1e300;
         int best = choice[c];
         for (int cfg = kWaveTiles64; cfg <= kGroupTiles128 && result == APSP_SUCCESS; ++cfg) {
@@ -846,6 +844,37 @@ apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t
     hipEventDestroy(e1);
     hipStreamDestroy(s);
     return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t graphs_per_class,
+                                  int32_t reps, double *ms_out) {
+    if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
+    if (graphs_per_class < 0 || reps < 0) return APSP_ERROR_INVALID_ARGUMENT;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess) return APSP_ERROR_HIP;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int32_t per = graphs_per_class ? graphs_per_class : cus;
+    // `per` graphs spread evenly over every size class
+    std::vector<int32_t> sizes;
+    for (int c = 0; c < kClasses; ++c) {
+        const int lo = c == 0 ? kBatchBS + 1 : kClassHi[c - 1] + 1, hi = kClassHi[c];
+        for (int32_t q = 0; q < per; ++q) sizes.push_back(lo + (int32_t)(((int64_t)q * (hi - lo + 1)) / per));
+    }
+    return autotune_on(sizes, dtype, want_pred, reps, ms_out);
+}
+
+apsp_status_t apsp_batch_autotune_sizes(const int32_t *ns, int32_t batch, apsp_dtype_t dtype, int32_t want_pred,
+                                        int32_t reps, double *ms_out) {
+    if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
+    if (!ns || batch <= 0 || reps < 0) return APSP_ERROR_INVALID_ARGUMENT;
+    std::vector<int32_t> sizes(ns, ns + batch);
+    for (int32_t v : sizes)
+        if (v < 1 || v > kClassHi[kClasses - 1]) return APSP_ERROR_INVALID_ARGUMENT;
+    return autotune_on(sizes, dtype, want_pred, reps, ms_out);
 }
 
 apsp_status_t apsp_solve_batched(void *packed_dist, int32_t *packed_pred, const int32_t *ns,

@@ -105,6 +105,9 @@ def test_batch_plan_host_argument_errors():
     assert L.apsp_batch_plan_create(ns.ctypes.data, offs.ctypes.data, 2, 5, 0,
                                     ctypes.byref(plan)) == apsp.INVALID_ARGUMENT
     assert L.apsp_batch_plan_execute(None, None, None, None, None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_batch_autotune_sizes(None, 3, 0, 0, 0, None) == apsp.INVALID_ARGUMENT
+    too_big = np.array([100, 2000], dtype=np.int32)
+    assert L.apsp_batch_autotune_sizes(too_big.ctypes.data, 2, 0, 0, 0, None) == apsp.INVALID_ARGUMENT
 
 
 def test_tuning_table_roundtrip(tmp_path):

@@ -253,3 +253,32 @@ def test_autotune_fills_table():
         assert all(t > 0 for t in times)
         # coordinate descent: the kept choice is the fastest trial for its class
         assert row["best"] == apsp.TEAM_CONFIGS[int(np.argmin(times))]
+
+
+def test_autotune_on_workload_sizes(orc, tmp_path):
+    """Tuning on the caller's sizes times only the classes present, keeps the
+    fastest trial for each, and leaves results exact."""
+    import paper_1811_01201_amd as apsp
+    describe("batched autotune on sizes")
+    saved = tmp_path / "before.json"
+    apsp.tune_save(str(saved))
+    try:
+        sizes = [70, 100, 300, 310, 40, 20]
+        rep = apsp.batch_autotune("int32", False, reps=1, ns=sizes)
+        for hi, row in rep.items():
+            times = [row[c] for c in apsp.TEAM_CONFIGS]
+            if hi in (128, 384):
+                assert all(t > 0 for t in times)
+                assert row["best"] == apsp.TEAM_CONFIGS[int(np.argmin(times))]
+            else:
+                assert all(t == 0 for t in times)
+        graphs = _graphs("int", sizes, seed=31)
+        outs, ns, offs = _run(graphs, np.int32, False)
+        D, _, st = outs[0]
+        for b, W in enumerate(graphs):
+            n = W.shape[0]
+            o = int(offs[b])
+            D0, _, _ = orc.fw(W)
+            assert st[b] == 0 and np.array_equal(D[o:o + n * n].reshape(n, n), D0)
+    finally:
+        apsp.tune_load(str(saved))
