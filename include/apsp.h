@@ -184,6 +184,30 @@ apsp_status_t apsp_probe_valu(double *lane_instr_per_s, double *elapsed_ms);
  * Must not overlap with solves in flight on that device. */
 apsp_status_t apsp_release_workspace(void);
 
+/* ------------------------------------------------------------------ paths
+ *
+ * Path reconstruction (the paper keeps the path matrix so that shortest
+ * paths, not only their lengths, can be recovered; Section "Floyd-Warshall
+ * Algorithm").  For each query t the vertices of the shortest path from
+ * src[t] to dst[t] are read from the canonical predecessor matrix.
+ *   pred     device, n x n int32, as written by apsp_solve with predecessors
+ *   src, dst device int32[q], vertex ids
+ *   paths    device int32[q * max_len]: query t's path, src[t] first and
+ *            dst[t] last, at paths[t * max_len ...]
+ *   lengths  device int32[q]: number of vertices on the path (1 when
+ *            src == dst), 0 when dst is unreachable, APSP_PATH_TOO_LONG when
+ *            the path has more than max_len vertices, APSP_PATH_BAD_QUERY
+ *            for a vertex id outside [0, n), APSP_PATH_BROKEN when the
+ *            chain leaves [0, n) or exceeds n - 1 hops (pred was not
+ *            produced by apsp_solve).
+ * Enqueued on stream; every walk is bounded by n steps and max_len writes.
+ */
+#define APSP_PATH_TOO_LONG (-1)
+#define APSP_PATH_BAD_QUERY (-2)
+#define APSP_PATH_BROKEN (-3)
+apsp_status_t apsp_paths(const int32_t *pred, int64_t n, const int32_t *src, const int32_t *dst, int32_t q,
+                         int32_t *paths, int32_t max_len, int32_t *lengths, hipStream_t stream);
+
 /* ----------------------------------------------------------------- batched
  *
  * Many independent graphs of uneven size, solved by one persistent fused

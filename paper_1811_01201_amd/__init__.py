@@ -117,6 +117,7 @@ def _bind_optional(L):
         "apsp_batch_plan_create_ex": ([vp, vp, i32, c_int, i32, vp, ctypes.POINTER(vp)], c_int),
         "apsp_batch_autotune": ([c_int, i32, i32, i32, ctypes.POINTER(ctypes.c_double)], c_int),
         "apsp_batch_autotune_sizes": ([vp, i32, c_int, i32, i32, ctypes.POINTER(ctypes.c_double)], c_int),
+        "apsp_paths": ([vp, i64, vp, vp, i32, vp, i32, vp, vp], c_int),
         "apsp_batch_config": ([i64, c_int, i32], i32),
         "apsp_tune_save": ([ctypes.c_char_p], c_int),
         "apsp_tune_load": ([ctypes.c_char_p], c_int),
@@ -184,6 +185,33 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
     if check and st != SUCCESS:
         raise APSPError(st, "apsp_solve_ex")
     return st
+
+
+PATH_TOO_LONG, PATH_BAD_QUERY, PATH_BROKEN = -1, -2, -3
+
+
+def paths(pred, src, dst, max_len: int, stream=None, check=True):
+    """Shortest paths read from a predecessor matrix (apsp_paths).
+
+    pred : torch.Tensor [n, n] int32 on the GPU (from solve(..., pred)).
+    src, dst : torch.Tensor [q] int32 on the same device.
+    Returns (paths [q, max_len] int32, lengths [q] int32), device tensors:
+    lengths[t] vertices, 0 unreachable, PATH_TOO_LONG / PATH_BAD_QUERY /
+    PATH_BROKEN otherwise."""
+    import torch
+    assert pred.dim() == 2 and pred.shape[0] == pred.shape[1] and pred.dtype == torch.int32
+    assert pred.is_cuda and pred.is_contiguous()
+    src = src.to(device=pred.device, dtype=torch.int32).contiguous()
+    dst = dst.to(device=pred.device, dtype=torch.int32).contiguous()
+    q = src.numel()
+    assert dst.numel() == q
+    out = torch.full((q, max(1, int(max_len))), -1, dtype=torch.int32, device=pred.device)
+    lengths = torch.empty(q, dtype=torch.int32, device=pred.device)
+    st = lib().apsp_paths(pred.data_ptr(), pred.shape[0], src.data_ptr(), dst.data_ptr(), q, out.data_ptr(),
+                          int(max_len), lengths.data_ptr(), _stream_ptr(stream))
+    if check and st != SUCCESS:
+        raise APSPError(st, "apsp_paths")
+    return out, lengths
 
 
 def solve_raw(dist_ptr, pred_ptr, n, dtype_code, stream_ptr, options: Options | None = None) -> int:

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libapsp.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["apsp_single.hip", "apsp_batched.hip", "apsp_server.hip", "apsp_probe.hip"]
+SOURCES = ["apsp_single.hip", "apsp_batched.hip", "apsp_server.hip", "apsp_probe.hip", "apsp_paths.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -132,3 +132,13 @@ def test_tuning_table_roundtrip(tmp_path):
         apsp.tune_load(str(tmp_path / "missing.json"))
     apsp.tune_load(str(p))  # a valid table stays in force after failed loads
     assert apsp.batch_config(500, "float32", True) == 2
+
+
+def test_paths_host_argument_errors():
+    L = apsp.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.apsp_paths(fake, 10, fake, fake, -1, fake, 4, fake, None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_paths(fake, 10, fake, fake, 3, fake, 0, fake, None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_paths(None, 10, fake, fake, 3, fake, 4, fake, None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_paths(fake, 70000, fake, fake, 3, fake, 4, fake, None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_paths(None, 10, None, None, 0, None, 4, None, None) == apsp.SUCCESS  # nothing to do
