@@ -66,6 +66,52 @@ def cpu_baseline(W, budget_s: float):
     }
 
 
+def sweep_leg(sizes, modes):
+    """The paper's size sweep (Section "Experimental Design": powers of two
+    from 4096 to 65536) on one GPU: float32 with the path matrix (the paper's
+    own configuration) and int32 distances.  Weights are integers 1..1000,
+    edge probability 0.3, synthetic.  One warm-up solve, then timed solves
+    (HIP events on the current stream)."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    import synth
+
+    rows = []
+    for n in sizes:
+        for mode in modes:
+            log(f"[sweep] n={n} {mode}: generating")
+            if mode == "f32pred":
+                W = synth.single_f32int(n, p=0.3, seed=synth.BASE_SEED + 10)
+            else:
+                W = synth.single_int32(n, p=0.3, seed=synth.BASE_SEED + 10)
+            pristine = torch.from_numpy(W).cuda()
+            del W
+            work = torch.empty_like(pristine)
+            pred = torch.empty(pristine.shape, dtype=torch.int32, device="cuda") if mode == "f32pred" else None
+            used = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+            reps = 1 if n >= 32768 else 3
+            times = []
+            for r in range(reps + 1):
+                work.copy_(pristine)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                apsp.solve(work, pred, arith_used=used)
+                e1.record()
+                torch.cuda.synchronize()
+                log(f"[sweep] n={n} {mode}: solve {r} {e0.elapsed_time(e1):.1f} ms")
+                if r > 0:
+                    times.append(e0.elapsed_time(e1))
+            t = min(times)
+            rows.append({"n": n, "mode": mode, "ms": round(t, 3), "gops": round(2.0 * n ** 3 / (t / 1e3) / 1e9, 1),
+                         "arithmetic": ("fp64 keys" if mode == "f32pred" else
+                                        "float32 (exact)" if int(used.item()) == 1 else "int32")})
+            del pristine, work, pred
+            torch.cuda.empty_cache()
+    return rows
+
+
 def batched_leg(replays: int):
     """4096 graphs (n uniform in [16, 512], p uniform in [0.05, 0.9], int32
     weights 1..1000) in one fused launch per replay, against the same graphs
@@ -287,6 +333,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-single", action="store_true", help="batched/serving legs only")
+    ap.add_argument("--sweep", default="",
+                    help="only the paper's size sweep, e.g. 4096,8192,16384,32768,65536 (one JSON line)")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--batched-replays", type=int, default=10)
@@ -301,6 +349,13 @@ def main():
     import torch
 
     import paper_1811_01201_amd as apsp
+
+    if args.sweep:
+        torch.cuda.set_device(0)
+        apsp.lib()
+        rows = sweep_leg([int(x) for x in args.sweep.split(",")], ["f32pred", "int32"])
+        print(json.dumps({"sweep": rows, "data": "synthetic", "n_gpus": 1}), flush=True)
+        return
 
     n = args.n
     torch.cuda.set_device(0)

@@ -45,12 +45,12 @@ def test_parity_auto_block(orc, n, kind, pred):
         assert first_mismatch(P, P0) is None, first_mismatch(P, P0)
 
 
-@pytest.mark.parametrize("bs,tt", [(64, 4), (64, 8), (128, 8), (256, 8)])
+# predecessor solves use blocks of at most 128 (8-byte keys); block size 256
+# with predecessors is rejected on the host (test_abi_cpu)
+@pytest.mark.parametrize("bs,tt,pred", [(64, 4, False), (64, 8, False), (128, 8, False), (256, 8, False),
+                                        (64, 4, True), (64, 8, True), (128, 8, True)])
 @pytest.mark.parametrize("n,kind", [(130, "int"), (300, "pot"), (512, "f32"), (700, "sparse")])
-@pytest.mark.parametrize("pred", [False, True])
-def test_parity_every_block_size(orc, bs, tt, n, kind, pred):
-    if bs == 256 and pred:
-        pytest.skip("predecessor solves use blocks of at most 128")
+def test_parity_every_block_size(orc, bs, tt, pred, n, kind):
     describe(f"single bs={bs} tt={tt} n={n} kind={kind} pred={pred}")
     W = _graph(kind, n, seed=77 + n)
     D0, P0, _ = oracle_expect(orc, W, pred)
