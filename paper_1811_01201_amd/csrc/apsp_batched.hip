@@ -309,11 +309,48 @@ __device__ __forceinline__ bool rules_out(Tin w, int64_t n) {
     }
 }
 
+// Whether any weight of a graph (count elements from a 16-byte-aligned g)
+// rules out policy Ar in favour of Alt: 16-byte loads, several in flight
+// per lane, lanes lane, lane + width, ... of the caller's group.
+template <class Ar, class Alt, class Tin>
+__device__ __forceinline__ bool scan_rules_out(const Tin *__restrict__ g, int64_t count, int64_t n, int lane,
+                                               int width) {
+    const int64_t nv = count / 4;
+    const int4 *__restrict__ v = reinterpret_cast<const int4 *>(g);
+    bool out = false;
+#pragma unroll 4
+    for (int64_t e = lane; e < nv; e += width) {
+        const int4 x = v[e];
+        Tin a[4];
+        __builtin_memcpy(a, &x, 16);
+        out |= rules_out<Ar, Alt>(a[0], n) | rules_out<Ar, Alt>(a[1], n) | rules_out<Ar, Alt>(a[2], n) |
+               rules_out<Ar, Alt>(a[3], n);
+    }
+    for (int64_t e = nv * 4 + lane; e < count; e += width) out |= rules_out<Ar, Alt>(g[e], n);
+    return out;
+}
+
 // ------------------------------------------------------------- the kernel
 // counters[0]: next team graph, [1]: next wavefront graph, [2]: finished
 // workgroups.  With a second policy Alt, each graph is checked first and
-// solved with Alt when rules_out says so.
-template <class Tin, class Ar, class Alt>
+// solved with Alt when rules_out says so.  SEL splits int32 distance
+// batches over two launches with one arithmetic each (a kernel holding
+// both spills registers): kIntGraphs solves only the graphs rules_out
+// excludes from float32 arithmetic, kFloatGraphs only the others.  The
+// int32 launch runs first, so the float32 one still sees the weights of
+// the graphs it solves; a graph the int32 launch solved may pass the check
+// afterwards and be solved again from its distances, which leaves them
+// unchanged.
+enum BatchSel { kEveryGraph = 0, kIntGraphs = 1, kFloatGraphs = 2 };
+
+template <int SEL, class Tin>
+__device__ __forceinline__ bool selected(bool excluded_from_float) {
+    if constexpr (SEL == kIntGraphs) return excluded_from_float;
+    if constexpr (SEL == kFloatGraphs) return !excluded_from_float;
+    return true;
+}
+
+template <class Tin, class Ar, class Alt, int SEL>
 __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(2)))
 batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pred,
                int32_t *__restrict__ status, void *__restrict__ scratch, int32_t *__restrict__ counters,
@@ -336,11 +373,13 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
         if (q >= meta.n_team) break;
         const int g = meta.order[q];
         const int64_t n = meta.ns[g], off = meta.offsets[g];
+        if constexpr (SEL != kEveryGraph) {
+            const bool out = scan_rules_out<ArF32, ArI32>(dist + off, n * n, n, tid, kBatchThreads);
+            if (!selected<SEL, Tin>(__syncthreads_or(out))) continue;
+        }
         bool use_alt = false;
         if constexpr (kDual) {
-            bool out = false;
-            for (int64_t e = tid; e < n * n; e += kBatchThreads) out |= rules_out<Ar, Alt>(dist[off + e], n);
-            use_alt = __syncthreads_or(out);
+            use_alt = __syncthreads_or(scan_rules_out<Ar, Alt>(dist + off, n * n, n, tid, kBatchThreads));
         }
         const int cfg = meta.cfg[g];
         if constexpr (kDual) {
@@ -361,11 +400,13 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
         if (q >= meta.batch) break;
         const int g = meta.order[q];
         const int64_t n = meta.ns[g], off = meta.offsets[g];
+        if constexpr (SEL != kEveryGraph) {
+            const bool out = scan_rules_out<ArF32, ArI32>(dist + off, n * n, n, lane, 64);
+            if (!selected<SEL, Tin>(__any(out))) continue;
+        }
         bool use_alt = false;
         if constexpr (kDual) {
-            bool out = false;
-            for (int64_t e = lane; e < n * n; e += 64) out |= rules_out<Ar, Alt>(dist[off + e], n);
-            use_alt = __any(out);
+            use_alt = __any(scan_rules_out<Ar, Alt>(dist + off, n * n, n, lane, 64));
         }
         if constexpr (kDual) {
             if (use_alt) {
@@ -442,9 +483,9 @@ apsp_status_t retire(apsp_batch_plan_t *p, hipStream_t s) {
     return APSP_SUCCESS;
 }
 
-template <class Tin, class Ar, class Alt>
+template <class Tin, class Ar, class Alt, int SEL = kEveryGraph>
 apsp_status_t launch(const BatchLaunch &L, void *dist, int32_t *pred, int32_t *status, hipStream_t s,
-                     Ar ar, Alt alt) {
+                     Ar ar, Alt alt, int32_t *counters) {
     BatchMeta m;
     m.order = (const int32_t *)L.meta;
     m.ns = m.order + L.batch;
@@ -453,8 +494,8 @@ apsp_status_t launch(const BatchLaunch &L, void *dist, int32_t *pred, int32_t *s
     m.batch = L.batch;
     m.n_team = L.n_team;
     m.scratch_elems = L.scratch_elems;
-    hipLaunchKernelGGL((batched_kernel<Tin, Ar, Alt>), dim3(L.grid), dim3(kBatchThreads), 0, s, m,
-                       (Tin *)dist, pred, status, L.scratch, L.counters, ar, alt);
+    hipLaunchKernelGGL((batched_kernel<Tin, Ar, Alt, SEL>), dim3(L.grid), dim3(kBatchThreads), 0, s, m,
+                       (Tin *)dist, pred, status, L.scratch, counters, ar, alt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         t_last_hip = (int)e;
@@ -471,11 +512,17 @@ apsp_status_t batched_launch(const BatchLaunch &L, apsp_dtype_t dtype, bool want
                              int32_t *pred, int32_t *status, hipStream_t s) {
     if (L.batch == 0) return APSP_SUCCESS;
     if (dtype == APSP_INT32) {
-        if (want_pred) return launch<int32_t>(L, dist, pred, status, s, ArKey{7}, NoAlt{});
-        return launch<int32_t>(L, dist, nullptr, status, s, ArF32{}, ArI32{});
+        if (want_pred) return launch<int32_t>(L, dist, pred, status, s, ArKey{7}, NoAlt{}, L.counters);
+        // int32 arithmetic for the graphs that need it, then float32 for the
+        // rest; each launch has its own counters
+        apsp_status_t st = launch<int32_t, ArI32, NoAlt, kIntGraphs>(L, dist, nullptr, status, s, ArI32{},
+                                                                    NoAlt{}, L.counters);
+        if (st != APSP_SUCCESS) return st;
+        return launch<int32_t, ArF32, NoAlt, kFloatGraphs>(L, dist, nullptr, status, s, ArF32{}, NoAlt{},
+                                                           L.counters + 4);
     }
-    if (want_pred) return launch<float>(L, dist, pred, status, s, ArKey{7}, ArLexF32{});
-    return launch<float>(L, dist, nullptr, status, s, ArF32{}, NoAlt{});
+    if (want_pred) return launch<float>(L, dist, pred, status, s, ArKey{7}, ArLexF32{}, L.counters);
+    return launch<float>(L, dist, nullptr, status, s, ArF32{}, NoAlt{}, L.counters);
 }
 
 void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, int32_t &n_team) {
@@ -687,14 +734,14 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
     p->grid = std::max(1, 2 * cus);
     const size_t elem = p->want_pred ? 8 : 4;
     if (hipMalloc(&p->dev_meta, host.size()) != hipSuccess ||
-        hipMalloc((void **)&p->counters, 4 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void **)&p->counters, 8 * sizeof(int32_t)) != hipSuccess ||
         (p->scratch_elems > 0 &&
          hipMalloc(&p->scratch, (size_t)p->grid * p->scratch_elems * elem) != hipSuccess)) {
         plan_free(p);
         return APSP_ERROR_OUT_OF_MEMORY;
     }
     if (hipMemcpy(p->dev_meta, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(p->counters, 0, 4 * sizeof(int32_t)) != hipSuccess) {
+        hipMemset(p->counters, 0, 8 * sizeof(int32_t)) != hipSuccess) {
         plan_free(p);
         return APSP_ERROR_HIP;
     }

@@ -51,7 +51,7 @@ struct BatchLaunch {
     int32_t batch, n_team;
     int64_t scratch_elems;  // per workgroup
     void *scratch;          // grid * scratch_elems * (4 or 8 bytes)
-    int32_t *counters;      // 4 int32, zero before the first launch
+    int32_t *counters;      // 8 int32 (two launches' counters), zero before the first launch
     int grid;
 };
 apsp_status_t batched_launch(const BatchLaunch &L, apsp_dtype_t dtype, bool want_pred, void *dist,
