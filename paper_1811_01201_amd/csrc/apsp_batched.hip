@@ -170,13 +170,16 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
     T(*buf)[BS] = reinterpret_cast<T(*)[BS]>(sm.p1);
     for (int r = 0; r < R; ++r) {
         const int64_t r0 = (int64_t)r * BS;
+        // the last block's k-range stops at n, rounded up to 32 (whole pairs
+        // of 16-wide chunks): the vertices beyond n are isolated padding
+        const int kc = r + 1 < R ? BS : (int)((n - r0 + 31) / 32 * 32);
         // phase 1
         if constexpr (CFG == kWaveTiles64) {
-            if (wave == 0) phase1_body<Ar, 64, true, 8>(X, ldp, r0, ar, buf, buf + 2);
+            if (wave == 0) phase1_body<Ar, 64, true, 8>(X, ldp, r0, ar, buf, buf + 2, kc);
         } else if constexpr (CFG == kGroupTiles64) {
-            phase1_body<Ar, 64, false, 4>(X, ldp, r0, ar, buf, buf + 2);
+            phase1_body<Ar, 64, false, 4>(X, ldp, r0, ar, buf, buf + 2, kc);
         } else {
-            phase1_body<Ar, 128, false, 8>(X, ldp, r0, ar, buf, buf + 2);
+            phase1_body<Ar, 128, false, 8>(X, ldp, r0, ar, buf, buf + 2, kc);
         }
         __syncthreads();
         // phase 2: block row r (tiles t < nt) and block column r
@@ -187,9 +190,9 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
                 q += (q >= r) ? 1 : 0;
                 const int64_t o = (int64_t)q * BS;
                 if (is_row)
-                    BTile<Ar>::run(sm.wave[wave], X, ldp, r0, o, r0, BS, ar);
+                    BTile<Ar>::run(sm.wave[wave], X, ldp, r0, o, r0, kc, ar);
                 else
-                    BTile<Ar>::run(sm.wave[wave], X, ldp, o, r0, r0, BS, ar);
+                    BTile<Ar>::run(sm.wave[wave], X, ldp, o, r0, r0, kc, ar);
             }
         } else {
             for (int t = 0; t < 2 * nt; ++t) {
@@ -199,9 +202,9 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
                 const int64_t o = (int64_t)q * BS;
                 const int64_t crow = is_row ? r0 : o, ccol = is_row ? o : r0;
                 if constexpr (CFG == kGroupTiles64)
-                    GTile64<Ar>::run(sm.g64, X, ldp, crow, ccol, r0, BS, ar);
+                    GTile64<Ar>::run(sm.g64, X, ldp, crow, ccol, r0, kc, ar);
                 else
-                    GTile128<Ar>::run(sm.g128, X, ldp, crow, ccol, r0, BS, ar);
+                    GTile128<Ar>::run(sm.g128, X, ldp, crow, ccol, r0, kc, ar);
             }
         }
         __syncthreads();
@@ -211,7 +214,7 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
                 int ti = t / nt, tj = t - (t / nt) * nt;
                 ti += (ti >= r) ? 1 : 0;
                 tj += (tj >= r) ? 1 : 0;
-                BTile<Ar>::run(sm.wave[wave], X, ldp, (int64_t)ti * BS, (int64_t)tj * BS, r0, BS, ar);
+                BTile<Ar>::run(sm.wave[wave], X, ldp, (int64_t)ti * BS, (int64_t)tj * BS, r0, kc, ar);
             }
         } else {
             for (int t = 0; t < nt * nt; ++t) {
@@ -219,9 +222,9 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
                 ti += (ti >= r) ? 1 : 0;
                 tj += (tj >= r) ? 1 : 0;
                 if constexpr (CFG == kGroupTiles64)
-                    GTile64<Ar>::run(sm.g64, X, ldp, (int64_t)ti * BS, (int64_t)tj * BS, r0, BS, ar);
+                    GTile64<Ar>::run(sm.g64, X, ldp, (int64_t)ti * BS, (int64_t)tj * BS, r0, kc, ar);
                 else
-                    GTile128<Ar>::run(sm.g128, X, ldp, (int64_t)ti * BS, (int64_t)tj * BS, r0, BS, ar);
+                    GTile128<Ar>::run(sm.g128, X, ldp, (int64_t)ti * BS, (int64_t)tj * BS, r0, kc, ar);
             }
         }
         __syncthreads();

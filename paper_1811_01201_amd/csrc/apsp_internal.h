@@ -668,11 +668,13 @@ __device__ __forceinline__ bool phase1_steps(P1Regs<Ar, BS, TT> &c, int ksteps, 
     return big;
 }
 
-// Closes the BS x BS diagonal block at (r0, r0) of D in place.
+// Closes the BS x BS diagonal block at (r0, r0) of D in place, through its
+// first ksteps vertices (a multiple of 16; fewer than BS only when the rest
+// are isolated padding vertices, which cannot shorten any path).
 template <class Ar, int BS, bool WAVE = false, int TT = 8>
 __device__ __forceinline__ void phase1_body(typename Ar::T *__restrict__ D, int64_t ld, int64_t r0,
                                             const Ar &ar, typename Ar::T (*colbuf)[BS],
-                                            typename Ar::T (*rowbuf)[BS]) {
+                                            typename Ar::T (*rowbuf)[BS], int ksteps = BS) {
     using T = typename Ar::T;
     constexpr int TM1 = P1S<Ar, BS, TT>::TM1, TN1 = P1S<Ar, BS, TT>::TN1, TX = P1S<Ar, BS, TT>::TX;
     constexpr int VW = Ar::VW;
@@ -687,7 +689,7 @@ __device__ __forceinline__ void phase1_body(typename Ar::T *__restrict__ D, int6
 #pragma unroll
         for (int g = 0; g < TN1 / VW; ++g)
             ld16(base + ((uint32_t)(ty * TM1 + m) * ldu + tx * TN1 + g * VW), &c[m][g * VW]);
-    const bool big = phase1_steps<Ar, BS, WAVE, TT>(c, BS, ar, colbuf, rowbuf);
+    const bool big = phase1_steps<Ar, BS, WAVE, TT>(c, ksteps, ar, colbuf, rowbuf);
     if constexpr (Ar::kWatch) {
         if (big || any_big(ar, c)) ar.raise();
     }
