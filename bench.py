@@ -114,7 +114,7 @@ def sweep_leg(sizes, modes):
 
 def batched_leg(replays: int):
     """4096 graphs (n uniform in [16, 512], p uniform in [0.05, 0.9], int32
-    weights 1..1000) in one fused launch per replay, against the same graphs
+    weights 1..1000) in the plan's fused launches per replay, against the same graphs
     solved one apsp_solve launch sequence per graph on one stream."""
     import numpy as np
     import torch
@@ -152,7 +152,7 @@ def batched_leg(replays: int):
     plan.destroy()
     return {
         "workload": "4096 graphs, n uniform int [16,512], edge prob uniform [0.05,0.9], int32 w in [1,1000], "
-                    "packed ragged, one fused launch",
+                    "packed ragged, fused launches (int32-arithmetic graphs, then float32-arithmetic graphs)",
         "solves_per_s": round(4096 / (med / 1e3), 1),
         "batch_ms_median": round(med, 3),
         "batch_ms_p99": round(float(np.percentile(times, 99)), 3),
@@ -181,7 +181,7 @@ def serving_leg(count: int):
 
     def run(rate, n_req, fifo=False):
         reqs = synth.requests(n_req, rate if rate else 1e9)
-        kw = dict(max_inflight=1, batch_max_n=-1) if fifo else dict(max_inflight=64, n_streams=4)
+        kw = dict(max_inflight=1, batch_max_n=-1) if fifo else dict(max_inflight=64, n_streams=8)
         sv = apsp.Server(**kw)
         tickets = []
         done = threading.Event()
@@ -338,7 +338,7 @@ def main():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--batched-replays", type=int, default=10)
-    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-requests", type=int, default=2000)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

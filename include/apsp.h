@@ -313,7 +313,7 @@ typedef struct apsp_server apsp_server_t;
 typedef struct {
     int64_t hbm_budget_bytes; /* device bytes the server may hold (0 = 1/2 of free memory) */
     int32_t max_inflight;     /* requests resident at once (0 = 64) */
-    int32_t n_streams;        /* HIP streams used for large requests (0 = 4) */
+    int32_t n_streams;        /* HIP streams used for large requests (0 = 8) */
     int32_t max_queue;        /* pending requests before submit fails (0 = 4096) */
     int32_t batch_max_n;      /* requests with n <= this are coalesced into batched launches
                                  (0 = 512, negative = never; at most 1024) */

@@ -384,7 +384,7 @@ apsp_status_t apsp_server_create(const apsp_server_config_t *config, apsp_server
         cfg.hbm_budget_bytes = (int64_t)(free_b / 2);
     }
     if (cfg.max_inflight == 0) cfg.max_inflight = 64;
-    if (cfg.n_streams == 0) cfg.n_streams = 4;
+    if (cfg.n_streams == 0) cfg.n_streams = 8;
     if (cfg.max_queue == 0) cfg.max_queue = 4096;
     if (cfg.batch_max_n == 0) cfg.batch_max_n = 512;
     if (cfg.batch_max_n < 0) cfg.batch_max_n = 0;  // never coalesce

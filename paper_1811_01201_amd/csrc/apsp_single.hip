@@ -34,6 +34,9 @@
 #ifndef P3_KEY_DMA
 #define P3_KEY_DMA 1
 #endif
+#ifndef P3_KEY_KC
+#define P3_KEY_KC 16
+#endif
 #ifndef P3_REST_CHUNKS
 #define P3_REST_CHUNKS 2
 #endif
@@ -206,7 +209,8 @@ phase3_kernel(void *X, int64_t ld, int r, int per_xcd, int seq0, int seq_end, Ar
               const int32_t *__restrict__ mode, const int32_t *__restrict__ skip) {
     constexpr int set = SET;
 #if P3_DMA
-    using TP = std::conditional_t<sizeof(typename Ar::T) == 4 || P3_KEY_DMA, TileProductDMA<Ar, MT, MT, 16, TT, TT>,
+    using TP = std::conditional_t<sizeof(typename Ar::T) == 4 || P3_KEY_DMA,
+                                  TileProductDMA<Ar, MT, MT, (sizeof(typename Ar::T) == 4 ? 16 : P3_KEY_KC), TT, TT>,
                                   TileProduct<Ar, MT, MT, 16, TT, TT>>;
 #else
     using TP = TileProduct<Ar, MT, MT, (sizeof(typename Ar::T) == 4 ? P3_KC : 16), TT, TT>;
