@@ -297,6 +297,34 @@ def test_full_size_n32768_potential_sampled_rows(orc):
     torch.cuda.empty_cache()
 
 
+def test_maximum_size_n65536(orc):
+    """n = 65536, the largest size the library accepts (the paper's largest),
+    potential weights with negative edges: one sampled row against the row
+    oracle exactly, plus the zero diagonal and D <= W on every element."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe("single n=65536 maximum size")
+    n = 65536
+    W = synth.potential_int32(n, p=0.05, seed=synth.BASE_SEED + 7)
+    d = torch.from_numpy(W).cuda()
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    apsp.solve(d, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    src = 40000
+    dr, _, s = orc.row(W, src)
+    assert s == 0
+    got = d[src].cpu().numpy()
+    assert np.array_equal(got, dr), first_mismatch(got[None], dr[None])
+    assert bool((torch.diagonal(d) == 0).all())
+    for r0 in range(0, n, 4096):
+        w = torch.from_numpy(W[r0:r0 + 4096]).cuda()
+        assert bool((d[r0:r0 + 4096] <= w).all()), r0
+    del d
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("n", [100, 257])
 def test_half_integer_float32_pred_exact(orc, n):
     """Non-integer weights switch predecessor solves to (distance, predecessor)
