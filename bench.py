@@ -230,6 +230,20 @@ def serving_leg(count: int):
     return out
 
 
+def device_state():
+    """Clock, temperature and power right after the timed region (through
+    torch's SMI bindings; None where unavailable)."""
+    import torch
+    out = {"name": torch.cuda.get_device_name(0)}
+    for key, fn in (("clock_mhz", "clock_rate"), ("temperature_c", "temperature"), ("power_w", "power_draw")):
+        try:
+            v = getattr(torch.cuda, fn)(0)
+            out[key] = round(v / 1000.0, 1) if key == "power_w" and v > 1000 else v
+        except Exception:
+            out[key] = None
+    return out
+
+
 def single_leg(args, n):
     """Timed single-graph solves; returns (host weights, JSON fields)."""
     import torch
@@ -268,6 +282,7 @@ def single_leg(args, n):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = apsp.profile_end()
+    dev_state = device_state()
     t = e0.elapsed_time(e1) / 1e3
     ms_per_step = t / args.steps * 1e3
     gops = 2.0 * n ** 3 * args.steps / t / 1e9
@@ -319,7 +334,7 @@ def single_leg(args, n):
     torch.cuda.empty_cache()
     return W, {"value": round(gops, 2), "ms_per_step": round(ms_per_step, 3), "wall_s": round(wall, 3),
                "dtype": "f32" if int(arith_used.item()) == 1 else "int32",
-               "roofline": roofline, "phases": phases}
+               "roofline": roofline, "phases": phases, "device": dev_state}
 
 
 def main():

@@ -322,27 +322,41 @@ __global__ void f32w_init_kernel(int32_t *words) {
 // Converts the caller's int32 weights into the ld x ld float32 work matrix
 // (INF -> +inf, padding vertices isolated); weights of magnitude >= 2^23 set
 // words[0] right away.
+// Row-wise element loops: blockIdx.y strides rows, each thread four
+// consecutive columns (ld is a multiple of the block size, so of 4).
+__device__ __forceinline__ float f32w_in_one(int32_t w, bool &big) {
+    if (w == kInf32) return __builtin_inff();
+    big |= (w >= (1 << 23) || w <= -(1 << 23));
+    return (float)w;
+}
+
+// vec: the caller's rows start on 16-byte boundaries (n % 4 == 0, aligned W)
 __global__ void f32w_in_kernel(const int32_t *__restrict__ W, int64_t n, float *__restrict__ X, int64_t ld,
-                               int32_t *__restrict__ words, const int32_t *__restrict__ skip) {
+                               int32_t *__restrict__ words, const int32_t *__restrict__ skip, int vec) {
     if (skip && *skip != APSP_SUCCESS) return;
-    const int64_t total = ld * ld;
     bool big = false;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / ld, j = e - i * ld;
-        float v;
-        if (i < n && j < n) {
-            const int32_t w = W[i * n + j];
-            if (w == kInf32) {
-                v = __builtin_inff();
+    for (int64_t i = blockIdx.y; i < ld; i += gridDim.y) {
+        for (int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; j < ld;
+             j += (int64_t)gridDim.x * blockDim.x * 4) {
+            float v[4];
+            if (vec && i < n && j + 4 <= n) {
+                const int4 w = *reinterpret_cast<const int4 *>(W + i * n + j);
+                v[0] = f32w_in_one(w.x, big);
+                v[1] = f32w_in_one(w.y, big);
+                v[2] = f32w_in_one(w.z, big);
+                v[3] = f32w_in_one(w.w, big);
             } else {
-                v = (float)w;
-                big |= (w >= (1 << 23) || w <= -(1 << 23));
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t jj = j + q;
+                    if (i < n && jj < n)
+                        v[q] = f32w_in_one(W[i * n + jj], big);
+                    else
+                        v[q] = (i == jj) ? 0.0f : __builtin_inff();  // padding vertices are isolated
+                }
             }
-        } else {
-            v = (i == j) ? 0.0f : __builtin_inff();
+            *reinterpret_cast<float4 *>(X + i * ld + j) = make_float4(v[0], v[1], v[2], v[3]);
         }
-        X[e] = v;
     }
     if (big) words[0] = 1;
 }
@@ -351,17 +365,29 @@ __global__ void f32w_in_kernel(const int32_t *__restrict__ W, int64_t n, float *
 // write it back (+inf -> INF) and report a negative diagonal.
 __global__ void f32w_out_kernel(const float *__restrict__ X, int64_t ld, int32_t *__restrict__ out, int64_t n,
                                 int32_t *__restrict__ status, const int32_t *__restrict__ words,
-                                const int32_t *__restrict__ skip) {
+                                const int32_t *__restrict__ skip, int vec) {
     if (skip && *skip != APSP_SUCCESS) return;
     if (words[0]) return;
-    const int64_t total = n * n;
     bool neg = false;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / n, j = e - i * n;
-        const float v = X[i * ld + j];
-        if (i == j && v < 0.0f) neg = true;
-        out[e] = (v == __builtin_inff()) ? kInf32 : (int32_t)v;
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+        for (int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; j < n;
+             j += (int64_t)gridDim.x * blockDim.x * 4) {
+            const float4 x = *reinterpret_cast<const float4 *>(X + i * ld + j);  // j + 3 < ld
+            const float v[4] = {x.x, x.y, x.z, x.w};
+            int32_t o[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                o[q] = (v[q] == __builtin_inff()) ? kInf32 : (int32_t)v[q];
+                if (i == j + q && v[q] < 0.0f) neg = true;
+            }
+            if (vec && j + 4 <= n) {
+                *reinterpret_cast<int4 *>(out + i * n + j) = make_int4(o[0], o[1], o[2], o[3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (j + q < n) out[i * n + j + q] = o[q];
+            }
+        }
     }
     if (neg && status) *status = APSP_ERROR_NEGATIVE_CYCLE;
 }
@@ -559,6 +585,14 @@ struct ProfScope {
         g_prof.push_back(rec);
     }
 };
+
+// Grid of the row-wise element kernels over a rows x cols region (4
+// columns per thread, 256 threads per block).
+inline dim3 grid_rows(int64_t rows, int64_t cols) {
+    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>((cols / 4 + 255) / 256, 64));
+    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(rows, 8192 / gx));
+    return dim3((unsigned)gx, (unsigned)gy);
+}
 
 inline int grid_for(int64_t elems, int per_block = 256) {
     int64_t g = (elems + per_block - 1) / per_block;
@@ -778,14 +812,15 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
             float *Xf = (float *)w;
             int32_t *words = (int32_t *)((char *)w + mat);
             hipLaunchKernelGGL(f32w_init_kernel, dim3(1), dim3(1), 0, s, words);
-            hipLaunchKernelGGL(f32w_in_kernel, dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n, Xf, ld, words,
-                               skip);
+            const int vec = (n % 4 == 0) && ((uintptr_t)dist % 16 == 0);
+            hipLaunchKernelGGL(f32w_in_kernel, grid_rows(ld, ld), dim3(256), 0, s, dist, n, Xf, ld, words, skip,
+                               vec);
             ArF32W arw;
             arw.big = words;
             st = run_rounds_bs<ArF32W>(bs, tt, lookahead, Xf, ld, arw, s, skip);
             if (st != APSP_SUCCESS) return st;
-            hipLaunchKernelGGL(f32w_out_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, Xf, ld, dist, n, status,
-                               words, skip);
+            hipLaunchKernelGGL(f32w_out_kernel, grid_rows(n, n), dim3(256), 0, s, Xf, ld, dist, n, status, words,
+                               skip, vec);
             hipLaunchKernelGGL(f32w_gate_kernel, dim3(1), dim3(1), 0, s, words, skip, opt.d_arith);
             const int32_t *gate = words + 1;
             int32_t *Xi = dist;
