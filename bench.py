@@ -237,8 +237,7 @@ def device_state():
     out = {"name": torch.cuda.get_device_name(0)}
     for key, fn in (("clock_mhz", "clock_rate"), ("temperature_c", "temperature"), ("power_w", "power_draw")):
         try:
-            v = getattr(torch.cuda, fn)(0)
-            out[key] = round(v / 1000.0, 1) if key == "power_w" and v > 1000 else v
+            out[key] = getattr(torch.cuda, fn)(0)  # ROCm builds read these through amd-smi (W, MHz, C)
         except Exception:
             out[key] = None
     return out
