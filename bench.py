@@ -11,7 +11,7 @@ resident in HBM before the timed region starts.
 
 Metric: min-plus GOPS = 2 n^3 / t (one add and one min per (i, j, k)).
 One JSON line is printed (see the fields below); ``--gpus`` above 1 is
-refused: this build measures one GPU.
+refused: the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -356,7 +356,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures a single GPU: this build has no multi-GPU path "
+        print("bench.py measures a single GPU: there is no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
