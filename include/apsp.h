@@ -208,6 +208,20 @@ apsp_status_t apsp_release_workspace(void);
 apsp_status_t apsp_paths(const int32_t *pred, int64_t n, const int32_t *src, const int32_t *dst, int32_t q,
                          int32_t *paths, int32_t max_len, int32_t *lengths, hipStream_t stream);
 
+/* The paper's form of the path matrix (Section "Floyd-Warshall Algorithm":
+ * P holds an intermediate vertex of the shortest path, from which the path
+ * is rebuilt recursively), derived from the canonical predecessor matrix:
+ * out(i, j) = pred(i, j) when that is an intermediate vertex (not i), else
+ * APSP_NO_PRED (direct edge, i == j, or unreachable).  Rebuilding
+ * path(i, j) = path(i, out(i, j)) + path(out(i, j), j) yields a shortest
+ * path (sub-paths of shortest paths are shortest; with ties the second half
+ * may differ from the one apsp_paths reads), in at most 2n - 3 calls.  The
+ * paper's matrix records the most recently added intermediate vertex, which
+ * depends on the evaluation order; this one does not.  pred, out: device
+ * n x n int32 (out may equal pred).
+ */
+apsp_status_t apsp_pred_to_intermediate(const int32_t *pred, int64_t n, int32_t *out, hipStream_t stream);
+
 /* ----------------------------------------------------------------- batched
  *
  * Many independent graphs of uneven size, solved by one persistent fused

@@ -118,6 +118,7 @@ def _bind_optional(L):
         "apsp_batch_autotune": ([c_int, i32, i32, i32, ctypes.POINTER(ctypes.c_double)], c_int),
         "apsp_batch_autotune_sizes": ([vp, i32, c_int, i32, i32, ctypes.POINTER(ctypes.c_double)], c_int),
         "apsp_paths": ([vp, i64, vp, vp, i32, vp, i32, vp, vp], c_int),
+        "apsp_pred_to_intermediate": ([vp, i64, vp, vp], c_int),
         "apsp_batch_config": ([i64, c_int, i32], i32),
         "apsp_tune_save": ([ctypes.c_char_p], c_int),
         "apsp_tune_load": ([ctypes.c_char_p], c_int),
@@ -212,6 +213,20 @@ def paths(pred, src, dst, max_len: int, stream=None, check=True):
     if check and st != SUCCESS:
         raise APSPError(st, "apsp_paths")
     return out, lengths
+
+
+def pred_to_intermediate(pred, out=None, stream=None, check=True):
+    """The paper's intermediate-vertex path matrix from a canonical
+    predecessor matrix (device tensors; see apsp_pred_to_intermediate)."""
+    import torch
+    assert pred.dim() == 2 and pred.shape[0] == pred.shape[1] and pred.dtype == torch.int32
+    assert pred.is_cuda and pred.is_contiguous()
+    if out is None:
+        out = torch.empty_like(pred)
+    st = lib().apsp_pred_to_intermediate(pred.data_ptr(), pred.shape[0], out.data_ptr(), _stream_ptr(stream))
+    if check and st != SUCCESS:
+        raise APSPError(st, "apsp_pred_to_intermediate")
+    return out
 
 
 def solve_raw(dist_ptr, pred_ptr, n, dtype_code, stream_ptr, options: Options | None = None) -> int:

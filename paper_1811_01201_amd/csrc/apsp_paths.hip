@@ -9,6 +9,8 @@
 // produced by apsp_solve cannot make a thread loop or write out of bounds.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "apsp_internal.h"
 
 namespace apsp {
@@ -53,9 +55,35 @@ __global__ void paths_kernel(const int32_t *__restrict__ pred, int64_t n, const 
     lengths[t] = len;
 }
 
+// The paper's form of the path matrix (Section "Floyd-Warshall Algorithm"):
+// an intermediate vertex of a shortest i -> j path, -1 when the path is the
+// direct edge (or i == j, or j unreachable), so that a path is rebuilt
+// recursively as path(i, m) + path(m, j).  From the canonical predecessor:
+// pred(i, j) lies on a shortest i -> j path and is intermediate unless it is
+// i itself.
+__global__ void intermediate_kernel(const int32_t *__restrict__ pred, int64_t n, int32_t *__restrict__ out) {
+    const int64_t total = n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n;
+        const int32_t p = pred[e];
+        out[e] = (p < 0 || p == i) ? APSP_NO_PRED : p;
+    }
+}
+
 }  // namespace apsp
 
 using namespace apsp;
+
+extern "C" apsp_status_t apsp_pred_to_intermediate(const int32_t *pred, int64_t n, int32_t *out,
+                                                   hipStream_t stream) {
+    if (n < 0 || n > kMaxN) return APSP_ERROR_INVALID_ARGUMENT;
+    if (n == 0) return APSP_SUCCESS;
+    if (!pred || !out) return APSP_ERROR_INVALID_ARGUMENT;
+    const int64_t blocks = std::min<int64_t>((n * n + 255) / 256, 8192);
+    hipLaunchKernelGGL(intermediate_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, pred, n, out);
+    return hipGetLastError() == hipSuccess ? APSP_SUCCESS : APSP_ERROR_HIP;
+}
 
 extern "C" apsp_status_t apsp_paths(const int32_t *pred, int64_t n, const int32_t *src, const int32_t *dst,
                                     int32_t q, int32_t *paths, int32_t max_len, int32_t *lengths,

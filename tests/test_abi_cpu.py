@@ -142,3 +142,11 @@ def test_paths_host_argument_errors():
     assert L.apsp_paths(None, 10, fake, fake, 3, fake, 4, fake, None) == apsp.INVALID_ARGUMENT
     assert L.apsp_paths(fake, 70000, fake, fake, 3, fake, 4, fake, None) == apsp.INVALID_ARGUMENT
     assert L.apsp_paths(None, 10, None, None, 0, None, 4, None, None) == apsp.SUCCESS  # nothing to do
+
+
+def test_pred_to_intermediate_host_argument_errors():
+    L = apsp.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.apsp_pred_to_intermediate(None, 10, fake, None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_pred_to_intermediate(fake, -1, fake, None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_pred_to_intermediate(None, 0, None, None) == apsp.SUCCESS

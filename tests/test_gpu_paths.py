@@ -89,3 +89,49 @@ def test_paths_broken_matrix_is_reported():
     paths, lengths = apsp.paths(p, src, dst, n)
     torch.cuda.synchronize()
     assert lengths.cpu().tolist() == [apsp.PATH_BROKEN, apsp.PATH_BROKEN, 0]
+
+
+def _rebuild(Pm, i, j, calls):
+    """Recursive rebuild from an intermediate-vertex matrix (the paper's form)."""
+    calls[0] += 1
+    assert calls[0] <= 2 * Pm.shape[0]
+    m = int(Pm[i, j])
+    if m < 0:
+        return [i, j]
+    left = _rebuild(Pm, i, m, calls)
+    right = _rebuild(Pm, m, j, calls)
+    return left + right[1:]
+
+
+@pytest.mark.parametrize("kind", ["int", "pot"])
+def test_intermediate_vertex_matrix_rebuilds_shortest_paths(orc, kind):
+    """The paper's form of P: recursive rebuilding terminates within 2n - 3
+    calls and gives a path of edges whose weights add up to the oracle's
+    distance, ending with the same last hop as the canonical predecessor."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe(f"paths intermediate matrix {kind}")
+    n = 200
+    W = synth.single_int32(n, p=0.03, seed=51) if kind == "int" else synth.potential_int32(n, p=0.03, seed=52)
+    d = torch.from_numpy(W).cuda()
+    p = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    apsp.solve(d, p)
+    Pm = apsp.pred_to_intermediate(p).cpu().numpy()
+    D0, P0, _ = orc.fw(W, pred=True)
+    rng = np.random.default_rng(3)
+    src = rng.integers(0, n, 500).astype(np.int32)
+    dst = rng.integers(0, n, 500).astype(np.int32)
+    paths, lengths = apsp.paths(p, torch.from_numpy(src), torch.from_numpy(dst), n)
+    paths, lengths = paths.cpu().numpy(), lengths.cpu().numpy()
+    for t in range(500):
+        i, j = int(src[t]), int(dst[t])
+        if i == j or D0[i, j] >= INF32:
+            assert Pm[i, j] == -1
+            continue
+        rebuilt = _rebuild(Pm, i, j, [0])
+        assert rebuilt[0] == i and rebuilt[-1] == j
+        assert all(W[rebuilt[h], rebuilt[h + 1]] != INF32 for h in range(len(rebuilt) - 1))
+        assert sum(W[rebuilt[h], rebuilt[h + 1]] for h in range(len(rebuilt) - 1)) == D0[i, j]
+        assert rebuilt[-2] == paths[t, lengths[t] - 2]  # the canonical last hop
+    assert np.array_equal(Pm, np.where((P0 < 0) | (P0 == np.arange(n)[:, None]), -1, P0))
