@@ -150,3 +150,9 @@ def test_pred_to_intermediate_host_argument_errors():
     assert L.apsp_pred_to_intermediate(None, 10, fake, None) == apsp.INVALID_ARGUMENT
     assert L.apsp_pred_to_intermediate(fake, -1, fake, None) == apsp.INVALID_ARGUMENT
     assert L.apsp_pred_to_intermediate(None, 0, None, None) == apsp.SUCCESS
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "single GPU" in r.stderr

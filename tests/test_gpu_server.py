@@ -160,3 +160,23 @@ def test_borrowed_strided_submission():
             Da, _, _ = gpu_solve(np.ascontiguousarray(base.numpy()[:n, :n]))
             assert np.array_equal(D, Da)
             sv.release(t)
+
+
+def test_large_int32_request_float32_arithmetic(orc):
+    """An int32 request above n = 4096 runs in float32 arithmetic inside the
+    server (work memory from the server's budget): equal to the solo solve
+    and to the row oracle."""
+    import paper_1811_01201_amd as apsp
+    describe("server large int32 request")
+    n = 5000
+    W = synth.potential_int32(n, p=0.05, seed=61)
+    with apsp.Server() as sv:
+        t = sv.submit(W)
+        assert sv.wait(t, timeout_us=60_000_000) == apsp.SUCCESS
+        D, _ = sv.result(t)
+        sv.release(t)
+    Da, _, st = gpu_solve(W)
+    assert st == 0 and np.array_equal(D, Da)
+    for src in (0, n - 1):
+        dr, _, s = orc.row(W, src)
+        assert s == 0 and np.array_equal(D[src], dr)
