@@ -243,10 +243,6 @@ template <class Ar, class Tin>
 __device__ void team_dispatch(int cfg, const Ar &ar, Tin *__restrict__ dist, int32_t *__restrict__ pred,
                               int32_t *__restrict__ status, int g, int64_t n, int64_t off,
                               typename Ar::T *__restrict__ X, TeamSmem<Ar> &sm) {
-#ifdef BATCH_ONLY_CFG
-    team_solve<Ar, Tin, BATCH_ONLY_CFG>(ar, dist, pred, status, g, n, off, X, sm);
-    return;
-#endif
     if (cfg == kGroupTiles64)
         team_solve<Ar, Tin, kGroupTiles64>(ar, dist, pred, status, g, n, off, X, sm);
     else if (cfg == kGroupTiles128)

@@ -430,9 +430,6 @@ __device__ __forceinline__ int tile_tid() {
 // the workgroup owns every C element that its reads could see (the panel
 // updates use a tile that spans the whole k-block in that direction).
 // ---------------------------------------------------------------------------
-#ifndef KG_UNROLL
-#define KG_UNROLL 1
-#endif
 
 template <class Ar, int MT, int NT, int KC, int TM, int TN, bool WAVE = false>
 struct TileProduct {
@@ -535,7 +532,7 @@ struct TileProduct {
             if (more) load_chunk(Abase + (ch + 1) * KC, Bbase + (uint32_t)((ch + 1) * KC) * ld, ld, ra, rb);
             const T *As = sm.a[buf];
             const T *Bs = sm.b[buf];
-#pragma unroll KG_UNROLL
+#pragma unroll 1
             for (int kg = 0; kg < KC; kg += VW) {
                 T a[TM][VW];
 #pragma unroll

@@ -19,27 +19,12 @@
 
 #include "apsp_internal.h"
 
-#ifndef P3_WAVES
-#define P3_WAVES 3
-#endif
-#ifndef P3_KC
-#define P3_KC 16
-#endif
-#ifndef P3_DMA
-#define P3_DMA 1
-#endif
-#ifndef P3_WAVES8
-#define P3_WAVES8 2
-#endif
-#ifndef P3_KEY_DMA
-#define P3_KEY_DMA 1
-#endif
-#ifndef P3_KEY_KC
-#define P3_KEY_KC 16
-#endif
-#ifndef P3_REST_CHUNKS
-#define P3_REST_CHUNKS 2
-#endif
+// Launch tuning (measured on MI355X): phase-3 waves per SIMD for 4-byte
+// elements on 128 x 128 tiles (163 VGPRs) and for 8-byte keys; kRest
+// launches per round under the two-stream schedule.
+constexpr int kP3Waves4 = 3;
+constexpr int kP3Waves8 = 2;
+constexpr int kRestChunks = 2;
 
 namespace apsp {
 
@@ -76,16 +61,11 @@ phase1_kernel(void *X, int64_t ld, int64_t r0, Ar ar, Alt alt, const int32_t *__
 // [nt, 2 nt) the column panel; nt = number of P2W-wide tiles outside block r.
 template <class Ar, int BS, int P2W, int TT>
 struct P2 {
-#if P3_DMA
     // 4-byte elements: LDS DMA; 8-byte keys strip A while staging it instead
     using RowT = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, BS, P2W, 16, TT, TT>,
                                     TileProduct<Ar, BS, P2W, 16, TT, TT>>;
     using ColT = std::conditional_t<sizeof(typename Ar::T) == 4, TileProductDMA<Ar, P2W, BS, 16, TT, TT>,
                                     TileProduct<Ar, P2W, BS, 16, TT, TT>>;
-#else
-    using RowT = TileProduct<Ar, BS, P2W, 16, TT, TT>;
-    using ColT = TileProduct<Ar, P2W, BS, 16, TT, TT>;
-#endif
     static_assert(RowT::NTH == ColT::NTH, "both panel shapes use one block size");
     union Smem {
         typename RowT::Smem row;
@@ -204,28 +184,19 @@ __device__ __forceinline__ bool phase3_tile(int set, int r, int nt, int pb, int 
 
 template <class Ar, class Alt, int BS, int MT, int SET, int TT>
 __global__ void __launch_bounds__((MT / TT) * (MT / TT))
-__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? (MT == 128 ? P3_WAVES : 2) : P3_WAVES8)))
+__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? (MT == 128 ? kP3Waves4 : 2) : kP3Waves8)))
 phase3_kernel(void *X, int64_t ld, int r, int per_xcd, int seq0, int seq_end, Ar ar, Alt alt,
               const int32_t *__restrict__ mode, const int32_t *__restrict__ skip) {
     constexpr int set = SET;
-#if P3_DMA
-    using TP = std::conditional_t<sizeof(typename Ar::T) == 4 || P3_KEY_DMA,
-                                  TileProductDMA<Ar, MT, MT, (sizeof(typename Ar::T) == 4 ? 16 : P3_KEY_KC), TT, TT>,
-                                  TileProduct<Ar, MT, MT, 16, TT, TT>>;
-#else
-    using TP = TileProduct<Ar, MT, MT, (sizeof(typename Ar::T) == 4 ? P3_KC : 16), TT, TT>;
-#endif
+    // LDS DMA staging (8-byte keys: stripped in LDS after each chunk arrives)
+    using TP = TileProductDMA<Ar, MT, MT, 16, TT, TT>;
     if (skip && *skip != APSP_SUCCESS) return;
     int64_t crow, ccol;
     if (!phase3_tile(set, r, (int)(ld / MT), BS / MT, per_xcd, seq0, seq_end, MT, crow, ccol)) return;
     const int64_t r0 = (int64_t)r * BS;
     if constexpr (!std::is_same_v<Alt, NoAlt>) {
-#if P3_DMA
         using TQ = std::conditional_t<sizeof(typename Alt::T) == 4, TileProductDMA<Alt, MT, MT, 16, TT, TT>,
                                       TileProduct<Alt, MT, MT, 16, TT, TT>>;
-#else
-        using TQ = TileProduct<Alt, MT, MT, (sizeof(typename Alt::T) == 4 ? P3_KC : 16), TT, TT>;
-#endif
         __shared__ union {
             typename TP::Smem a;
             typename TQ::Smem b;
@@ -640,7 +611,7 @@ apsp_status_t aux_stream(int dev, hipStream_t s, AuxStream **out) {
 // kCross(r+1) touches tiles last written by kRest(r), hence its wait.
 // A phase-1 workgroup needs most of a compute unit's registers, so it only
 // starts where kRest's workgroups drain; kRest is therefore issued as
-// P3_REST_CHUNKS launches, whose boundaries let the caller stream's kernels
+// kRestChunks launches, whose boundaries let the caller stream's kernels
 // in (2 measured best: about 1.4 % at n = 32768, 6 % at n = 16384).
 template <class Ar, class Alt, int BS, int TT>
 apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, const int32_t *mode,
@@ -689,11 +660,11 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
                                per_xcd, a, b, ar, alt, mode, skip);
     };
     auto p3 = [&](int r, int set, hipStream_t st) { p3_part(r, set, st, 0, p3_count(set, nt, pb)); };
-    // kRest in P3_REST_CHUNKS launches: between them the caller stream's
+    // kRest in kRestChunks launches: between them the caller stream's
     // critical-path kernels find free compute units
     auto p3_rest = [&](int r, hipStream_t st) {
         const int64_t total = p3_count(kRest, nt, pb);
-        const int C = P3_REST_CHUNKS;
+        const int C = kRestChunks;
         for (int c = 0; c < C; ++c) p3_part(r, kRest, st, total * c / C, total * (c + 1) / C);
     };
     if (!aux) {
