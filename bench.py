@@ -105,7 +105,8 @@ def sweep_leg(sizes, modes):
                     times.append(e0.elapsed_time(e1))
             t = min(times)
             rows.append({"n": n, "mode": mode, "ms": round(t, 3), "gops": round(2.0 * n ** 3 / (t / 1e3) / 1e9, 1),
-                         "arithmetic": ("fp64 keys" if mode == "f32pred" else
+                         "arithmetic": (("float32 distances + key product (exact)" if int(used.item()) == 1
+                                         else "fp64 keys") if mode == "f32pred" else
                                         "float32 (exact)" if int(used.item()) == 1 else "int32")})
             del pristine, work, pred
             torch.cuda.empty_cache()

@@ -126,17 +126,27 @@ typedef struct {
                               second stream; 1 = one stream, rounds in order */
     int32_t use_graph;     /* nonzero: capture the launch sequence once per shape into a
                               hipGraph and replay it (fewer launch gaps for small n) */
-    int32_t arith;         /* int32 distance solves only (ignored otherwise): 0 = automatic
-                              (float32 arithmetic above n = 4096), 1 = int32 arithmetic,
-                              2 = float32 arithmetic at any n.  float32 arithmetic holds
-                              the integers exactly while every operand stays below 2^23 in
-                              magnitude, which the kernels check; if one does not, the
-                              device redoes the solve in int32 arithmetic.  Either way the
-                              result is the exact int32 result. */
+    int32_t arith;         /* Distances only, int32 weights (ignored for float32 weights):
+                              0 = automatic (float32 arithmetic above n = 4096), 1 = int32
+                              arithmetic, 2 = float32 arithmetic at any n.  float32
+                              arithmetic holds the integers exactly while every operand
+                              stays below 2^23 in magnitude, which the kernels check; if one
+                              does not, the device redoes the solve in int32 arithmetic.
+                              Either way the result is the exact int32 result.
+                              With predecessors (either dtype): 0 = automatic (the float32
+                              route above n = 4096), 1 = the exact fp64-key recurrence,
+                              2 = the float32 route at any n: exact float32 distances, then
+                              the canonical predecessors read off one float32 min-plus
+                              product of (D(i,v) 2^S + v) with (W(v,j) 2^S), S = bits of
+                              n - 1.  The device checks that every key involved is exact
+                              (weights and distances small enough, the winning key's
+                              distance equal to D(i,j)); if not, it runs the recurrence on
+                              the original weights instead.  The results are the same. */
     int32_t *d_status;     /* device int32 or NULL: receives APSP_SUCCESS,
                               APSP_ERROR_INVALID_VALUE or APSP_ERROR_NEGATIVE_CYCLE */
     int32_t *d_arith;      /* device int32 or NULL: receives 1 if the result came from float32
-                              arithmetic, 0 if from int32 arithmetic */
+                              arithmetic (with predecessors: the float32 route held), 0 if
+                              from int32 arithmetic (the recurrence) */
 } apsp_options_t;
 
 /* apsp_solve with options (NULL options = defaults = apsp_solve). */
@@ -166,6 +176,7 @@ typedef struct {
                                         round's block row/column under the two-stream schedule) */
     apsp_kernel_time_t other;        /* set-up and wrap-up passes */
     apsp_kernel_time_t phase3_cross; /* two-stream schedule: the next round's block row/column */
+    apsp_kernel_time_t pred_product; /* predecessors read off the float32 key product */
 } apsp_profile_t;
 
 apsp_status_t apsp_profile_begin(void);

@@ -43,7 +43,7 @@ class KernelTime(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("phase1", KernelTime), ("phase2", KernelTime), ("phase3", KernelTime),
-                ("other", KernelTime), ("phase3_cross", KernelTime)]
+                ("other", KernelTime), ("phase3_cross", KernelTime), ("pred_product", KernelTime)]
 
     def as_dict(self):
         out = {}
@@ -164,9 +164,13 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
     status : optional torch.Tensor [1] int32 on the device, receives the
              data-dependent status (required with validate=True).
     arith  : int32 distance solves: 0 automatic, 1 int32 arithmetic, 2 float32
-             arithmetic (exact, checked, int32 redo when needed).
+             arithmetic (exact, checked, int32 redo when needed).  With pred
+             (either dtype): 0 automatic, 1 the fp64-key recurrence, 2 float32
+             distances + the predecessor key product (exact, checked, the
+             recurrence when needed).
     arith_used : optional torch.Tensor [1] int32 on the device, receives 1 if the
-             result came from float32 arithmetic, else 0.
+             result came from float32 arithmetic (with pred: the product held),
+             else 0.
     Returns the host status of the enqueue (raises APSPError unless check=False).
     """
     assert dist.dim() == 2 and dist.shape[0] == dist.shape[1], "dist must be square"

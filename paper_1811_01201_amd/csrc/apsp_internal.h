@@ -348,6 +348,26 @@ struct TileProductDMA {
         }
     }
 
+    // c <- min(c, A (x) B) over kcount (a multiple of 2 KC) columns of A /
+    // rows of B, double-buffered through LDS.  B advances by KC rows per
+    // chunk with 64-bit offsets, so K may span a whole matrix.
+    __device__ __forceinline__ static void accumulate(Smem &sm, T (&c)[TM][TN], const T *__restrict__ Abase,
+                                                      const T *__restrict__ Bbase, uint32_t ld, int kcount,
+                                                      int tx, int ty, const Ar &ar) {
+        const int nch = kcount / KC;
+        const int64_t bstep = (int64_t)KC * ld;
+        copy_chunk(sm.a0, sm.b0, Abase, Bbase, ld);
+        copies_done(sm.a0, ar);
+        for (int ch = 0; ch < nch; ch += 2) {
+            copy_chunk(sm.a1, sm.b1, Abase + (ch + 1) * KC, Bbase + (ch + 1) * bstep, ld);
+            compute(c, sm.a0, sm.b0, tx, ty, ar);
+            copies_done(sm.a1, ar);
+            if (ch + 2 < nch) copy_chunk(sm.a0, sm.b0, Abase + (ch + 2) * KC, Bbase + (ch + 2) * bstep, ld);
+            compute(c, sm.a1, sm.b1, tx, ty, ar);
+            if (ch + 2 < nch) copies_done(sm.a0, ar);
+        }
+    }
+
     // WATCH: check the tile's inputs and outputs with the policy (see ArF32W)
     template <bool WATCH = false>
     __device__ __forceinline__ static void run(Smem &sm, T *__restrict__ D, int64_t ld64, int64_t crow,
@@ -367,18 +387,7 @@ struct TileProductDMA {
                 ld16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
         bool big = false;
         if constexpr (WATCH) big = any_big(ar, c);
-        const int nch = kcount / KC;  // even: kcount is a multiple of 2 KC
-        copy_chunk(sm.a0, sm.b0, Abase, Bbase, ld);
-        copies_done(sm.a0, ar);
-        for (int ch = 0; ch < nch; ch += 2) {
-            copy_chunk(sm.a1, sm.b1, Abase + (ch + 1) * KC, Bbase + (uint32_t)((ch + 1) * KC) * ld, ld);
-            compute(c, sm.a0, sm.b0, tx, ty, ar);
-            copies_done(sm.a1, ar);
-            if (ch + 2 < nch)
-                copy_chunk(sm.a0, sm.b0, Abase + (ch + 2) * KC, Bbase + (uint32_t)((ch + 2) * KC) * ld, ld);
-            compute(c, sm.a1, sm.b1, tx, ty, ar);
-            if (ch + 2 < nch) copies_done(sm.a0, ar);
-        }
+        accumulate(sm, c, Abase, Bbase, ld, kcount, tx, ty, ar);
         if constexpr (WATCH && Ar::kWatch) {
             if (big || any_big(ar, c)) ar.raise();
         }

@@ -473,6 +473,282 @@ __global__ void pred_unpack_kernel(const void *__restrict__ Xv, int64_t ld, T *_
     if (neg && status) *status = APSP_ERROR_NEGATIVE_CYCLE;
 }
 
+// ------------------------------------ predecessors from final distances
+// With exact distances D, the canonical predecessor has the closed form
+//     P(i,j) = min{v != j : W(v,j) finite, D(i,v) + W(v,j) = D(i,j)}
+// (the fixed point of the lexicographic recurrence), and
+//     D(i,j) * 2^S + P(i,j) = min_v [(D(i,v) * 2^S + v) + W(v,j) * 2^S]
+// over v != j (S bits hold any vertex).  So a solve that needs predecessors
+// can compute the distances in exact float32 arithmetic (ArF32W) and then
+// read P off one float32 min-plus product of A(i,v) = D(i,v) 2^S + v with
+// B(v,j) = W(v,j) 2^S (B(j,j) = +inf), in place of the fp64-key recurrence.
+// The product is exact when A and B are: every B entry is (|W| < 2^23),
+// and an A entry of magnitude >= 2^24 can only lose when all weights are
+// non-negative (its candidates then stay >= 2^24 above every in-range
+// key).  The winning key must lie below 2^24 in magnitude and its distance
+// part must equal D(i,j).  Anything else raises a word and the device runs
+// the fp64-key recurrence on the original weights instead.
+//
+// words (int32): see kPP* below.  APSP_SUCCESS in kPPGate opens the
+// fallback; APSP_SUCCESS in kPPRounds opens the float32 distance rounds.
+constexpr int kPPBig = 0;       // a watched float32 value reached 2^23 (ArF32W)
+constexpr int kPPGate = 1;      // fallback gate
+constexpr int kPPMode = 2;      // float32 weights not all integers within the bound: pairs
+constexpr int kPPReject = 3;    // a non-zero diagonal entry
+constexpr int kPPNegW = 4;      // some finite off-diagonal weight is negative
+constexpr int kPPPosBig = 5;    // some finite A entry >= 2^24
+constexpr int kPPNegBig = 6;    // some finite A entry <= -2^24
+constexpr int kPPFail = 7;      // the product's check failed for some (i,j)
+constexpr int kPPWritten = 8;   // dist holds distances (the weights must be restored)
+constexpr int kPPSkip = 9;      // the product does not run
+constexpr int kPPRounds = 10;   // gate of the float32 distance rounds
+constexpr int kPPWords = 11;
+
+__global__ void pp_init_kernel(int32_t *words) {
+    for (int q = 0; q < kPPWords; ++q) words[q] = 0;
+    words[kPPGate] = 1;
+    words[kPPRounds] = 1;
+}
+
+template <class T>
+__device__ __forceinline__ void pp_in_one(T w, bool diag, float bound, float scale, float &x, float &b,
+                                          bool &big, bool &mode, bool &reject, bool &negw) {
+    bool fin;
+    float wf;
+    if constexpr (std::is_same_v<T, int32_t>) {
+        fin = w != kInf32;
+        wf = (float)w;
+        if (fin && (w >= (1 << 23) || w <= -(1 << 23))) big = true;
+    } else {
+        fin = w != __builtin_inff();
+        wf = w;
+        if (fin && (w != __builtin_floorf(w) || __builtin_fabsf(w) > bound)) mode = true;  // NaN too
+        if (fin && __builtin_fabsf(w) >= 8388608.0f) big = true;
+    }
+    if (diag) {
+        if (!(w == T(0))) reject = true;
+        x = 0.0f;
+        b = __builtin_inff();
+    } else {
+        x = fin ? wf : __builtin_inff();
+        b = fin ? wf * scale : __builtin_inff();
+        if (fin && wf < 0.0f) negw = true;
+    }
+}
+
+// W (n x n, caller's) -> X (float32 distances to be, ld x ld, padding
+// vertices isolated) and B = W 2^S with +inf on the diagonal and padding.
+template <class T>
+__global__ void pp_in_kernel(const T *__restrict__ W, int64_t n, float *__restrict__ X, float *__restrict__ Bm,
+                             int64_t ld, int S, float bound, int32_t *__restrict__ words,
+                             const int32_t *__restrict__ skip, int vec) {
+    if (skip && *skip != APSP_SUCCESS) return;
+    const float scale = __builtin_ldexpf(1.0f, S);
+    bool big = false, mode = false, reject = false, negw = false;
+    for (int64_t i = blockIdx.y; i < ld; i += gridDim.y) {
+        for (int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; j < ld;
+             j += (int64_t)gridDim.x * blockDim.x * 4) {
+            float x[4], b[4];
+            if (vec && i < n && j + 4 <= n) {
+                T w[4];
+                if constexpr (std::is_same_v<T, int32_t>) {
+                    const int4 v = *reinterpret_cast<const int4 *>(W + i * n + j);
+                    w[0] = v.x, w[1] = v.y, w[2] = v.z, w[3] = v.w;
+                } else {
+                    const float4 v = *reinterpret_cast<const float4 *>(W + i * n + j);
+                    w[0] = v.x, w[1] = v.y, w[2] = v.z, w[3] = v.w;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    pp_in_one<T>(w[q], i == j + q, bound, scale, x[q], b[q], big, mode, reject, negw);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t jj = j + q;
+                    if (i < n && jj < n) {
+                        pp_in_one<T>(W[i * n + jj], i == jj, bound, scale, x[q], b[q], big, mode, reject, negw);
+                    } else {
+                        x[q] = (i == jj) ? 0.0f : __builtin_inff();
+                        b[q] = __builtin_inff();
+                    }
+                }
+            }
+            *reinterpret_cast<float4 *>(X + i * ld + j) = make_float4(x[0], x[1], x[2], x[3]);
+            *reinterpret_cast<float4 *>(Bm + i * ld + j) = make_float4(b[0], b[1], b[2], b[3]);
+        }
+    }
+    if (big) words[kPPBig] = 1;
+    if (mode) words[kPPMode] = 1;
+    if (reject) words[kPPReject] = 1;
+    if (negw) words[kPPNegW] = 1;
+}
+
+// Opens the float32 distance rounds unless the weights already rule the
+// product out (pairs needed, or a non-zero diagonal).
+__global__ void pp_rounds_gate_kernel(int32_t *words, const int32_t *__restrict__ skip) {
+    const bool ok = !(skip && *skip != APSP_SUCCESS);
+    words[kPPRounds] = (ok && !words[kPPMode] && !words[kPPReject]) ? APSP_SUCCESS : 1;
+}
+
+// If the float32 distances are exact: writes them to dist (+inf -> INF for
+// int32), reports a negative diagonal, and turns X into A in place:
+// A(i,v) = X(i,v) 2^S + v (+inf stays +inf; padding columns are +inf).
+template <class T>
+__global__ void pp_out_kernel(float *__restrict__ X, int64_t ld, T *__restrict__ dist, int64_t n, int S,
+                              int32_t *__restrict__ words, int32_t *__restrict__ status,
+                              const int32_t *__restrict__ skip, int vec) {
+    if (skip && *skip != APSP_SUCCESS) return;
+    if (words[kPPBig] || words[kPPRounds] != APSP_SUCCESS) return;
+    bool neg = false, posbig = false, negbig = false;
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+        for (int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; j < n;
+             j += (int64_t)gridDim.x * blockDim.x * 4) {
+            float4 *px = reinterpret_cast<float4 *>(X + i * ld + j);  // j + 3 < ld
+            const float4 xv = *px;
+            const float x[4] = {xv.x, xv.y, xv.z, xv.w};
+            T o[4];
+            float a[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool fin = x[q] != __builtin_inff();
+                if constexpr (std::is_same_v<T, int32_t>)
+                    o[q] = fin ? (int32_t)x[q] : kInf32;
+                else
+                    o[q] = x[q];
+                if (i == j + q && x[q] < 0.0f) neg = true;
+                if (fin) {
+                    const double kd = __builtin_ldexp((double)x[q], S) + (double)(j + q);
+                    posbig |= kd >= 16777216.0;
+                    negbig |= kd <= -16777216.0;
+                    a[q] = (float)kd;
+                } else {
+                    a[q] = __builtin_inff();
+                }
+            }
+            *px = make_float4(a[0], a[1], a[2], a[3]);
+            if (vec && j + 4 <= n) {
+                if constexpr (std::is_same_v<T, int32_t>)
+                    *reinterpret_cast<int4 *>(dist + i * n + j) = make_int4(o[0], o[1], o[2], o[3]);
+                else
+                    *reinterpret_cast<float4 *>(dist + i * n + j) = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (j + q < n) dist[i * n + j + q] = o[q];
+            }
+        }
+    }
+    if (threadIdx.x == 0) words[kPPWritten] = 1;
+    if (posbig) words[kPPPosBig] = 1;
+    if (negbig) words[kPPNegBig] = 1;
+    if (neg && status) *status = APSP_ERROR_NEGATIVE_CYCLE;
+}
+
+// Decides whether the product runs (its keys would be exact).
+__global__ void pp_product_gate_kernel(int32_t *words) {
+    const bool no = words[kPPBig] || words[kPPRounds] != APSP_SUCCESS || words[kPPNegBig] ||
+                    (words[kPPPosBig] && words[kPPNegW]);
+    words[kPPSkip] = no ? 1 : 0;
+}
+
+// P(i,j) from min_v A(i,v) + B(v,j) over v < kcount, 128 x 128 output tiles
+// (the 8 x 8 register blocks and LDS DMA staging of phase 3), tiles grouped
+// 8 rows at a time and split over the XCDs in contiguous stretches.
+template <class T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kP3Waves4)))
+pp_product_kernel(const float *__restrict__ A, const float *__restrict__ Bm, int64_t ld, int kcount,
+                  const T *__restrict__ dist, int32_t *__restrict__ pred, int64_t n, int S, int nt, int per_xcd,
+                  int32_t *__restrict__ words, const int32_t *__restrict__ skip) {
+    using TP = TileProductDMA<ArF32, 128, 128, 16, 8, 8>;
+    static_assert(TP::NTH == 256 && TP::TX == 16 && TP::TY == 16 && TP::GN == 2, "tile shape");
+    if (skip && *skip != APSP_SUCCESS) return;
+    if (words[kPPSkip]) return;
+    constexpr int GROUP = 8;
+    const int w = blockIdx.x;
+    const int seq = (w & 7) * per_xcd + (w >> 3);
+    if (seq >= nt * nt) return;
+    const int group = seq / (GROUP * nt);
+    const int first = group * GROUP;
+    const int rows = min(GROUP, nt - first);
+    const int within = seq - group * GROUP * nt;
+    const int64_t crow = (int64_t)(first + within % rows) * 128;
+    const int64_t ccol = (int64_t)(within / rows) * 128;
+    __shared__ typename TP::Smem sm;
+    const int tx = threadIdx.x % TP::TX, ty = threadIdx.x / TP::TX;
+    float c[8][8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[m][q] = __builtin_inff();
+    TP::accumulate(sm, c, A + crow * ld, Bm + ccol, (uint32_t)ld, kcount, tx, ty, ArF32{});
+    const float down = __builtin_ldexpf(1.0f, -S), up = __builtin_ldexpf(1.0f, S);
+    bool fail = false;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int64_t i = crow + ty + TP::TY * m;
+        if (i >= n) continue;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t j = ccol + (q / 4) * TP::GSTRIDE + tx * 4 + (q % 4);
+            if (j >= n) continue;
+            const T d = dist[i * n + j];
+            bool reach;
+            if constexpr (std::is_same_v<T, int32_t>)
+                reach = d != kInf32;
+            else
+                reach = d != __builtin_inff();
+            int32_t p = APSP_NO_PRED;
+            if (i != j && reach) {
+                const float key = c[m][q];
+                if (__builtin_fabsf(key) < 16777216.0f) {
+                    const float kd = __builtin_floorf(key * down);
+                    if (kd == (float)d)
+                        p = (int32_t)(key - kd * up);
+                    else
+                        fail = true;
+                } else {
+                    fail = true;  // also +inf: no candidate although D(i,j) is finite
+                }
+            }
+            pred[i * n + j] = p;
+        }
+    }
+    if (fail) words[kPPFail] = 1;
+}
+
+// Opens the fp64-key fallback when the product did not run or failed its
+// check; reports the arithmetic that produced the result (1 = float32
+// distances + product, 0 = the exact key recurrence).
+__global__ void pp_gate_kernel(int32_t *words, const int32_t *__restrict__ skip, int32_t *arith_used) {
+    const bool ok = !(skip && *skip != APSP_SUCCESS);
+    const bool redo = ok && (words[kPPSkip] || words[kPPFail]);
+    words[kPPGate] = redo ? APSP_SUCCESS : 1;
+    if (arith_used) *arith_used = (ok && !redo) ? 1 : 0;
+}
+
+// Fallback after dist was overwritten: the weights back from B (exact: every
+// weight was an integer below 2^23), zero diagonal.
+template <class T>
+__global__ void pp_restore_kernel(const float *__restrict__ Bm, int64_t ld, T *__restrict__ dist, int64_t n, int S,
+                                  const int32_t *__restrict__ words) {
+    if (words[kPPGate] != APSP_SUCCESS || !words[kPPWritten]) return;
+    const float down = __builtin_ldexpf(1.0f, -S);
+    const int64_t total = n * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e - i * n;
+        const float b = Bm[i * ld + j];
+        T w;
+        if (i == j)
+            w = T(0);
+        else if (b == __builtin_inff())
+            w = std::is_same_v<T, int32_t> ? T(kInf32) : T(__builtin_inff());
+        else
+            w = (T)(b * down);
+        dist[e] = w;
+    }
+}
+
 // --------------------------------------------------------------- runtime
 namespace {
 
@@ -519,7 +795,7 @@ apsp_status_t cached_workspace(int dev, hipStream_t s, size_t bytes, void **out)
 }
 
 // Optional per-launch timing (apsp_profile_begin / _end).
-enum KernelKind { kPhase1 = 0, kPhase2 = 1, kPhase3 = 2, kOther = 3, kPhase3Cross = 4 };
+enum KernelKind { kPhase1 = 0, kPhase2 = 1, kPhase3 = 2, kOther = 3, kPhase3Cross = 4, kPredProduct = 5 };
 struct ProfRecord {
     int kind;
     double updates;
@@ -731,11 +1007,49 @@ bool use_f32w(int64_t n, apsp_dtype_t dtype, bool with_pred, int arith) {
     return arith == 2 || n > 4096;
 }
 
+// Predecessor solves: float32 distances + the key product (exact, with
+// the fp64-key recurrence as the device's fallback) when asked to, or
+// automatically above n = 4096, where the product costs less than the
+// recurrence's fp64 arithmetic (measured on MI355X: 1.4x faster at n = 8192
+// and 16384, even at n = 4096, slower below).
+bool use_pp(int64_t n, bool with_pred, int arith) {
+    if (!with_pred || arith == 1) return false;
+    return arith == 2 || n > 4096;
+}
+
+int pp_bits(int64_t n) {
+    int S = 1;
+    while ((int64_t(1) << S) < n) ++S;
+    return S;
+}
+
+// Block sizes and padded orders of a predecessor solve with the product:
+// the distance rounds (ld, a multiple of the 128-wide product tiles too)
+// and the fallback recurrence (ldf <= ld).
+struct PPShape {
+    int bsd, bsf;
+    int64_t ld, ldf;
+};
+PPShape pp_shape(int64_t n, int opt_bs) {
+    PPShape p;
+    p.bsd = opt_bs ? opt_bs : auto_block(n, false);
+    p.bsf = opt_bs ? opt_bs : auto_block(n, true);
+    const int64_t m = std::max(p.bsd, 128);
+    p.ld = (n + m - 1) / m * m;
+    p.ldf = (n + p.bsf - 1) / p.bsf * p.bsf;
+    return p;
+}
+
 // Work memory a solve needs beyond dist/pred (0 when it runs in place).
-size_t work_bytes(int64_t n, bool with_pred, int bs, bool aligned, bool f32w) {
+size_t work_bytes(int64_t n, bool with_pred, int opt_bs, bool aligned, apsp_dtype_t dtype, int arith) {
+    if (use_pp(n, with_pred, arith)) {
+        const int64_t ld = pp_shape(n, opt_bs).ld;
+        return (size_t)(ld * ld) * 8 + 256;
+    }
+    const int bs = opt_bs ? opt_bs : auto_block(n, with_pred);
     const int64_t ld = (n + bs - 1) / bs * bs;
     if (with_pred) return (size_t)(ld * ld) * 8 + 256;
-    if (f32w) return (size_t)(ld * ld) * 4 + 256;
+    if (use_f32w(n, dtype, with_pred, arith)) return (size_t)(ld * ld) * 4 + 256;
     if (ld == n && aligned) return 0;
     return (size_t)(ld * ld) * 4;
 }
@@ -808,6 +1122,60 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
             return APSP_SUCCESS;
         }
     }
+    if (use_pp(n, with_pred, opt.arith)) {
+        // [X: ld^2 float32][B: ld^2 float32][words]; the fallback's fp64 keys
+        // (ldf^2 x 8 bytes) reuse the two matrices
+        const PPShape sh = pp_shape(n, opt.block_size);
+        const int ttd = opt.thread_tile ? opt.thread_tile : auto_tile(n, sh.bsd);
+        const int ttf = opt.thread_tile ? opt.thread_tile : auto_tile(n, sh.bsf);
+        const size_t mat = (size_t)(sh.ld * sh.ld) * 4;
+        void *w = nullptr;
+        apsp_status_t st = workspace(dev, s, 2 * mat + 256, &w);
+        if (st != APSP_SUCCESS) return st;
+        float *X = (float *)w;
+        float *Bm = (float *)((char *)w + mat);
+        int32_t *words = (int32_t *)((char *)w + 2 * mat);
+        const int S = pp_bits(n);
+        const int vec = (n % 4 == 0) && ((uintptr_t)dist % 16 == 0);
+        hipLaunchKernelGGL(pp_init_kernel, dim3(1), dim3(1), 0, s, words);
+        hipLaunchKernelGGL((pp_in_kernel<T>), grid_rows(sh.ld, sh.ld), dim3(256), 0, s, dist, n, X, Bm, sh.ld, S,
+                           (float)apsp_weight_bound(n), words, skip, vec);
+        hipLaunchKernelGGL(pp_rounds_gate_kernel, dim3(1), dim3(1), 0, s, words, skip);
+        ArF32W arw;
+        arw.big = words + kPPBig;
+        st = run_rounds_bs<ArF32W>(sh.bsd, ttd, lookahead, X, sh.ld, arw, s, words + kPPRounds);
+        if (st != APSP_SUCCESS) return st;
+        hipLaunchKernelGGL((pp_out_kernel<T>), grid_rows(n, n), dim3(256), 0, s, X, sh.ld, dist, n, S, words,
+                           status, skip, vec);
+        hipLaunchKernelGGL(pp_product_gate_kernel, dim3(1), dim3(1), 0, s, words);
+        {
+            const int nt = (int)((n + 127) / 128);
+            const int per_xcd = (nt * nt + 7) / 8;
+            const int kcount = (int)((n + 31) / 32 * 32);
+            ProfScope ps(kPredProduct, (double)n * (double)n * (double)kcount, s);
+            hipLaunchKernelGGL((pp_product_kernel<T>), dim3(8 * per_xcd), dim3(256), 0, s, X, Bm, sh.ld, kcount,
+                               dist, pred, n, S, nt, per_xcd, words, skip);
+        }
+        hipLaunchKernelGGL(pp_gate_kernel, dim3(1), dim3(1), 0, s, words, skip, opt.d_arith);
+        const int32_t *gate = words + kPPGate;
+        hipLaunchKernelGGL((pp_restore_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, Bm, sh.ld, dist, n, S,
+                           words);
+        // the fallback: the exact fp64-key recurrence (pairs for float32
+        // weights that are not integers within the bound)
+        int32_t *mode = std::is_same_v<T, float> ? words + kPPMode : nullptr;
+        ArKey ar{pred_bits(sh.ldf)};
+        hipLaunchKernelGGL((pred_pack_kernel<T>), dim3(grid_for(sh.ldf * sh.ldf)), dim3(256), 0, s, dist, n, w,
+                           sh.ldf, ar.S, mode, gate);
+        if constexpr (std::is_same_v<T, float>)
+            st = run_rounds_bs<ArKey, ArLexF32>(sh.bsf, ttf, lookahead, w, sh.ldf, ar, s, gate, ArLexF32{}, mode);
+        else
+            st = run_rounds_bs<ArKey>(sh.bsf, ttf, lookahead, w, sh.ldf, ar, s, gate);
+        if (st != APSP_SUCCESS) return st;
+        hipLaunchKernelGGL((pred_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, w, sh.ldf, dist, pred,
+                           n, ar.S, mode, status, gate);
+        APSP_HIP(hipGetLastError());
+        return APSP_SUCCESS;
+    }
     if (!with_pred) {
         T *X = dist;
         const bool inplace = (ld == n) && ((uintptr_t)dist % 16 == 0);
@@ -858,7 +1226,7 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
 }  // namespace
 
 size_t solve_work_bytes(int64_t n, apsp_dtype_t dtype, bool with_pred) {
-    return work_bytes(n, with_pred, auto_block(n, with_pred), true, use_f32w(n, dtype, with_pred, 0));
+    return work_bytes(n, with_pred, 0, true, dtype, 0);
 }
 
 namespace {
@@ -908,8 +1276,7 @@ apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dty
     const int tt = opt.thread_tile ? opt.thread_tile : auto_tile(n, bs);
     // the work memory must exist (at its final address) before recording
     void *w = ws;
-    const size_t need = work_bytes(n, with_pred, bs, ((uintptr_t)dist % 16) == 0,
-                                   use_f32w(n, dtype, with_pred, opt.arith));
+    const size_t need = work_bytes(n, with_pred, opt.block_size, ((uintptr_t)dist % 16) == 0, dtype, opt.arith);
     if (!w && need > 0) {
         apsp_status_t st = cached_workspace(dev, s, need, &w);
         if (st != APSP_SUCCESS) return st;
@@ -1034,8 +1401,8 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out) {
         recs.swap(g_prof);
     }
     *out = apsp_profile_t{};
-    apsp_kernel_time_t *slot[5] = {&out->phase1, &out->phase2, &out->phase3, &out->other,
-                                   &out->phase3_cross};
+    apsp_kernel_time_t *slot[6] = {&out->phase1, &out->phase2, &out->phase3, &out->other,
+                                   &out->phase3_cross, &out->pred_product};
     apsp_status_t st = APSP_SUCCESS;
     for (auto &r : recs) {
         float ms = 0.f;
