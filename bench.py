@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--skip-single", action="store_true", help="batched/serving legs only")
     ap.add_argument("--sweep", default="",
                     help="only the paper's size sweep, e.g. 4096,8192,16384,32768,65536 (one JSON line)")
+    ap.add_argument("--sweep-modes", default="f32pred,int32",
+                    help="sweep runs: f32pred (float32 + predecessors), int32 (distances)")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--batched-replays", type=int, default=10)
@@ -368,7 +370,10 @@ def main():
     if args.sweep:
         torch.cuda.set_device(0)
         apsp.lib()
-        rows = sweep_leg([int(x) for x in args.sweep.split(",")], ["f32pred", "int32"])
+        modes = [m for m in args.sweep_modes.split(",") if m]
+        if not modes or any(m not in ("f32pred", "int32") for m in modes):
+            ap.error("--sweep-modes takes f32pred and/or int32")
+        rows = sweep_leg([int(x) for x in args.sweep.split(",")], modes)
         print(json.dumps({"sweep": rows, "data": "synthetic", "n_gpus": 1}), flush=True)
         return
 

@@ -1114,7 +1114,9 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
                 hipLaunchKernelGGL((pad_in_kernel<int32_t>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n,
                                    Xi, ld, kInf32, gate);
             }
-            st = run_rounds_bs<ArI32>(bs, tt, lookahead, Xi, ld, ArI32{}, s, gate, NoAlt{}, nullptr, false);
+            // in order (3 launches per round): when the gate stays closed,
+            // every launch still costs its dispatch
+            st = run_rounds_bs<ArI32>(bs, tt, false, Xi, ld, ArI32{}, s, gate, NoAlt{}, nullptr, false);
             if (st != APSP_SUCCESS) return st;
             hipLaunchKernelGGL((finalize_kernel<int32_t>), dim3(grid_for(n * n)), dim3(256), 0, s, Xi, ld, dist,
                                n, status, gate);
@@ -1166,10 +1168,12 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         ArKey ar{pred_bits(sh.ldf)};
         hipLaunchKernelGGL((pred_pack_kernel<T>), dim3(grid_for(sh.ldf * sh.ldf)), dim3(256), 0, s, dist, n, w,
                            sh.ldf, ar.S, mode, gate);
+        // in order (3 launches per round), as a closed gate still costs
+        // every launch's dispatch
         if constexpr (std::is_same_v<T, float>)
-            st = run_rounds_bs<ArKey, ArLexF32>(sh.bsf, ttf, lookahead, w, sh.ldf, ar, s, gate, ArLexF32{}, mode);
+            st = run_rounds_bs<ArKey, ArLexF32>(sh.bsf, ttf, false, w, sh.ldf, ar, s, gate, ArLexF32{}, mode, false);
         else
-            st = run_rounds_bs<ArKey>(sh.bsf, ttf, lookahead, w, sh.ldf, ar, s, gate);
+            st = run_rounds_bs<ArKey>(sh.bsf, ttf, false, w, sh.ldf, ar, s, gate, NoAlt{}, nullptr, false);
         if (st != APSP_SUCCESS) return st;
         hipLaunchKernelGGL((pred_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, w, sh.ldf, dist, pred,
                            n, ar.S, mode, status, gate);
