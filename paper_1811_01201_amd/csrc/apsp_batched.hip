@@ -141,7 +141,7 @@ union alignas(16) TeamSmem {
     typename BTile<Ar>::Smem wave[kBatchThreads / 64];
     typename GTile64<Ar>::Smem g64;
     typename GTile128<Ar>::Smem g128;
-    typename Ar::T p1[4 * 128];  // phase-1 publication buffers
+    typename Ar::T p1[8 * 128];  // phase-1 publication buffers (4 column + 4 row)
 };
 
 template <class Ar, class Tin, int CFG>
@@ -175,11 +175,11 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
         const int kc = r + 1 < R ? BS : (int)((n - r0 + 31) / 32 * 32);
         // phase 1
         if constexpr (CFG == kWaveTiles64) {
-            if (wave == 0) phase1_body<Ar, 64, true, 8>(X, ldp, r0, ar, buf, buf + 2, kc);
+            if (wave == 0) phase1_body<Ar, 64, true, 8>(X, ldp, r0, ar, buf, buf + 4, kc);
         } else if constexpr (CFG == kGroupTiles64) {
-            phase1_body<Ar, 64, false, 4>(X, ldp, r0, ar, buf, buf + 2, kc);
+            phase1_body<Ar, 64, false, 4>(X, ldp, r0, ar, buf, buf + 4, kc);
         } else {
-            phase1_body<Ar, 128, false, 8>(X, ldp, r0, ar, buf, buf + 2, kc);
+            phase1_body<Ar, 128, false, 8>(X, ldp, r0, ar, buf, buf + 4, kc);
         }
         __syncthreads();
         // phase 2: block row r (tiles t < nt) and block column r
@@ -411,13 +411,13 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
             if (use_alt) {
                 using TA = typename Alt::T;
                 TA(*buf)[kBatchBS] = reinterpret_cast<TA(*)[kBatchBS]>(&sm.b.wave[wave]);
-                wave_solve<Alt, Tin>(alt, dist, pred, status, g, n, off, buf, buf + 2);
+                wave_solve<Alt, Tin>(alt, dist, pred, status, g, n, off, buf, buf + 4);
                 continue;
             }
         }
         using TR = typename Ar::T;
         TR(*buf)[kBatchBS] = reinterpret_cast<TR(*)[kBatchBS]>(&sm.a.wave[wave]);
-        wave_solve<Ar, Tin>(ar, dist, pred, status, g, n, off, buf, buf + 2);
+        wave_solve<Ar, Tin>(ar, dist, pred, status, g, n, off, buf, buf + 4);
     }
     __syncthreads();
     if (tid == 0) {

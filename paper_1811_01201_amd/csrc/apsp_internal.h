@@ -621,7 +621,22 @@ using P1Regs = typename Ar::T[P1S<Ar, BS, TT>::TM1][P1S<Ar, BS, TT>::TN1];
 // The k-steps of a diagonal-block closure on a register-resident block:
 // steps 0 <= k < ksteps (ksteps a multiple of 16, at most BS).
 // Returns true if a watching policy (kWatch) saw a published value that is
-// unsafe as an operand; always false otherwise.
+// unsafe as an operand; always false otherwise.  colbuf and rowbuf each
+// hold 4 rows of BS elements.
+//
+// 4-byte elements with blocks of at most 8 rows take the k-steps in pairs:
+// the owners publish columns k, k+1 and rows k, k+1 as they stand before
+// step k; every thread forms column k+1 and row k+1 as step k leaves them,
+//     D'(i,k+1) = min(D(i,k+1), D(i,k) + D(k,k+1)),
+//     D'(k+1,j) = min(D(k+1,j), D(k+1,k) + D(k,j)),
+// for its own rows and columns, and applies both steps at once,
+//     D''(i,j) = min(D(i,j), D(i,k) + D(k,j), D'(i,k+1) + D'(k+1,j)),
+// one three-input minimum per element and one barrier per two steps.  The
+// values are those of two single steps, bit for bit, for every policy
+// (the same sums and minima).  Under a watching policy the derived
+// D'(i,k+1) and D'(k+1,j) need no check of their own: each lies between
+// a published value (watched) and the block's final value in that place
+// (watched at the end), since values only decrease.
 template <class Ar, int BS, bool WAVE, int TT = 8>
 __device__ __forceinline__ bool phase1_steps(P1Regs<Ar, BS, TT> &c, int ksteps, const Ar &ar,
                                              typename Ar::T (*colbuf)[BS],
@@ -631,6 +646,59 @@ __device__ __forceinline__ bool phase1_steps(P1Regs<Ar, BS, TT> &c, int ksteps, 
     constexpr int TM1 = P1S<Ar, BS, TT>::TM1, TN1 = P1S<Ar, BS, TT>::TN1, TX = P1S<Ar, BS, TT>::TX;
     constexpr int VW = Ar::VW;
     const int tid = tile_tid<WAVE>(), tx = tid % TX, ty = tid / TX;
+    if constexpr (sizeof(T) == 4 && TM1 <= 8) {
+        static_assert(TM1 % 2 == 0 && TN1 % 2 == 0, "a step pair has one owner");
+        for (int kb = 0; kb < ksteps / 16; ++kb) {
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 2) {
+                const int buf = (kk >> 1) & 1;
+                T(*const cb)[BS] = colbuf + 2 * buf;
+                T(*const rb)[BS] = rowbuf + 2 * buf;
+                if (tx == kb * (16 / TN1) + kk / TN1) {
+#pragma unroll
+                    for (int m = 0; m < TM1; ++m) {
+                        const T v0 = ar.strip(c[m][kk % TN1]), v1 = ar.strip(c[m][kk % TN1 + 1]);
+                        if constexpr (Ar::kWatch) big |= ar.is_big(v0) | ar.is_big(v1);
+                        cb[0][ty * TM1 + m] = v0;
+                        cb[1][ty * TM1 + m] = v1;
+                    }
+                }
+                if (ty == kb * (16 / TM1) + kk / TM1) {
+#pragma unroll
+                    for (int n = 0; n < TN1; ++n) {
+                        if constexpr (Ar::kWatch)
+                            big |= ar.is_big(c[kk % TM1][n]) | ar.is_big(c[kk % TM1 + 1][n]);
+                        rb[0][tx * TN1 + n] = c[kk % TM1][n];
+                        rb[1][tx * TN1 + n] = c[kk % TM1 + 1][n];
+                    }
+                }
+                tile_sync<WAVE>();
+                const int k = kb * 16 + kk;
+                const T dk_k1 = ar.strip(rb[0][k + 1]);  // D(k, k+1) as a left operand
+                const T dk1_k = ar.strip(rb[1][k]);      // D(k+1, k) as a left operand
+                T a0[TM1], a1[TM1], b0[TN1], b1[TN1];
+#pragma unroll
+                for (int g = 0; g < TM1 / VW; ++g) {
+                    ld16(&cb[0][ty * TM1 + g * VW], &a0[g * VW]);
+                    ld16(&cb[1][ty * TM1 + g * VW], &a1[g * VW]);
+                }
+#pragma unroll
+                for (int g = 0; g < TN1 / VW; ++g) {
+                    ld16(&rb[0][tx * TN1 + g * VW], &b0[g * VW]);
+                    ld16(&rb[1][tx * TN1 + g * VW], &b1[g * VW]);
+                }
+#pragma unroll
+                for (int m = 0; m < TM1; ++m) a1[m] = ar.mn(a1[m], ar.add(a0[m], dk_k1));
+#pragma unroll
+                for (int n = 0; n < TN1; ++n) b1[n] = ar.mn(b1[n], ar.add(dk1_k, b0[n]));
+#pragma unroll
+                for (int m = 0; m < TM1; ++m)
+#pragma unroll
+                    for (int n = 0; n < TN1; ++n) c[m][n] = ar.relax2(c[m][n], a0[m], b0[n], a1[m], b1[n]);
+            }
+        }
+        return big;
+    }
     // 16 steps per iteration keep every register index static: the owner of
     // column k holds it at n = k mod TN1, the owner of row k at m = k mod TM1.
     for (int kb = 0; kb < ksteps / 16; ++kb) {

@@ -38,17 +38,17 @@ phase1_kernel(void *X, int64_t ld, int64_t r0, Ar ar, Alt alt, const int32_t *__
     if (skip && *skip != APSP_SUCCESS) return;
     constexpr int E = sizeof(typename Ar::T) > sizeof(typename Alt::T) ? sizeof(typename Ar::T)
                                                                         : sizeof(typename Alt::T);
-    __shared__ __attribute__((aligned(16))) char lds[2 * 2 * BS * E];
+    __shared__ __attribute__((aligned(16))) char lds[2 * 4 * BS * E];  // 4 column + 4 row buffers
     if constexpr (!std::is_same_v<Alt, NoAlt>) {
         if (use_alt<Ar, Alt>(mode)) {
             using T = typename Alt::T;
             phase1_body<Alt, BS, false, TT>((T *)X, ld, r0, alt, (T(*)[BS])lds,
-                                            (T(*)[BS])(lds + 2 * BS * sizeof(T)));
+                                            (T(*)[BS])(lds + 4 * BS * sizeof(T)));
             return;
         }
     }
     using T = typename Ar::T;
-    phase1_body<Ar, BS, false, TT>((T *)X, ld, r0, ar, (T(*)[BS])lds, (T(*)[BS])(lds + 2 * BS * sizeof(T)));
+    phase1_body<Ar, BS, false, TT>((T *)X, ld, r0, ar, (T(*)[BS])lds, (T(*)[BS])(lds + 4 * BS * sizeof(T)));
 }
 
 // ---------------------------------------------------------------- phase 2
