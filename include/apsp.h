@@ -281,8 +281,9 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
  *
  * The batched launch picks a team configuration (tile size and per-thread
  * register block, see apsp_batch_plan_create_ex) per graph from a table
- * indexed by (dtype, predecessors, size class), size classes n in (64,128],
- * (128,256], (256,384], (384,512], (512,1024].  The table starts from
+ * indexed by (dtype, predecessors, size class), 8 size classes n in
+ * (64,128], (128,192], (192,256], (256,320], (320,384], (384,448],
+ * (448,512], (512,1024].  The table starts from
  * built-in defaults, is read from the JSON file named by the environment
  * variable APSP_TUNE_TABLE on first use, and can be measured on the current
  * device: apsp_batch_autotune builds one synthetic batch with
@@ -290,6 +291,7 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
  * class (coordinate descent, the other classes at their current choice),
  * times the whole batch with each configuration for that class (reps timed
  * executions, 0 = 3) and keeps the fastest.  ms_out[class * 3 + config]
+ * (24 doubles)
  * (when not NULL) receives the per-execution milliseconds of each trial.
  * It allocates device memory and synchronises its own stream.
  */

@@ -443,7 +443,7 @@ class Server:
 
 
 TEAM_CONFIGS = ("wave_tiles_64", "group_tiles_64", "group_tiles_128")
-SIZE_CLASSES = (128, 256, 384, 512, 1024)
+SIZE_CLASSES = (128, 192, 256, 320, 384, 448, 512, 1024)
 
 
 def batch_autotune(dtype="int32", want_pred=False, graphs_per_class=0, reps=0, ns=None) -> dict:

@@ -112,6 +112,27 @@ __device__ __forceinline__ bool from_work(const Ar &ar, typename Ar::T v, int64_
     return neg;
 }
 
+// ------------------------------------------- per-graph policy choice
+// A graph takes the second policy Alt when one of its weights rules out the
+// first:
+//   float32 weights with predecessors (ArKey / ArLexF32): a finite weight
+//     that is not an integer within the bound (keys would not be exact);
+//   int32 distances (ArF32 / ArI32): a negative weight or one with
+//     |w| (n - 1) >= 2^23.  Otherwise every operand the blocked schedule
+//     adds is a restricted shortest-path length below 2^23 in magnitude, so
+//     every float32 sum is an exact integer below 2^24 and the float32
+//     solve equals the int32 one; float32 adds issue at twice the rate.
+template <class Ar, class Alt, class Tin>
+__device__ __forceinline__ bool rules_out(Tin w, int64_t n) {
+    if constexpr (std::is_same_v<Ar, ArF32> && std::is_same_v<Alt, ArI32>) {
+        return w != kInf32 && (w < 0 || (int64_t)w * (n - 1) >= (int64_t(1) << 23));
+    } else {
+        const float bound = (float)weight_bound(n);
+        const float f = (float)w;
+        return f != __builtin_inff() && (f != __builtin_floorf(f) || __builtin_fabsf(f) > bound);
+    }
+}
+
 // ------------------------------------------------------------ team path
 // Team configurations (chosen per graph; see the plan's size classes):
 //   kWaveTiles64   64-wide k-blocks; each wavefront owns whole 64 x 64 tiles
@@ -144,7 +165,10 @@ union alignas(16) TeamSmem {
     typename Ar::T p1[8 * 128];  // phase-1 publication buffers (4 column + 4 row)
 };
 
-template <class Ar, class Tin, int CFG>
+// CHECK: the float32 launch of an int32 batch; the graph is dropped (left
+// to the int32 launch) if a weight rules float32 arithmetic out, which the
+// copy into the work matrix checks on the way.
+template <class Ar, class Tin, int CFG, bool CHECK = false>
 __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__restrict__ pred,
                            int32_t *__restrict__ status, int g, int64_t n, int64_t off,
                            typename Ar::T *__restrict__ X, TeamSmem<Ar> &sm) {
@@ -158,13 +182,19 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
         while ((int64_t(1) << S) < ldp + 1) ++S;
         ar.S = S;
     }
+    bool ruled_out = false;
     for (int64_t e = tid; e < ldp * ldp; e += kBatchThreads) {
         const int64_t i = e / ldp, j = e - i * ldp;
         const bool inside = i < n && j < n;
         const Tin w = inside ? dist[off + i * n + j] : Tin(0);
+        if constexpr (CHECK) ruled_out |= inside && rules_out<ArF32, ArI32>(w, n);
         X[e] = to_work(ar, w, inside, i, j);
     }
-    __syncthreads();
+    if constexpr (CHECK) {
+        if (__syncthreads_or(ruled_out)) return;  // uniform: the whole workgroup leaves
+    } else {
+        __syncthreads();
+    }
     const int R = (int)(ldp / BS);
     const int nt = R - 1;
     T(*buf)[BS] = reinterpret_cast<T(*)[BS]>(sm.p1);
@@ -239,21 +269,22 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
     __syncthreads();
 }
 
-template <class Ar, class Tin>
+template <class Ar, class Tin, bool CHECK = false>
 __device__ void team_dispatch(int cfg, const Ar &ar, Tin *__restrict__ dist, int32_t *__restrict__ pred,
                               int32_t *__restrict__ status, int g, int64_t n, int64_t off,
                               typename Ar::T *__restrict__ X, TeamSmem<Ar> &sm) {
     if (cfg == kGroupTiles64)
-        team_solve<Ar, Tin, kGroupTiles64>(ar, dist, pred, status, g, n, off, X, sm);
+        team_solve<Ar, Tin, kGroupTiles64, CHECK>(ar, dist, pred, status, g, n, off, X, sm);
     else if (cfg == kGroupTiles128)
-        team_solve<Ar, Tin, kGroupTiles128>(ar, dist, pred, status, g, n, off, X, sm);
+        team_solve<Ar, Tin, kGroupTiles128, CHECK>(ar, dist, pred, status, g, n, off, X, sm);
     else
-        team_solve<Ar, Tin, kWaveTiles64>(ar, dist, pred, status, g, n, off, X, sm);
+        team_solve<Ar, Tin, kWaveTiles64, CHECK>(ar, dist, pred, status, g, n, off, X, sm);
 }
 
 // ------------------------------------------------------ wavefront path
 // n <= 64: the whole graph in one wavefront's registers (8 x 8 per lane).
-template <class Ar, class Tin>
+// CHECK as for team_solve.
+template <class Ar, class Tin, bool CHECK = false>
 __device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__restrict__ pred,
                            int32_t *__restrict__ status, int g, int64_t n, int64_t off,
                            typename Ar::T (*colbuf)[kBatchBS], typename Ar::T (*rowbuf)[kBatchBS]) {
@@ -262,6 +293,7 @@ __device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
     if constexpr (std::is_same_v<Ar, ArKey>) ar.S = 7;  // vertices 0..63, none = 127
     const int lane = threadIdx.x & 63, tx = lane % 8, ty = lane / 8;
     T c[8][8];
+    bool ruled_out = false;
 #pragma unroll
     for (int m = 0; m < 8; ++m)
 #pragma unroll
@@ -269,8 +301,12 @@ __device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
             const int64_t i = ty * 8 + m, j = tx * 8 + q;
             const bool inside = i < n && j < n;
             const Tin w = inside ? dist[off + i * n + j] : Tin(0);
+            if constexpr (CHECK) ruled_out |= inside && rules_out<ArF32, ArI32>(w, n);
             c[m][q] = to_work(ar, w, inside, i, j);
         }
+    if constexpr (CHECK) {
+        if (__any(ruled_out)) return;  // uniform over the wavefront
+    }
     const int ksteps = (int)((n + 15) / 16 * 16);  // vertices >= n are isolated
     phase1_steps<Ar, kBatchBS, true>(c, ksteps, ar, colbuf, rowbuf);
     bool neg = false;
@@ -285,27 +321,6 @@ __device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
         }
     neg = __any(neg);
     if (status && lane == 0) status[g] = neg ? APSP_ERROR_NEGATIVE_CYCLE : APSP_SUCCESS;
-}
-
-// ------------------------------------------- per-graph policy choice
-// A graph takes the second policy Alt when one of its weights rules out the
-// first:
-//   float32 weights with predecessors (ArKey / ArLexF32): a finite weight
-//     that is not an integer within the bound (keys would not be exact);
-//   int32 distances (ArF32 / ArI32): a negative weight or one with
-//     |w| (n - 1) >= 2^23.  Otherwise every operand the blocked schedule
-//     adds is a restricted shortest-path length below 2^23 in magnitude, so
-//     every float32 sum is an exact integer below 2^24 and the float32
-//     solve equals the int32 one; float32 adds issue at twice the rate.
-template <class Ar, class Alt, class Tin>
-__device__ __forceinline__ bool rules_out(Tin w, int64_t n) {
-    if constexpr (std::is_same_v<Ar, ArF32> && std::is_same_v<Alt, ArI32>) {
-        return w != kInf32 && (w < 0 || (int64_t)w * (n - 1) >= (int64_t(1) << 23));
-    } else {
-        const float bound = (float)weight_bound(n);
-        const float f = (float)w;
-        return f != __builtin_inff() && (f != __builtin_floorf(f) || __builtin_fabsf(f) > bound);
-    }
 }
 
 // Whether any weight of a graph (count elements from a 16-byte-aligned g)
@@ -372,7 +387,7 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
         if (q >= meta.n_team) break;
         const int g = meta.order[q];
         const int64_t n = meta.ns[g], off = meta.offsets[g];
-        if constexpr (SEL != kEveryGraph) {
+        if constexpr (SEL == kIntGraphs) {
             const bool out = scan_rules_out<ArF32, ArI32>(dist + off, n * n, n, tid, kBatchThreads);
             if (!selected<SEL, Tin>(__syncthreads_or(out))) continue;
         }
@@ -388,7 +403,9 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
                 continue;
             }
         }
-        team_dispatch<Ar, Tin>(cfg, ar, dist, pred, status, g, n, off, (typename Ar::T *)my_scratch, sm.a);
+        // the float32 launch checks the weights while copying them in
+        team_dispatch<Ar, Tin, SEL == kFloatGraphs>(cfg, ar, dist, pred, status, g, n, off,
+                                                    (typename Ar::T *)my_scratch, sm.a);
     }
     // small graphs: every wavefront on its own
     const int wave = tid >> 6, lane = tid & 63;
@@ -399,7 +416,7 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
         if (q >= meta.batch) break;
         const int g = meta.order[q];
         const int64_t n = meta.ns[g], off = meta.offsets[g];
-        if constexpr (SEL != kEveryGraph) {
+        if constexpr (SEL == kIntGraphs) {
             const bool out = scan_rules_out<ArF32, ArI32>(dist + off, n * n, n, lane, 64);
             if (!selected<SEL, Tin>(__any(out))) continue;
         }
@@ -417,7 +434,7 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
         }
         using TR = typename Ar::T;
         TR(*buf)[kBatchBS] = reinterpret_cast<TR(*)[kBatchBS]>(&sm.a.wave[wave]);
-        wave_solve<Ar, Tin>(ar, dist, pred, status, g, n, off, buf, buf + 4);
+        wave_solve<Ar, Tin, SEL == kFloatGraphs>(ar, dist, pred, status, g, n, off, buf, buf + 4);
     }
     __syncthreads();
     if (tid == 0) {
@@ -534,17 +551,22 @@ void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, 
 
 // ------------------------------------------------------- tuning table
 // Team configuration per (dtype, predecessors, size class); size classes
-// are n in (64,128], (128,256], (256,384], (384,512], (512,1024].
-constexpr int kClasses = 5;
-constexpr int kClassHi[kClasses] = {128, 256, 384, 512, 1024};
+// are n in (64,128], (128,192], ..., (448,512] (64 wide, so a class pads
+// its graphs to one multiple of 64) and (512,1024].  Distance defaults
+// (measured on MI355X, graphs of one size per batch): 128 x 128 group tiles
+// where the 64-padded size is a multiple of 128 (their padding is then no
+// larger and they run 9-14 % faster: n = 256, 384, 512), wavefront tiles
+// elsewhere above 128, 64 x 64 group tiles up to 128.  8-byte keys keep
+// the 64-wide configurations.
+constexpr int kClasses = 8;
+constexpr int kClassHi[kClasses] = {128, 192, 256, 320, 384, 448, 512, 1024};
 std::mutex g_tune_mu;
+constexpr int8_t kW = kWaveTiles64, kG = kGroupTiles64, kG2 = kGroupTiles128;
 int8_t g_tune[2][2][kClasses] = {
     // int32: distances, predecessors
-    {{kGroupTiles64, kGroupTiles64, kWaveTiles64, kWaveTiles64, kWaveTiles64},
-     {kGroupTiles64, kGroupTiles64, kWaveTiles64, kWaveTiles64, kWaveTiles64}},
+    {{kG, kW, kG2, kW, kG2, kW, kG2, kW}, {kG, kG, kG, kW, kW, kW, kW, kW}},
     // float32
-    {{kGroupTiles64, kGroupTiles64, kWaveTiles64, kWaveTiles64, kWaveTiles64},
-     {kGroupTiles64, kGroupTiles64, kWaveTiles64, kWaveTiles64, kWaveTiles64}}};
+    {{kG, kW, kG2, kW, kG2, kW, kG2, kW}, {kG, kG, kG, kW, kW, kW, kW, kW}}};
 bool g_tune_env_checked = false;
 
 int size_class(int64_t n) {
@@ -567,9 +589,9 @@ int8_t batch_config(int64_t n, apsp_dtype_t dtype, bool pred) {
 }
 
 // JSON form of the table:
-//   {"version": 1, "classes": [128, 256, 384, 512, 1024],
+//   {"version": 2, "classes": [128, 192, 256, 320, 384, 448, 512, 1024],
 //    "configs": ["wave_tiles_64", "group_tiles_64", "group_tiles_128"],
-//    "table": {"int32": {"dist": [c0..c4], "pred": [..]}, "float32": {...}}}
+//    "table": {"int32": {"dist": [c0..c7], "pred": [..]}, "float32": {...}}}
 apsp_status_t tune_load_locked(const char *path) {
     FILE *f = std::fopen(path, "rb");
     if (!f) return APSP_ERROR_INVALID_ARGUMENT;
@@ -606,7 +628,9 @@ apsp_status_t tune_load_locked(const char *path) {
 apsp_status_t tune_save_locked(const char *path) {
     FILE *f = std::fopen(path, "wb");
     if (!f) return APSP_ERROR_INVALID_ARGUMENT;
-    std::fprintf(f, "{\"version\": 1, \"classes\": [128, 256, 384, 512, 1024],\n");
+    std::fprintf(f, "{\"version\": 2, \"classes\": [");
+    for (int c = 0; c < kClasses; ++c) std::fprintf(f, "%s%d", c ? ", " : "", kClassHi[c]);
+    std::fprintf(f, "],\n");
     std::fprintf(f, " \"configs\": [\"wave_tiles_64\", \"group_tiles_64\", \"group_tiles_128\"],\n");
     std::fprintf(f, " \"table\": {");
     const char *dts[2] = {"int32", "float32"};

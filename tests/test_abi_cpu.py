@@ -117,15 +117,16 @@ def test_tuning_table_roundtrip(tmp_path):
     text = p.read_text()
     import json
     doc = json.loads(text)
-    assert doc["classes"] == [128, 256, 384, 512, 1024]
+    assert doc["classes"] == [128, 192, 256, 320, 384, 448, 512, 1024]
     assert set(doc["table"]) == {"int32", "float32"}
-    doc["table"]["float32"]["pred"] = [2, 1, 0, 2, 1]
+    doc["table"]["float32"]["pred"] = [2, 1, 0, 2, 1, 0, 2, 1]
     p.write_text(json.dumps(doc))
     apsp.tune_load(str(p))
-    assert [apsp.batch_config(n, "float32", True) for n in (100, 200, 300, 500, 900)] == [2, 1, 0, 2, 1]
+    assert [apsp.batch_config(n, "float32", True) for n in (100, 150, 200, 300, 350, 400, 500, 900)] == \
+        [2, 1, 0, 2, 1, 0, 2, 1]
     assert apsp.batch_config(64, "int32") == -1
     bad = tmp_path / "bad.json"
-    bad.write_text('{"table": {"int32": {"dist": [0, 7, 0, 0, 0]}}}')
+    bad.write_text('{"table": {"int32": {"dist": [0, 7, 0, 0, 0, 0, 0, 0]}}}')
     with pytest.raises(apsp.APSPError):
         apsp.tune_load(str(bad))
     with pytest.raises(apsp.APSPError):
