@@ -122,16 +122,32 @@ __device__ __forceinline__ bool from_work(const Ar &ar, typename Ar::T v, int64_
 //     adds is a restricted shortest-path length below 2^23 in magnitude, so
 //     every float32 sum is an exact integer below 2^24 and the float32
 //     solve equals the int32 one; float32 adds issue at twice the rate.
-template <class Ar, class Alt, class Tin>
-__device__ __forceinline__ bool rules_out(Tin w, int64_t n) {
-    if constexpr (std::is_same_v<Ar, ArF32> && std::is_same_v<Alt, ArI32>) {
-        return w != kInf32 && (w < 0 || (int64_t)w * (n - 1) >= (int64_t(1) << 23));
-    } else {
-        const float bound = (float)weight_bound(n);
-        const float f = (float)w;
-        return f != __builtin_inff() && (f != __builtin_floorf(f) || __builtin_fabsf(f) > bound);
-    }
+// The int32 test as one unsigned comparison: w (n - 1) >= 2^23 for w >= 0
+// is w >= lim = ceil(2^23 / (n - 1)), and a negative w read as unsigned is
+// at least 2^31 > lim.  n <= 1: lim = 2^31 (only negative weights).
+__device__ __forceinline__ uint32_t f32_limit(int64_t n) {
+    return n <= 1 ? 0x80000000u : (uint32_t)(((int64_t(1) << 23) + (n - 2)) / (n - 1));
 }
+__device__ __forceinline__ bool f32_ruled_out(int32_t w, uint32_t lim) {
+    return ((uint32_t)w >= lim) & (w != kInf32);
+}
+
+// Per-graph form of the test: lim() once per graph, out() per weight.
+template <class Ar, class Alt, class Tin>
+struct RuleOut {
+    float bound;
+    __device__ __forceinline__ explicit RuleOut(int64_t n) : bound((float)weight_bound(n)) {}
+    __device__ __forceinline__ bool out(Tin w) const {
+        const float f = (float)w;
+        return (f != __builtin_inff()) & ((f != __builtin_floorf(f)) | (__builtin_fabsf(f) > bound));
+    }
+};
+template <>
+struct RuleOut<ArF32, ArI32, int32_t> {
+    uint32_t lim;
+    __device__ __forceinline__ explicit RuleOut(int64_t n) : lim(f32_limit(n)) {}
+    __device__ __forceinline__ bool out(int32_t w) const { return f32_ruled_out(w, lim); }
+};
 
 // ------------------------------------------------------------ team path
 // Team configurations (chosen per graph; see the plan's size classes):
@@ -183,11 +199,12 @@ __device__ void team_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
         ar.S = S;
     }
     bool ruled_out = false;
+    const uint32_t lim = f32_limit(n);
     for (int64_t e = tid; e < ldp * ldp; e += kBatchThreads) {
         const int64_t i = e / ldp, j = e - i * ldp;
         const bool inside = i < n && j < n;
         const Tin w = inside ? dist[off + i * n + j] : Tin(0);
-        if constexpr (CHECK) ruled_out |= inside && rules_out<ArF32, ArI32>(w, n);
+        if constexpr (CHECK) ruled_out |= inside & f32_ruled_out(w, lim);
         X[e] = to_work(ar, w, inside, i, j);
     }
     if constexpr (CHECK) {
@@ -294,6 +311,7 @@ __device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
     const int lane = threadIdx.x & 63, tx = lane % 8, ty = lane / 8;
     T c[8][8];
     bool ruled_out = false;
+    const uint32_t lim = f32_limit(n);
 #pragma unroll
     for (int m = 0; m < 8; ++m)
 #pragma unroll
@@ -301,7 +319,7 @@ __device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
             const int64_t i = ty * 8 + m, j = tx * 8 + q;
             const bool inside = i < n && j < n;
             const Tin w = inside ? dist[off + i * n + j] : Tin(0);
-            if constexpr (CHECK) ruled_out |= inside && rules_out<ArF32, ArI32>(w, n);
+            if constexpr (CHECK) ruled_out |= inside & f32_ruled_out(w, lim);
             c[m][q] = to_work(ar, w, inside, i, j);
         }
     if constexpr (CHECK) {
@@ -329,18 +347,26 @@ __device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
 template <class Ar, class Alt, class Tin>
 __device__ __forceinline__ bool scan_rules_out(const Tin *__restrict__ g, int64_t count, int64_t n, int lane,
                                                int width) {
+    const RuleOut<Ar, Alt, Tin> rule(n);
     const int64_t nv = count / 4;
     const int4 *__restrict__ v = reinterpret_cast<const int4 *>(g);
-    bool out = false;
-#pragma unroll 4
-    for (int64_t e = lane; e < nv; e += width) {
-        const int4 x = v[e];
+    auto any4 = [&](const int4 &x) {
         Tin a[4];
         __builtin_memcpy(a, &x, 16);
-        out |= rules_out<Ar, Alt>(a[0], n) | rules_out<Ar, Alt>(a[1], n) | rules_out<Ar, Alt>(a[2], n) |
-               rules_out<Ar, Alt>(a[3], n);
+        return rule.out(a[0]) | rule.out(a[1]) | rule.out(a[2]) | rule.out(a[3]);
+    };
+    bool out = false;
+    int64_t e = lane;
+    // eight 16-byte loads in flight per lane, then their tests
+    for (; e + 7 * (int64_t)width < nv; e += 8 * (int64_t)width) {
+        int4 x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = v[e + u * (int64_t)width];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) out |= any4(x[u]);
     }
-    for (int64_t e = nv * 4 + lane; e < count; e += width) out |= rules_out<Ar, Alt>(g[e], n);
+    for (; e < nv; e += width) out |= any4(v[e]);
+    for (int64_t t = nv * 4 + lane; t < count; t += width) out |= rule.out(g[t]);
     return out;
 }
 

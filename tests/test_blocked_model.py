@@ -226,3 +226,21 @@ def test_wrapping_model_does_wrap():
     np.fill_diagonal(W, 0)
     _, neg, wrapped = blocked_wrapping(W, bs, rng)
     assert wrapped and neg
+
+
+def test_float32_eligibility_as_one_unsigned_compare():
+    """The batched launches test int32 weights for float32 arithmetic as
+    (unsigned)w >= ceil(2^23/(n-1)) and w != INF (2^31 for n <= 1): the same
+    predicate as "finite and (negative, or w (n-1) >= 2^23)", on edge values
+    of every size class and beyond."""
+    rng = np.random.default_rng(3)
+    for n in list(range(1, 70)) + [127, 128, 129, 511, 512, 513, 1024, 4097, 65536]:
+        lim = 2 ** 31 if n <= 1 else (2 ** 23 + n - 2) // (n - 1)
+        near = [lim - 1, lim, lim + 1] if lim < 2 ** 31 else []
+        ws = np.array([0, 1, -1, -(2 ** 31), 2 ** 31 - 1, INF32, INF32 - 1, INF32 + 1, 2 ** 23, 2 ** 22] + near +
+                      list(rng.integers(-(2 ** 31), 2 ** 31, size=200)), dtype=np.int64)
+        ws = ws[(ws >= -(2 ** 31)) & (ws < 2 ** 31)]
+        for w in ws.tolist():
+            plain = w != INF32 and (w < 0 or w * (n - 1) >= 2 ** 23)
+            fast = (w % 2 ** 32) >= lim and w != INF32
+            assert plain == fast, (n, w)
