@@ -51,6 +51,54 @@ phase1_kernel(void *X, int64_t ld, int64_t r0, Ar ar, Alt alt, const int32_t *__
     phase1_body<Ar, BS, false, TT>((T *)X, ld, r0, ar, (T(*)[BS])lds, (T(*)[BS])(lds + 4 * BS * sizeof(T)));
 }
 
+// Phase 1 at BS = 256 for 4-byte elements without a second policy: the
+// diagonal block closed by a blocked Floyd-Warshall of its own inside one
+// 256-thread workgroup, four 64-wide rounds of (64 x 64 diagonal closure;
+// its block row and column as products against it; the other nine 64 x 64
+// tiles as products), which reaches the values of 256 single steps by the
+// blocked schedule's own argument.  Every product is watched (inputs and
+// outputs) as well as every closure's publications and results, so a
+// watching policy still sees each operand.  Its registers and LDS fit in
+// what one phase-3 workgroup frees: it starts as soon as any of those
+// finishes, where the one-step-per-barrier kernel needs a whole compute
+// unit to drain.
+template <class Ar>
+__global__ void __launch_bounds__(256) phase1_blocked_kernel(void *X, int64_t ld, int64_t r0, Ar ar,
+                                                             const int32_t *__restrict__ skip) {
+    using T = typename Ar::T;
+    using GT = TileProductDMA<Ar, 64, 64, 16, 4, 4>;
+    static_assert(sizeof(T) == 4 && GT::NTH == 256 && P1S<Ar, 64, 4>::NTH == 256, "one 256-thread workgroup");
+    if (skip && *skip != APSP_SUCCESS) return;
+    __shared__ union alignas(16) {
+        typename GT::Smem t;
+        T p1[8 * 64];  // closure publications: 4 column + 4 row buffers
+    } sm;
+    T *const D = (T *)X;
+    T(*const buf)[64] = reinterpret_cast<T(*)[64]>(sm.p1);
+    for (int s = 0; s < 4; ++s) {
+        const int64_t d0 = r0 + 64 * s;
+        phase1_body<Ar, 64, false, 4>(D, ld, d0, ar, buf, buf + 4);
+        __syncthreads();
+        for (int t = 0; t < 6; ++t) {  // block row s (t < 3) and block column s
+            int q = t % 3;
+            q += (q >= s) ? 1 : 0;
+            const int64_t o = r0 + 64 * q;
+            if (t < 3)
+                GT::template run<true>(sm.t, D, ld, d0, o, d0, 64, ar);
+            else
+                GT::template run<true>(sm.t, D, ld, o, d0, d0, 64, ar);
+        }
+        __syncthreads();
+        for (int t = 0; t < 9; ++t) {
+            int a = t / 3, b = t % 3;
+            a += (a >= s) ? 1 : 0;
+            b += (b >= s) ? 1 : 0;
+            GT::template run<true>(sm.t, D, ld, r0 + 64 * a, r0 + 64 * b, d0, 64, ar);
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- phase 2
 // Block row r:    C = D[r-block rows, J cols] (BS x P2W tiles), A = closed
 //                 diagonal block, B = C's own old values.
@@ -906,10 +954,22 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
         apsp_status_t st = aux_stream(dev, s, &aux);
         if (st != APSP_SUCCESS) return st;
     }
+    // the blocked closure is slower on its own (one wavefront per SIMD) but
+    // starts in any slot a phase-3 workgroup frees: it pays off where
+    // phase 3 is long enough to hide it (measured on MI355X: -3 % at
+    // n = 16384, -0.4 % at 32768, +20 % at 8192)
+    constexpr bool kBlockedP1 = BS == 256 && sizeof(typename Ar::T) == 4 && std::is_same_v<Alt, NoAlt>;
+    const bool blocked_p1 = kBlockedP1 && ld >= 16384;
     auto p1 = [&](int r) {
         ProfScope ps(prof ? kPhase1 : -1, bs3, s);
-        hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS, TT>), dim3(1), dim3(P1S<Ar, BS, TT>::NTH), 0, s, X,
-                           ld, (int64_t)r * BS, ar, alt, mode, skip);
+        if (blocked_p1) {
+            if constexpr (kBlockedP1)
+                hipLaunchKernelGGL((phase1_blocked_kernel<Ar>), dim3(1), dim3(256), 0, s, X, ld, (int64_t)r * BS,
+                                   ar, skip);
+        } else {
+            hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS, TT>), dim3(1), dim3(P1S<Ar, BS, TT>::NTH), 0, s, X,
+                               ld, (int64_t)r * BS, ar, alt, mode, skip);
+        }
     };
     auto p2 = [&](int r) {
         if (nt2 <= 0) return;
