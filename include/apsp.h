@@ -153,6 +153,38 @@ typedef struct {
 apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype,
                             hipStream_t stream, const apsp_options_t *options);
 
+/* ---------------------------------------------------------------- steppers
+ *
+ * A solve issued a few rounds at a time (round-level preemption, for
+ * serving: large solves yield the device between slices).  The launch
+ * sequence of a solve never depends on the data (every data-dependent
+ * choice is a device word), so apsp_stepper_begin records the whole
+ * sequence of apsp_solve_ex for (dist, pred, stream) without issuing
+ * anything, and apsp_stepper_step issues the next `rounds` rounds of it
+ * (rounds <= 0: everything left), the distance state staying in device
+ * memory between steps.  Round counts include the device-gated fallback
+ * passes, which cost one near-empty launch per kernel when skipped.  The
+ * result after the last step is the result of apsp_solve_ex with the same
+ * options (use_graph ignored), bit for bit.
+ *
+ * The stepper owns its work memory (allocated at create for any alignment
+ * of dist) and its second stream, so slices of several steppers and any
+ * other work may interleave on one device, even on one caller stream.
+ * Steps are issued on the stream given to begin.  dist/pred must stay
+ * valid until the last step's work completes.  A stepper is not
+ * thread-safe.  begin while a previous solve is not fully issued returns
+ * APSP_ERROR_NOT_READY.  destroy synchronises the stepper's streams first.
+ */
+typedef struct apsp_stepper apsp_stepper_t;
+apsp_status_t apsp_stepper_create(int64_t n, apsp_dtype_t dtype, int32_t want_pred,
+                                  const apsp_options_t *options, apsp_stepper_t **out);
+apsp_status_t apsp_stepper_begin(apsp_stepper_t *stepper, void *dist, int32_t *pred, hipStream_t stream);
+/* *done (optional) = 1 once the whole solve has been issued. */
+apsp_status_t apsp_stepper_step(apsp_stepper_t *stepper, int32_t rounds, int32_t *done);
+/* Rounds in the recorded solve (-1 for NULL; 0 before begin). */
+int64_t apsp_stepper_rounds(const apsp_stepper_t *stepper);
+apsp_status_t apsp_stepper_destroy(apsp_stepper_t *stepper);
+
 /* ---------------------------------------------------------------- profiling
  *
  * Per-kernel timing of the single-graph path for benchmarks: between

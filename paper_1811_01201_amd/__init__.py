@@ -122,6 +122,11 @@ def _bind_optional(L):
         "apsp_batch_config": ([i64, c_int, i32], i32),
         "apsp_tune_save": ([ctypes.c_char_p], c_int),
         "apsp_tune_load": ([ctypes.c_char_p], c_int),
+        "apsp_stepper_create": ([i64, c_int, i32, ctypes.POINTER(Options), ctypes.POINTER(vp)], c_int),
+        "apsp_stepper_begin": ([vp, vp, vp, vp], c_int),
+        "apsp_stepper_step": ([vp, i32, ctypes.POINTER(i32)], c_int),
+        "apsp_stepper_rounds": ([vp], i64),
+        "apsp_stepper_destroy": ([vp], c_int),
     }
     for name, (args, res) in table.items():
         f = getattr(L, name, None)
@@ -190,6 +195,55 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
     if check and st != SUCCESS:
         raise APSPError(st, "apsp_solve_ex")
     return st
+
+
+class Stepper:
+    """A solve issued a few rounds at a time (apsp_stepper_*): begin() records
+    the launch sequence of solve() for these tensors on a stream, step(k)
+    issues the next k rounds (k <= 0: all that is left) and returns True once
+    everything is issued.  The final result equals solve()'s bit for bit."""
+
+    def __init__(self, n: int, dtype: str = "int32", want_pred: bool = False, *, validate=False, block_size=0,
+                 thread_tile=0, schedule=0, arith=0, status=None, arith_used=None):
+        self.n = int(n)
+        self.want_pred = bool(want_pred)
+        opt = Options(int(validate), int(block_size), int(thread_tile), int(schedule), 0, int(arith),
+                      status.data_ptr() if status is not None else None,
+                      arith_used.data_ptr() if arith_used is not None else None)
+        self._s = ctypes.c_void_p()
+        st = lib().apsp_stepper_create(self.n, INT32 if dtype in ("int32", INT32) else FLOAT32,
+                                       int(self.want_pred), ctypes.byref(opt), ctypes.byref(self._s))
+        if st != SUCCESS:
+            raise APSPError(st, "apsp_stepper_create")
+
+    def begin(self, dist, pred=None, stream=None) -> None:
+        assert dist.is_cuda and dist.is_contiguous() and tuple(dist.shape) == (self.n, self.n)
+        st = lib().apsp_stepper_begin(self._s, dist.data_ptr(), pred.data_ptr() if pred is not None else None,
+                                      _stream_ptr(stream))
+        if st != SUCCESS:
+            raise APSPError(st, "apsp_stepper_begin")
+
+    def step(self, rounds: int = 1) -> bool:
+        done = ctypes.c_int32(0)
+        st = lib().apsp_stepper_step(self._s, int(rounds), ctypes.byref(done))
+        if st != SUCCESS:
+            raise APSPError(st, "apsp_stepper_step")
+        return bool(done.value)
+
+    @property
+    def rounds(self) -> int:
+        return int(lib().apsp_stepper_rounds(self._s))
+
+    def destroy(self) -> None:
+        if self._s:
+            lib().apsp_stepper_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 PATH_TOO_LONG, PATH_BAD_QUERY, PATH_BROKEN = -1, -2, -3

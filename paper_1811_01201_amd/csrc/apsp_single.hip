@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <tuple>
 #include <type_traits>
 #include <map>
@@ -855,6 +856,15 @@ std::vector<ProfRecord> g_prof;
 
 thread_local bool t_capturing = false;  // launches are being recorded into a hipGraph
 
+// Operations of a solve recorded for a stepper (see enq below).
+struct Recorder {
+    std::vector<std::function<hipError_t()>> ops;
+    std::vector<size_t> marks;  // index of the first operation of each round
+};
+struct AuxStream;
+thread_local Recorder *t_rec = nullptr;
+thread_local AuxStream *t_aux = nullptr;  // the recording stepper's second stream
+
 struct ProfScope {
     ProfRecord rec{};
     hipStream_t s;
@@ -862,7 +872,7 @@ struct ProfScope {
     ProfScope(int kind, double updates, hipStream_t stream) : s(stream) {
         {
             std::lock_guard<std::mutex> lk(g_prof_mu);
-            on = g_prof_on && !t_capturing && kind >= 0;
+            on = g_prof_on && !t_capturing && !t_rec && kind >= 0;
         }
         if (!on) return;
         rec.kind = kind;
@@ -922,6 +932,37 @@ apsp_status_t aux_stream(int dev, hipStream_t s, AuxStream **out) {
     return APSP_SUCCESS;
 }
 
+// ------------------------------------------------------------ recording
+// The launch sequence of a solve never depends on the data (every
+// data-dependent choice is a device word), so it can be recorded once and
+// issued later in slices: a stepper (apsp_stepper_*) records it, with its
+// own work memory and second stream, and issues it a few rounds at a time.
+// Without a recorder every operation is issued at once.
+template <class K, class... A>
+inline void enq(K kernel, dim3 grid, dim3 block, hipStream_t s, A... args) {
+    if (t_rec) {
+        t_rec->ops.push_back([=]() -> hipError_t {
+            hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+            return hipGetLastError();
+        });
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    }
+}
+inline hipError_t enq_record(hipEvent_t e, hipStream_t s) {
+    if (!t_rec) return hipEventRecord(e, s);
+    t_rec->ops.push_back([=]() { return hipEventRecord(e, s); });
+    return hipSuccess;
+}
+inline hipError_t enq_wait(hipStream_t s, hipEvent_t e) {
+    if (!t_rec) return hipStreamWaitEvent(s, e, 0);
+    t_rec->ops.push_back([=]() { return hipStreamWaitEvent(s, e, 0); });
+    return hipSuccess;
+}
+inline void round_mark() {
+    if (t_rec) t_rec->marks.push_back(t_rec->ops.size());
+}
+
 // The round loop on a work matrix of size ld (a multiple of BS).
 //
 // One stream, in order: for each round r, phase 1, phase 2, phase 3.
@@ -951,8 +992,12 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     AuxStream *aux = nullptr;
     // the split pays off once phase 3 is throughput- rather than latency-bound
     if (lookahead && R >= 3 && ld >= 4096) {
-        apsp_status_t st = aux_stream(dev, s, &aux);
-        if (st != APSP_SUCCESS) return st;
+        if (t_aux) {
+            aux = t_aux;
+        } else {
+            apsp_status_t st = aux_stream(dev, s, &aux);
+            if (st != APSP_SUCCESS) return st;
+        }
     }
     // the blocked closure is slower on its own (one wavefront per SIMD) but
     // starts in any slot a phase-3 workgroup frees: it pays off where
@@ -964,18 +1009,18 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
         ProfScope ps(prof ? kPhase1 : -1, bs3, s);
         if (blocked_p1) {
             if constexpr (kBlockedP1)
-                hipLaunchKernelGGL((phase1_blocked_kernel<Ar>), dim3(1), dim3(256), 0, s, X, ld, (int64_t)r * BS,
+                enq((phase1_blocked_kernel<Ar>), dim3(1), dim3(256), s, X, ld, (int64_t)r * BS,
                                    ar, skip);
         } else {
-            hipLaunchKernelGGL((phase1_kernel<Ar, Alt, BS, TT>), dim3(1), dim3(P1S<Ar, BS, TT>::NTH), 0, s, X,
+            enq((phase1_kernel<Ar, Alt, BS, TT>), dim3(1), dim3(P1S<Ar, BS, TT>::NTH), s, X,
                                ld, (int64_t)r * BS, ar, alt, mode, skip);
         }
     };
     auto p2 = [&](int r) {
         if (nt2 <= 0) return;
         ProfScope ps(prof ? kPhase2 : -1, 2.0 * bs3 * (ld / BS - 1), s);
-        hipLaunchKernelGGL((phase2_kernel<Ar, Alt, BS, P2W, TT>), dim3(2 * nt2),
-                           dim3((BS / TT) * (P2W / TT)), 0, s, X, ld, (int64_t)r * BS, nt2, ar, alt, mode,
+        enq((phase2_kernel<Ar, Alt, BS, P2W, TT>), dim3(2 * nt2),
+                           dim3((BS / TT) * (P2W / TT)), s, X, ld, (int64_t)r * BS, nt2, ar, alt, mode,
                            skip);
     };
     auto p3_part = [&](int r, int set, hipStream_t st, int64_t seq0, int64_t seq_end) {
@@ -986,13 +1031,13 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
         const dim3 grid(8 * per_xcd), block((MT / TT) * (MT / TT));
         const int a = (int)seq0, b = (int)seq_end;
         if (set == kAll)
-            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kAll, TT>), grid, block, 0, st, X, ld, r,
+            enq((phase3_kernel<Ar, Alt, BS, MT, kAll, TT>), grid, block, st, X, ld, r,
                                per_xcd, a, b, ar, alt, mode, skip);
         else if (set == kRest)
-            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kRest, TT>), grid, block, 0, st, X, ld, r,
+            enq((phase3_kernel<Ar, Alt, BS, MT, kRest, TT>), grid, block, st, X, ld, r,
                                per_xcd, a, b, ar, alt, mode, skip);
         else
-            hipLaunchKernelGGL((phase3_kernel<Ar, Alt, BS, MT, kCross, TT>), grid, block, 0, st, X, ld, r,
+            enq((phase3_kernel<Ar, Alt, BS, MT, kCross, TT>), grid, block, st, X, ld, r,
                                per_xcd, a, b, ar, alt, mode, skip);
     };
     auto p3 = [&](int r, int set, hipStream_t st) { p3_part(r, set, st, 0, p3_count(set, nt, pb)); };
@@ -1005,25 +1050,28 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     };
     if (!aux) {
         for (int r = 0; r < R; ++r) {
+            round_mark();
             p1(r);
             p2(r);
             p3(r, kAll, s);
         }
     } else {
+        round_mark();
         p1(0);
         p2(0);
-        APSP_HIP(hipEventRecord(aux->panels, s));
+        APSP_HIP(enq_record(aux->panels, s));
         for (int r = 0; r + 1 < R; ++r) {
-            APSP_HIP(hipStreamWaitEvent(aux->s, aux->panels, 0));
+            if (r > 0) round_mark();
+            APSP_HIP(enq_wait(aux->s, aux->panels));
             p3_rest(r, aux->s);
-            if (r > 0) APSP_HIP(hipStreamWaitEvent(s, aux->rest, 0));
-            APSP_HIP(hipEventRecord(aux->rest, aux->s));
+            if (r > 0) APSP_HIP(enq_wait(s, aux->rest));
+            APSP_HIP(enq_record(aux->rest, aux->s));
             p3(r, kCross, s);
             p1(r + 1);
             p2(r + 1);
-            APSP_HIP(hipEventRecord(aux->panels, s));
+            APSP_HIP(enq_record(aux->panels, s));
         }
-        APSP_HIP(hipStreamWaitEvent(s, aux->rest, 0));
+        APSP_HIP(enq_wait(s, aux->rest));
         p3(R - 1, kAll, s);
     }
     APSP_HIP(hipGetLastError());
@@ -1137,15 +1185,15 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
     const int64_t ld = (n + bs - 1) / bs * bs;
     int32_t *status = opt.d_status;
     const int32_t *skip = nullptr;
-    if (status) hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(1), 0, s, status);
+    if (status) enq(status_init_kernel, dim3(1), dim3(1), s, status);
     if (opt.validate) {
-        hipLaunchKernelGGL((validate_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, dist, n,
+        enq((validate_kernel<T>), dim3(grid_for(n * n)), dim3(256), s, dist, n,
                            apsp_weight_bound(n), status);
         skip = status;
     }
     constexpr T inf = std::is_same_v<T, int32_t> ? T(kInf32) : T(__builtin_huge_valf());
     const bool f32w = std::is_same_v<T, int32_t> && use_f32w(n, APSP_INT32, with_pred, opt.arith);
-    if (!f32w && opt.d_arith) hipLaunchKernelGGL(store_word_kernel, dim3(1), dim3(1), 0, s, opt.d_arith, 0);
+    if (!f32w && opt.d_arith) enq(store_word_kernel, dim3(1), dim3(1), s, opt.d_arith, 0);
     if constexpr (std::is_same_v<T, int32_t>) {
         if (f32w) {
             // float32 pass (exact while watched), then an int32 pass that the
@@ -1156,29 +1204,29 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
             if (st != APSP_SUCCESS) return st;
             float *Xf = (float *)w;
             int32_t *words = (int32_t *)((char *)w + mat);
-            hipLaunchKernelGGL(f32w_init_kernel, dim3(1), dim3(1), 0, s, words);
+            enq(f32w_init_kernel, dim3(1), dim3(1), s, words);
             const int vec = (n % 4 == 0) && ((uintptr_t)dist % 16 == 0);
-            hipLaunchKernelGGL(f32w_in_kernel, grid_rows(ld, ld), dim3(256), 0, s, dist, n, Xf, ld, words, skip,
+            enq(f32w_in_kernel, grid_rows(ld, ld), dim3(256), s, dist, n, Xf, ld, words, skip,
                                vec);
             ArF32W arw;
             arw.big = words;
             st = run_rounds_bs<ArF32W>(bs, tt, lookahead, Xf, ld, arw, s, skip);
             if (st != APSP_SUCCESS) return st;
-            hipLaunchKernelGGL(f32w_out_kernel, grid_rows(n, n), dim3(256), 0, s, Xf, ld, dist, n, status, words,
+            enq(f32w_out_kernel, grid_rows(n, n), dim3(256), s, Xf, ld, dist, n, status, words,
                                skip, vec);
-            hipLaunchKernelGGL(f32w_gate_kernel, dim3(1), dim3(1), 0, s, words, skip, opt.d_arith);
+            enq(f32w_gate_kernel, dim3(1), dim3(1), s, words, skip, opt.d_arith);
             const int32_t *gate = words + 1;
             int32_t *Xi = dist;
             if (!((ld == n) && ((uintptr_t)dist % 16 == 0))) {
                 Xi = (int32_t *)w;  // the float32 matrix is no longer needed
-                hipLaunchKernelGGL((pad_in_kernel<int32_t>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n,
+                enq((pad_in_kernel<int32_t>), dim3(grid_for(ld * ld)), dim3(256), s, dist, n,
                                    Xi, ld, kInf32, gate);
             }
             // in order (3 launches per round): when the gate stays closed,
             // every launch still costs its dispatch
             st = run_rounds_bs<ArI32>(bs, tt, false, Xi, ld, ArI32{}, s, gate, NoAlt{}, nullptr, false);
             if (st != APSP_SUCCESS) return st;
-            hipLaunchKernelGGL((finalize_kernel<int32_t>), dim3(grid_for(n * n)), dim3(256), 0, s, Xi, ld, dist,
+            enq((finalize_kernel<int32_t>), dim3(grid_for(n * n)), dim3(256), s, Xi, ld, dist,
                                n, status, gate);
             APSP_HIP(hipGetLastError());
             return APSP_SUCCESS;
@@ -1199,34 +1247,34 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         int32_t *words = (int32_t *)((char *)w + 2 * mat);
         const int S = pp_bits(n);
         const int vec = (n % 4 == 0) && ((uintptr_t)dist % 16 == 0);
-        hipLaunchKernelGGL(pp_init_kernel, dim3(1), dim3(1), 0, s, words);
-        hipLaunchKernelGGL((pp_in_kernel<T>), grid_rows(sh.ld, sh.ld), dim3(256), 0, s, dist, n, X, Bm, sh.ld, S,
+        enq(pp_init_kernel, dim3(1), dim3(1), s, words);
+        enq((pp_in_kernel<T>), grid_rows(sh.ld, sh.ld), dim3(256), s, dist, n, X, Bm, sh.ld, S,
                            (float)apsp_weight_bound(n), words, skip, vec);
-        hipLaunchKernelGGL(pp_rounds_gate_kernel, dim3(1), dim3(1), 0, s, words, skip);
+        enq(pp_rounds_gate_kernel, dim3(1), dim3(1), s, words, skip);
         ArF32W arw;
         arw.big = words + kPPBig;
         st = run_rounds_bs<ArF32W>(sh.bsd, ttd, lookahead, X, sh.ld, arw, s, words + kPPRounds);
         if (st != APSP_SUCCESS) return st;
-        hipLaunchKernelGGL((pp_out_kernel<T>), grid_rows(n, n), dim3(256), 0, s, X, sh.ld, dist, n, S, words,
+        enq((pp_out_kernel<T>), grid_rows(n, n), dim3(256), s, X, sh.ld, dist, n, S, words,
                            status, skip, vec);
-        hipLaunchKernelGGL(pp_product_gate_kernel, dim3(1), dim3(1), 0, s, words);
+        enq(pp_product_gate_kernel, dim3(1), dim3(1), s, words);
         {
             const int nt = (int)((n + 127) / 128);
             const int per_xcd = (nt * nt + 7) / 8;
             const int kcount = (int)((n + 31) / 32 * 32);
             ProfScope ps(kPredProduct, (double)n * (double)n * (double)kcount, s);
-            hipLaunchKernelGGL((pp_product_kernel<T>), dim3(8 * per_xcd), dim3(256), 0, s, X, Bm, sh.ld, kcount,
+            enq((pp_product_kernel<T>), dim3(8 * per_xcd), dim3(256), s, X, Bm, sh.ld, kcount,
                                dist, pred, n, S, nt, per_xcd, words, skip);
         }
-        hipLaunchKernelGGL(pp_gate_kernel, dim3(1), dim3(1), 0, s, words, skip, opt.d_arith);
+        enq(pp_gate_kernel, dim3(1), dim3(1), s, words, skip, opt.d_arith);
         const int32_t *gate = words + kPPGate;
-        hipLaunchKernelGGL((pp_restore_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, Bm, sh.ld, dist, n, S,
+        enq((pp_restore_kernel<T>), dim3(grid_for(n * n)), dim3(256), s, Bm, sh.ld, dist, n, S,
                            words);
         // the fallback: the exact fp64-key recurrence (pairs for float32
         // weights that are not integers within the bound)
         int32_t *mode = std::is_same_v<T, float> ? words + kPPMode : nullptr;
         ArKey ar{pred_bits(sh.ldf)};
-        hipLaunchKernelGGL((pred_pack_kernel<T>), dim3(grid_for(sh.ldf * sh.ldf)), dim3(256), 0, s, dist, n, w,
+        enq((pred_pack_kernel<T>), dim3(grid_for(sh.ldf * sh.ldf)), dim3(256), s, dist, n, w,
                            sh.ldf, ar.S, mode, gate);
         // in order (3 launches per round), as a closed gate still costs
         // every launch's dispatch
@@ -1235,7 +1283,7 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         else
             st = run_rounds_bs<ArKey>(sh.bsf, ttf, false, w, sh.ldf, ar, s, gate, NoAlt{}, nullptr, false);
         if (st != APSP_SUCCESS) return st;
-        hipLaunchKernelGGL((pred_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, w, sh.ldf, dist, pred,
+        enq((pred_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), s, w, sh.ldf, dist, pred,
                            n, ar.S, mode, status, gate);
         APSP_HIP(hipGetLastError());
         return APSP_SUCCESS;
@@ -1248,7 +1296,7 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
             apsp_status_t st = workspace(dev, s, (size_t)(ld * ld) * sizeof(T), &w);
             if (st != APSP_SUCCESS) return st;
             X = (T *)w;
-            hipLaunchKernelGGL((pad_in_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n, X,
+            enq((pad_in_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), s, dist, n, X,
                                ld, inf, skip);
         }
         apsp_status_t st;
@@ -1257,7 +1305,7 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         else
             st = run_rounds_bs<ArF32>(bs, tt, lookahead, X, ld, ArF32{}, s, skip);
         if (st != APSP_SUCCESS) return st;
-        hipLaunchKernelGGL((finalize_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, X, ld, dist, n,
+        enq((finalize_kernel<T>), dim3(grid_for(n * n)), dim3(256), s, X, ld, dist, n,
                            status, skip);
     } else {
         // ld^2 8-byte elements, then one int32 mode word
@@ -1269,18 +1317,18 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         ArKey ar{pred_bits(ld)};
         if constexpr (std::is_same_v<T, float>) {
             mode = (int32_t *)((char *)w + mat);
-            hipLaunchKernelGGL(mode_init_kernel, dim3(1), dim3(1), 0, s, mode);
-            hipLaunchKernelGGL(integral_check_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, dist, n,
+            enq(mode_init_kernel, dim3(1), dim3(1), s, mode);
+            enq(integral_check_kernel, dim3(grid_for(n * n)), dim3(256), s, dist, n,
                                (float)apsp_weight_bound(n), mode);
         }
-        hipLaunchKernelGGL((pred_pack_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), 0, s, dist, n, w,
+        enq((pred_pack_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), s, dist, n, w,
                            ld, ar.S, mode, skip);
         if constexpr (std::is_same_v<T, float>)
             st = run_rounds_bs<ArKey, ArLexF32>(bs, tt, lookahead, w, ld, ar, s, skip, ArLexF32{}, mode);
         else
             st = run_rounds_bs<ArKey>(bs, tt, lookahead, w, ld, ar, s, skip);
         if (st != APSP_SUCCESS) return st;
-        hipLaunchKernelGGL((pred_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), 0, s, w, ld, dist,
+        enq((pred_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), s, w, ld, dist,
                            pred, n, ar.S, mode, status, skip);
     }
     APSP_HIP(hipGetLastError());
@@ -1485,6 +1533,148 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out) {
         hipEventDestroy(r.stop);
     }
     return st;
+}
+
+}  // extern "C"
+
+// A recorded solve issued in slices of rounds (round-level preemption): it
+// owns its work memory and second stream, so its slices may interleave with
+// any other work, including other steppers on the same caller stream.
+struct apsp_stepper {
+    int device = 0;
+    int64_t n = 0;
+    apsp_dtype_t dtype = APSP_INT32;
+    bool want_pred = false;
+    apsp_options_t opt{};
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    AuxStream aux{};
+    Recorder rec;
+    hipStream_t stream = nullptr;
+    size_t next = 0;  // next operation to issue
+    bool begun = false;
+};
+
+namespace {
+
+struct RecordScope {
+    RecordScope(Recorder *r, AuxStream *a) {
+        t_rec = r;
+        t_aux = a;
+    }
+    ~RecordScope() {
+        t_rec = nullptr;
+        t_aux = nullptr;
+    }
+};
+
+apsp_status_t check_options(int64_t n, apsp_dtype_t dtype, bool with_pred, const apsp_options_t &opt) {
+    if (n < 0 || n > kMaxN) return APSP_ERROR_INVALID_ARGUMENT;
+    if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.block_size != 0 && opt.block_size != 64 && opt.block_size != 128 && opt.block_size != 256)
+        return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.thread_tile != 0 && opt.thread_tile != 4 && opt.thread_tile != 8) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.thread_tile == 4 && opt.block_size != 0 && opt.block_size != 64) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.block_size == 256 && with_pred) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.arith < 0 || opt.arith > 2) return APSP_ERROR_INVALID_ARGUMENT;
+    return APSP_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+apsp_status_t apsp_stepper_create(int64_t n, apsp_dtype_t dtype, int32_t want_pred, const apsp_options_t *options,
+                                  apsp_stepper_t **out) {
+    if (!out) return APSP_ERROR_INVALID_ARGUMENT;
+    *out = nullptr;
+    apsp_options_t opt{};
+    if (options) opt = *options;
+    opt.use_graph = 0;  // a stepper issues recorded operations itself
+    apsp_status_t st = check_options(n, dtype, want_pred != 0, opt);
+    if (st != APSP_SUCCESS) return st;
+    auto *p = new apsp_stepper();
+    p->n = n;
+    p->dtype = dtype;
+    p->want_pred = want_pred != 0;
+    p->opt = opt;
+    hipError_t e = hipGetDevice(&p->device);
+    // work memory for any alignment of the caller's matrix
+    p->ws_bytes = n ? work_bytes(n, p->want_pred, opt.block_size, false, dtype, opt.arith) : 0;
+    if (e == hipSuccess && p->ws_bytes) e = hipMalloc(&p->ws, p->ws_bytes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->aux.s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->aux.panels, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->aux.rest, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        apsp_stepper_destroy(p);
+        return e == hipErrorOutOfMemory ? APSP_ERROR_OUT_OF_MEMORY : APSP_ERROR_HIP;
+    }
+    *out = p;
+    return APSP_SUCCESS;
+}
+
+apsp_status_t apsp_stepper_begin(apsp_stepper_t *p, void *dist, int32_t *pred, hipStream_t stream) {
+    if (!p) return APSP_ERROR_INVALID_ARGUMENT;
+    if ((pred != nullptr) != p->want_pred) return APSP_ERROR_INVALID_ARGUMENT;
+    if (p->n > 0 && (!dist || ((uintptr_t)dist % 4) != 0 || ((uintptr_t)pred % 4) != 0))
+        return APSP_ERROR_INVALID_ARGUMENT;
+    if (p->begun && p->next < p->rec.ops.size()) return APSP_ERROR_NOT_READY;  // the last solve is not issued
+    p->rec.ops.clear();
+    p->rec.marks.clear();
+    p->next = 0;
+    p->begun = false;
+    if (p->n > 0) {
+        int dev = 0;
+        APSP_HIP(hipGetDevice(&dev));
+        if (dev != p->device) return APSP_ERROR_INVALID_ARGUMENT;
+        RecordScope rs(&p->rec, &p->aux);
+        apsp_status_t st = solve_direct(dist, pred, p->n, p->dtype, stream, p->opt, p->ws, p->ws_bytes);
+        if (st != APSP_SUCCESS) {
+            p->rec.ops.clear();
+            p->rec.marks.clear();
+            return st;
+        }
+    }
+    p->stream = stream;
+    p->begun = true;
+    return APSP_SUCCESS;
+}
+
+apsp_status_t apsp_stepper_step(apsp_stepper_t *p, int32_t rounds, int32_t *done) {
+    if (!p || !p->begun) return APSP_ERROR_INVALID_ARGUMENT;
+    const auto &ops = p->rec.ops;
+    const auto &marks = p->rec.marks;
+    size_t stop = ops.size();
+    if (rounds > 0) {
+        // rounds whose first operation is already issued, then `rounds` more
+        const size_t started = (size_t)(std::lower_bound(marks.begin(), marks.end(), p->next) - marks.begin());
+        if (started + (size_t)rounds < marks.size()) stop = marks[started + (size_t)rounds];
+    }
+    for (; p->next < stop; ++p->next) {
+        const hipError_t e = ops[p->next]();
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            return APSP_ERROR_HIP;
+        }
+    }
+    if (done) *done = p->next == ops.size() ? 1 : 0;
+    return APSP_SUCCESS;
+}
+
+int64_t apsp_stepper_rounds(const apsp_stepper_t *p) { return p ? (int64_t)p->rec.marks.size() : -1; }
+
+apsp_status_t apsp_stepper_destroy(apsp_stepper_t *p) {
+    if (!p) return APSP_ERROR_INVALID_ARGUMENT;
+    if (p->stream || p->begun) hipStreamSynchronize(p->stream);
+    if (p->aux.s) hipStreamSynchronize(p->aux.s);
+    if (p->ws) hipFree(p->ws);
+    if (p->aux.panels) hipEventDestroy(p->aux.panels);
+    if (p->aux.rest) hipEventDestroy(p->aux.rest);
+    if (p->aux.s) hipStreamDestroy(p->aux.s);
+    delete p;
+    return APSP_SUCCESS;
 }
 
 apsp_status_t apsp_release_workspace(void) {

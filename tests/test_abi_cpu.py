@@ -157,3 +157,20 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "single GPU" in r.stderr
+
+
+def test_stepper_host_argument_errors():
+    L = apsp.lib()
+    out = ctypes.c_void_p()
+    bad = apsp.Options(0, 256, 0, 0, 0, 0, None)  # block 256 with predecessors
+    assert L.apsp_stepper_create(100, apsp.INT32, 1, ctypes.byref(bad), ctypes.byref(out)) == apsp.INVALID_ARGUMENT
+    assert L.apsp_stepper_create(-1, apsp.INT32, 0, None, ctypes.byref(out)) == apsp.INVALID_ARGUMENT
+    assert L.apsp_stepper_create(10, 5, 0, None, ctypes.byref(out)) == apsp.INVALID_ARGUMENT
+    assert L.apsp_stepper_create(10, apsp.INT32, 0, None, None) == apsp.INVALID_ARGUMENT
+    bad_arith = apsp.Options(0, 0, 0, 0, 0, 4, None)
+    assert L.apsp_stepper_create(10, apsp.INT32, 0, ctypes.byref(bad_arith), ctypes.byref(out)) == \
+        apsp.INVALID_ARGUMENT
+    assert L.apsp_stepper_begin(None, None, None, None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_stepper_step(None, 1, None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_stepper_rounds(None) == -1
+    assert L.apsp_stepper_destroy(None) == apsp.INVALID_ARGUMENT
