@@ -180,9 +180,10 @@ def serving_leg(count: int):
     base = {"int32": torch.from_numpy(synth.single_int32(nmax, 0.2, seed=synth.BASE_SEED + 4)).pin_memory(),
             "float32": torch.from_numpy(synth.single_f32int(nmax, 0.2, seed=synth.BASE_SEED + 4)).pin_memory()}
 
-    def run(rate, n_req, fifo=False):
+    def run(rate, n_req, fifo=False, slice_rounds=0):
         reqs = synth.requests(n_req, rate if rate else 1e9)
-        kw = dict(max_inflight=1, batch_max_n=-1) if fifo else dict(max_inflight=64, n_streams=8)
+        kw = dict(max_inflight=1, batch_max_n=-1) if fifo else dict(max_inflight=64, n_streams=8,
+                                                                      slice_rounds=slice_rounds)
         sv = apsp.Server(**kw)
         tickets = []
         done = threading.Event()
@@ -218,9 +219,15 @@ def serving_leg(count: int):
         sv.destroy()
         if errors:
             raise RuntimeError(f"serving requests failed: {errors[:5]}")
-        return {"offered_rate": round(rate, 1) if rate else "saturated", "requests": n_req,
-                "solves_per_s": round(s["solves_per_s"], 1), "p50_ms": round(s["p50_latency_ms"], 3),
-                "p99_ms": round(s["p99_latency_ms"], 3)}
+        out = {"offered_rate": round(rate, 1) if rate else "saturated", "requests": n_req,
+               "solves_per_s": round(s["solves_per_s"], 1), "p50_ms": round(s["p50_latency_ms"], 3),
+               "p99_ms": round(s["p99_latency_ms"], 3)}
+        if not fifo:  # coalesced (n <= 512) and large requests separately
+            out.update({"small_p50_ms": round(s["p50_small_ms"], 3), "small_p99_ms": round(s["p99_small_ms"], 3),
+                        "large_p50_ms": round(s["p50_large_ms"], 3), "large_p99_ms": round(s["p99_large_ms"], 3)})
+        if slice_rounds:
+            out["slice_rounds"] = slice_rounds
+        return out
 
     sat = run(None, count)
     out = {"workload": "Poisson stream, n=round(exp U[ln32,ln8192]), int32/float32 integer weights "
@@ -228,6 +235,8 @@ def serving_leg(count: int):
            "continuous_batching": [sat], "fifo_one_at_a_time": [run(None, max(100, count // 2), fifo=True)]}
     for f in (0.5, 0.9):
         out["continuous_batching"].append(run(f * sat["solves_per_s"], count))
+    # round-level preemption: large solves issued 4 rounds at a time
+    out["continuous_batching_sliced"] = [run(0.9 * sat["solves_per_s"], count, slice_rounds=4)]
     return out
 
 

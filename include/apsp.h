@@ -376,6 +376,10 @@ typedef struct {
     int32_t max_queue;        /* pending requests before submit fails (0 = 4096) */
     int32_t batch_max_n;      /* requests with n <= this are coalesced into batched launches
                                  (0 = 512, negative = never; at most 1024) */
+    int32_t slice_rounds;     /* 0: a large request's whole solve is issued at admission;
+                                 > 0: it is issued this many rounds at a time (a stepper,
+                                 see apsp_stepper_*), the next slice once the last one has
+                                 finished, so later requests are not queued behind it */
 } apsp_server_config_t;
 
 typedef struct {
@@ -395,6 +399,8 @@ typedef struct {
     int64_t bytes_in_use;
     double p50_latency_ms, p99_latency_ms; /* submit -> result ready, completed requests */
     double solves_per_s;                   /* completed / (last completion - first submit) */
+    double p50_small_ms, p99_small_ms;     /* the same for requests coalesced into batched launches */
+    double p50_large_ms, p99_large_ms;     /* ... and for the others (0 when there were none) */
 } apsp_server_stats_t;
 
 apsp_status_t apsp_server_create(const apsp_server_config_t *config, apsp_server_t **out);

@@ -386,7 +386,7 @@ def solve_batched(packed_dist, ns, offsets, packed_pred=None, stream=None) -> No
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
                 ("n_streams", ctypes.c_int32), ("max_queue", ctypes.c_int32),
-                ("batch_max_n", ctypes.c_int32)]
+                ("batch_max_n", ctypes.c_int32), ("slice_rounds", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -399,7 +399,9 @@ class ServerStats(ctypes.Structure):
                 ("failed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("inflight", ctypes.c_int64),
                 ("bytes_in_use", ctypes.c_int64), ("p50_latency_ms", ctypes.c_double),
-                ("p99_latency_ms", ctypes.c_double), ("solves_per_s", ctypes.c_double)]
+                ("p99_latency_ms", ctypes.c_double), ("solves_per_s", ctypes.c_double),
+                ("p50_small_ms", ctypes.c_double), ("p99_small_ms", ctypes.c_double),
+                ("p50_large_ms", ctypes.c_double), ("p99_large_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -410,10 +412,11 @@ class Server:
     include/apsp.h).  Weights are numpy arrays (copied at submit) or, with
     borrow=True, pinned host tensors that stay alive until completion."""
 
-    def __init__(self, hbm_budget_bytes=0, max_inflight=0, n_streams=0, max_queue=0, batch_max_n=0):
+    def __init__(self, hbm_budget_bytes=0, max_inflight=0, n_streams=0, max_queue=0, batch_max_n=0,
+                 slice_rounds=0):
         self._h = ctypes.c_void_p()
         cfg = ServerConfig(int(hbm_budget_bytes), int(max_inflight), int(n_streams), int(max_queue),
-                           int(batch_max_n))
+                           int(batch_max_n), int(slice_rounds))
         st = lib().apsp_server_create(ctypes.byref(cfg), ctypes.byref(self._h))
         if st != SUCCESS:
             raise APSPError(st, "apsp_server_create")

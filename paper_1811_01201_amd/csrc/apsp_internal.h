@@ -44,6 +44,11 @@ apsp_status_t solve_internal(void *dist, int32_t *pred, int64_t n, apsp_dtype_t 
 // Work memory solve_internal needs for (n, pred) with automatic block size
 // and a 16-byte aligned dist.
 size_t solve_work_bytes(int64_t n, apsp_dtype_t dtype, bool with_pred);
+// Steppers with lent work memory and destruction without
+// stream synchronisation, for the server.
+apsp_status_t stepper_create(int64_t n, apsp_dtype_t dtype, bool want_pred, const apsp_options_t *options,
+                             bool lend, void *ws, size_t ws_bytes, apsp_stepper_t **out);
+apsp_status_t stepper_destroy(apsp_stepper_t *p, bool sync);
 
 // Batched launch on caller-owned metadata (see apsp_batched.hip).
 struct BatchLaunch {

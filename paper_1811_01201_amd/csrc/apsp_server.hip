@@ -9,7 +9,11 @@
 //     launch on the batch stream (their results live in that launch's packed
 //     arena until every member is released);
 //   * larger requests get their own buffers and run apsp_solve on one of
-//     n_streams streams, so they overlap each other and the batched work.
+//     n_streams streams, so they overlap each other and the batched work;
+//     with slice_rounds > 0 their launch sequence goes out slice_rounds
+//     rounds at a time (a stepper), the next slice only once the last one
+//     has finished, so requests admitted meanwhile are not queued behind a
+//     large solve's remaining rounds (round-level preemption).
 // Results stay resident in device memory until released; releasing returns
 // their bytes to the budget, which admits waiting requests.  Completion is
 // observed by polling a per-launch event; latency = completion observed -
@@ -62,6 +66,10 @@ struct Request {
     int32_t *d_status = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    apsp_stepper_t *stepper = nullptr;  // sliced large path
+    hipEvent_t slice_done = nullptr;
+    bool all_issued = true;
+    apsp_status_t slice_error = APSP_SUCCESS;
     // batched path
     std::shared_ptr<Group> group;
     int64_t group_off = 0;  // element offset in the group's arena
@@ -111,6 +119,7 @@ struct apsp_server {
     // statistics
     int64_t submitted = 0, completed = 0, failed = 0, cancelled = 0;
     std::vector<double> latencies_ms;
+    std::vector<char> latency_large;  // per latency: a large (not coalesced) request
     Clock::time_point first_submit, last_done;
     bool have_first = false;
 
@@ -135,9 +144,33 @@ bool apsp_server::poll_locked() {
     bool any = false;
     for (auto it = running_large.begin(); it != running_large.end();) {
         Request *r = *it;
+        if (!r->all_issued) {
+            // sliced: the next slice once the previous one has finished
+            if (hipEventQuery(r->slice_done) == hipSuccess) {
+                int32_t last = 0;
+                apsp_status_t st = apsp_stepper_step(r->stepper, cfg.slice_rounds, &last);
+                hipError_t e = hipSuccess;
+                if (st == APSP_SUCCESS) e = hipEventRecord(last ? r->done : r->slice_done, r->stream);
+                if (st != APSP_SUCCESS || e != hipSuccess) {
+                    // what was issued still runs: let it finish, then fail the request
+                    r->slice_error = st != APSP_SUCCESS ? st : APSP_ERROR_HIP;
+                    hipStreamSynchronize(r->stream);
+                    hipEventRecord(r->done, r->stream);
+                    last = 1;
+                }
+                if (last) r->all_issued = true;
+            }
+            ++it;
+            continue;
+        }
         if (hipEventQuery(r->done) == hipSuccess) {
             int32_t st = 0;
             hipMemcpy(&st, r->d_status, sizeof(int32_t), hipMemcpyDeviceToHost);
+            if (r->slice_error != APSP_SUCCESS) st = r->slice_error;
+            if (r->stepper) stepper_destroy(r->stepper, false);  // its work has completed
+            r->stepper = nullptr;
+            if (r->slice_done) hipEventDestroy(r->slice_done);
+            r->slice_done = nullptr;
             if (r->d_work) hipFreeAsync(r->d_work, r->stream);
             r->d_work = nullptr;
             bytes_in_use -= (int64_t)r->transient;
@@ -186,6 +219,7 @@ void apsp_server::finish(Request *r, apsp_status_t st) {
         ++failed;
     }
     latencies_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+    latency_large.push_back(r->group ? 0 : 1);
     last_done = r->t_done;
     if (r->h_staging) {
         hipHostFree(r->h_staging);
@@ -230,17 +264,33 @@ void apsp_server::launch_large(Request *r) {
         hipMemcpy2DAsync(r->d_dist, (size_t)r->n * 4, r->h_src, (size_t)r->h_ld * 4, (size_t)r->n * 4,
                          (size_t)r->n, hipMemcpyHostToDevice, s) != hipSuccess)
         st = APSP_ERROR_HIP;
-    if (st == APSP_SUCCESS) {
-        apsp_options_t opt{};
-        opt.d_status = r->d_status;
-        st = solve_internal(r->d_dist, r->d_pred, r->n, r->dtype, s, opt, r->d_work, r->transient);
-    }
-    if (st == APSP_SUCCESS && (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess ||
-                               hipEventRecord(r->done, s) != hipSuccess))
+    apsp_options_t opt{};
+    opt.d_status = r->d_status;
+    if (st == APSP_SUCCESS && hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess)
         st = APSP_ERROR_HIP;
+    if (st == APSP_SUCCESS && cfg.slice_rounds > 0) {
+        // sliced: record the solve, issue its first slice
+        int32_t last = 0;
+        st = stepper_create(r->n, r->dtype, r->want_pred, &opt, true, r->d_work, r->transient, &r->stepper);
+        if (st == APSP_SUCCESS && hipEventCreateWithFlags(&r->slice_done, hipEventDisableTiming) != hipSuccess)
+            st = APSP_ERROR_HIP;
+        if (st == APSP_SUCCESS) st = apsp_stepper_begin(r->stepper, r->d_dist, r->d_pred, s);
+        if (st == APSP_SUCCESS) st = apsp_stepper_step(r->stepper, cfg.slice_rounds, &last);
+        if (st == APSP_SUCCESS && hipEventRecord(last ? r->done : r->slice_done, s) != hipSuccess)
+            st = APSP_ERROR_HIP;
+        r->all_issued = last != 0;
+    } else if (st == APSP_SUCCESS) {
+        st = solve_internal(r->d_dist, r->d_pred, r->n, r->dtype, s, opt, r->d_work, r->transient);
+        if (st == APSP_SUCCESS && hipEventRecord(r->done, s) != hipSuccess) st = APSP_ERROR_HIP;
+    }
     r->state = RState::Running;
     if (st != APSP_SUCCESS) {
         hipStreamSynchronize(s);
+        if (r->stepper) stepper_destroy(r->stepper, false);
+        r->stepper = nullptr;
+        if (r->slice_done) hipEventDestroy(r->slice_done);
+        r->slice_done = nullptr;
+        r->all_issued = true;
         bytes_in_use -= (int64_t)r->transient;
         r->transient = 0;
         finish(r, st);
@@ -369,7 +419,7 @@ apsp_status_t apsp_server_create(const apsp_server_config_t *config, apsp_server
     apsp_server_config_t cfg{};
     if (config) cfg = *config;
     if (cfg.hbm_budget_bytes < 0 || cfg.max_inflight < 0 || cfg.n_streams < 0 || cfg.max_queue < 0 ||
-        cfg.batch_max_n > 1024)
+        cfg.batch_max_n > 1024 || cfg.slice_rounds < 0)
         return APSP_ERROR_INVALID_ARGUMENT;
     auto *sv = new (std::nothrow) apsp_server();
     if (!sv) return APSP_ERROR_OUT_OF_MEMORY;
@@ -615,6 +665,16 @@ apsp_status_t apsp_server_stats(apsp_server_t *sv, apsp_server_stats_t *out) {
         };
         s.p50_latency_ms = pct(0.50);
         s.p99_latency_ms = pct(0.99);
+        for (int large = 0; large < 2; ++large) {
+            std::vector<double> c;
+            for (size_t i = 0; i < sv->latencies_ms.size(); ++i)
+                if (sv->latency_large[i] == large) c.push_back(sv->latencies_ms[i]);
+            if (c.empty()) continue;
+            std::sort(c.begin(), c.end());
+            auto q = [&](double f) { return c[(size_t)std::min<double>((double)c.size() - 1, std::ceil(f * c.size()) - 1)]; };
+            (large ? s.p50_large_ms : s.p50_small_ms) = q(0.50);
+            (large ? s.p99_large_ms : s.p99_small_ms) = q(0.99);
+        }
         const double span = std::chrono::duration<double>(sv->last_done - sv->first_submit).count();
         s.solves_per_s = span > 0 ? (double)sv->completed / span : 0.0;
     }

@@ -1548,6 +1548,7 @@ struct apsp_stepper {
     apsp_options_t opt{};
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    bool owns_ws = true;  // false: work memory lent by the server
     AuxStream aux{};
     Recorder rec;
     hipStream_t stream = nullptr;
@@ -1585,34 +1586,77 @@ apsp_status_t check_options(int64_t n, apsp_dtype_t dtype, bool with_pred, const
 
 extern "C" {
 
-apsp_status_t apsp_stepper_create(int64_t n, apsp_dtype_t dtype, int32_t want_pred, const apsp_options_t *options,
-                                  apsp_stepper_t **out) {
+}  // extern "C"
+
+namespace apsp {
+
+// lend == false: the stepper allocates (and frees) work memory for any
+// alignment of dist; lend == true: it uses the caller's ws_bytes at ws (null
+// when 0), which must cover a solve of (n, pred, options) on a 16-byte
+// aligned dist (begin fails with APSP_ERROR_INVALID_ARGUMENT otherwise).
+apsp_status_t stepper_create(int64_t n, apsp_dtype_t dtype, bool want_pred, const apsp_options_t *options,
+                             bool lend, void *ws, size_t ws_bytes, apsp_stepper_t **out) {
     if (!out) return APSP_ERROR_INVALID_ARGUMENT;
     *out = nullptr;
     apsp_options_t opt{};
     if (options) opt = *options;
     opt.use_graph = 0;  // a stepper issues recorded operations itself
-    apsp_status_t st = check_options(n, dtype, want_pred != 0, opt);
+    apsp_status_t st = check_options(n, dtype, want_pred, opt);
     if (st != APSP_SUCCESS) return st;
     auto *p = new apsp_stepper();
     p->n = n;
     p->dtype = dtype;
-    p->want_pred = want_pred != 0;
+    p->want_pred = want_pred;
     p->opt = opt;
     hipError_t e = hipGetDevice(&p->device);
     // work memory for any alignment of the caller's matrix
-    p->ws_bytes = n ? work_bytes(n, p->want_pred, opt.block_size, false, dtype, opt.arith) : 0;
-    if (e == hipSuccess && p->ws_bytes) e = hipMalloc(&p->ws, p->ws_bytes);
+    const size_t need = n ? work_bytes(n, p->want_pred, opt.block_size, lend, dtype, opt.arith) : 0;
+    if (lend) {
+        if (ws_bytes < need) {
+            delete p;
+            return APSP_ERROR_INVALID_ARGUMENT;
+        }
+        p->ws = ws;
+        p->ws_bytes = ws_bytes;
+        p->owns_ws = false;
+    } else {
+        p->ws_bytes = need;
+        if (e == hipSuccess && p->ws_bytes) e = hipMalloc(&p->ws, p->ws_bytes);
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->aux.s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->aux.panels, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->aux.rest, hipEventDisableTiming);
     if (e != hipSuccess) {
         g_last_hip = (int)e;
-        apsp_stepper_destroy(p);
+        stepper_destroy(p, true);
         return e == hipErrorOutOfMemory ? APSP_ERROR_OUT_OF_MEMORY : APSP_ERROR_HIP;
     }
     *out = p;
     return APSP_SUCCESS;
+}
+
+// sync: wait for the stepper's streams first (the server destroys steppers
+// whose final event it has already seen complete, and must not block on the
+// other work of a shared stream).
+apsp_status_t stepper_destroy(apsp_stepper_t *p, bool sync) {
+    if (!p) return APSP_ERROR_INVALID_ARGUMENT;
+    if (sync && p->begun) hipStreamSynchronize(p->stream);
+    if (sync && p->aux.s) hipStreamSynchronize(p->aux.s);
+    if (p->ws && p->owns_ws) hipFree(p->ws);
+    if (p->aux.panels) hipEventDestroy(p->aux.panels);
+    if (p->aux.rest) hipEventDestroy(p->aux.rest);
+    if (p->aux.s) hipStreamDestroy(p->aux.s);
+    delete p;
+    return APSP_SUCCESS;
+}
+
+}  // namespace apsp
+
+extern "C" {
+
+apsp_status_t apsp_stepper_create(int64_t n, apsp_dtype_t dtype, int32_t want_pred, const apsp_options_t *options,
+                                  apsp_stepper_t **out) {
+    return stepper_create(n, dtype, want_pred != 0, options, false, nullptr, 0, out);
 }
 
 apsp_status_t apsp_stepper_begin(apsp_stepper_t *p, void *dist, int32_t *pred, hipStream_t stream) {
@@ -1665,17 +1709,7 @@ apsp_status_t apsp_stepper_step(apsp_stepper_t *p, int32_t rounds, int32_t *done
 
 int64_t apsp_stepper_rounds(const apsp_stepper_t *p) { return p ? (int64_t)p->rec.marks.size() : -1; }
 
-apsp_status_t apsp_stepper_destroy(apsp_stepper_t *p) {
-    if (!p) return APSP_ERROR_INVALID_ARGUMENT;
-    if (p->stream || p->begun) hipStreamSynchronize(p->stream);
-    if (p->aux.s) hipStreamSynchronize(p->aux.s);
-    if (p->ws) hipFree(p->ws);
-    if (p->aux.panels) hipEventDestroy(p->aux.panels);
-    if (p->aux.rest) hipEventDestroy(p->aux.rest);
-    if (p->aux.s) hipStreamDestroy(p->aux.s);
-    delete p;
-    return APSP_SUCCESS;
-}
+apsp_status_t apsp_stepper_destroy(apsp_stepper_t *p) { return stepper_destroy(p, true); }
 
 apsp_status_t apsp_release_workspace(void) {
     int dev = 0;

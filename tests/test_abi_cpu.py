@@ -84,6 +84,8 @@ def test_server_host_argument_errors():
     assert L.apsp_server_create(ctypes.byref(bad), ctypes.byref(out)) == apsp.INVALID_ARGUMENT
     bad = apsp.ServerConfig(0, 0, 0, 0, 2048)
     assert L.apsp_server_create(ctypes.byref(bad), ctypes.byref(out)) == apsp.INVALID_ARGUMENT
+    bad = apsp.ServerConfig(0, 0, 0, 0, 0, -1)  # negative slice length
+    assert L.apsp_server_create(ctypes.byref(bad), ctypes.byref(out)) == apsp.INVALID_ARGUMENT
 
 
 def test_batch_plan_host_argument_errors():

@@ -180,3 +180,42 @@ def test_large_int32_request_float32_arithmetic(orc):
     for src in (0, n - 1):
         dr, _, s = orc.row(W, src)
         assert s == 0 and np.array_equal(D[src], dr)
+
+
+@pytest.mark.parametrize("slice_rounds", [1, 4])
+def test_sliced_large_requests_equal_alone(orc, slice_rounds):
+    """Round-level preemption: large requests issued slice_rounds rounds at a
+    time, interleaved with small batched requests and each other, give the
+    bits of the same request solved alone; per-class latencies are reported."""
+    import paper_1811_01201_amd as apsp
+    describe(f"server sliced rounds={slice_rounds}")
+    reqs = _mix(24, seed=11, n_hi=3000)
+    reqs += [(synth.single_f32int(4500, 0.2, seed=12), True), (synth.potential_int32(5000, p=0.1, seed=13), False)]
+    with apsp.Server(n_streams=2, slice_rounds=slice_rounds) as sv:
+        tickets = [sv.submit(W, want_pred=p) for W, p in reqs]
+        for t, (W, p) in zip(tickets, reqs):
+            assert sv.wait(t) == apsp.SUCCESS
+            D, P = sv.result(t)
+            Da, Pa, st = gpu_solve(W, pred=p)
+            assert st == 0 and np.array_equal(D, Da)
+            if p:
+                assert np.array_equal(P, Pa)
+            if W.shape[0] <= 300:
+                D0, _, _ = orc.fw(W)
+                assert np.array_equal(D, D0.astype(D.dtype))
+            assert sv.release(t) == apsp.SUCCESS
+        s = sv.stats()
+        assert s["completed"] == len(reqs) and s["failed"] == 0
+        assert s["p99_large_ms"] >= s["p50_large_ms"] > 0
+        assert s["p99_small_ms"] >= s["p50_small_ms"] > 0
+
+
+def test_sliced_negative_cycle_reported():
+    import paper_1811_01201_amd as apsp
+    describe("server sliced negative cycle")
+    W = synth.single_int32(900, p=0.05, seed=21)
+    W[10, 150], W[150, 10] = 5, -9
+    with apsp.Server(slice_rounds=2, batch_max_n=-1) as sv:
+        t = sv.submit(W)
+        assert sv.wait(t) == apsp.NEGATIVE_CYCLE
+        sv.release(t)
