@@ -1433,6 +1433,20 @@ apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dty
 
 }  // namespace
 
+// Host-side checks shared by apsp_solve_ex and the steppers.
+apsp_status_t check_options(int64_t n, apsp_dtype_t dtype, bool with_pred, const apsp_options_t &opt) {
+    if (n < 0 || n > kMaxN) return APSP_ERROR_INVALID_ARGUMENT;
+    if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.block_size != 0 && opt.block_size != 64 && opt.block_size != 128 && opt.block_size != 256)
+        return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.thread_tile != 0 && opt.thread_tile != 4 && opt.thread_tile != 8) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.thread_tile == 4 && opt.block_size != 0 && opt.block_size != 64) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.block_size == 256 && with_pred) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.arith < 0 || opt.arith > 2) return APSP_ERROR_INVALID_ARGUMENT;
+    return APSP_SUCCESS;
+}
+
 apsp_status_t solve_internal(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t s,
                              const apsp_options_t &opt, void *ws, size_t ws_bytes) {
     if (n == 0) return APSP_SUCCESS;
@@ -1474,15 +1488,8 @@ apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t d
                             hipStream_t stream, const apsp_options_t *options) {
     apsp_options_t opt{};
     if (options) opt = *options;
-    if (n < 0 || n > kMaxN) return APSP_ERROR_INVALID_ARGUMENT;
-    if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.block_size != 0 && opt.block_size != 64 && opt.block_size != 128 && opt.block_size != 256)
-        return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.thread_tile != 0 && opt.thread_tile != 4 && opt.thread_tile != 8) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.thread_tile == 4 && opt.block_size != 0 && opt.block_size != 64) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.block_size == 256 && pred) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.arith < 0 || opt.arith > 2) return APSP_ERROR_INVALID_ARGUMENT;
+    const apsp_status_t bad = check_options(n, dtype, pred != nullptr, opt);
+    if (bad != APSP_SUCCESS) return bad;
     if (n == 0) return APSP_SUCCESS;
     if (!dist || ((uintptr_t)dist % 4) != 0 || ((uintptr_t)pred % 4) != 0)
         return APSP_ERROR_INVALID_ARGUMENT;
@@ -1569,18 +1576,6 @@ struct RecordScope {
     }
 };
 
-apsp_status_t check_options(int64_t n, apsp_dtype_t dtype, bool with_pred, const apsp_options_t &opt) {
-    if (n < 0 || n > kMaxN) return APSP_ERROR_INVALID_ARGUMENT;
-    if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.block_size != 0 && opt.block_size != 64 && opt.block_size != 128 && opt.block_size != 256)
-        return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.thread_tile != 0 && opt.thread_tile != 4 && opt.thread_tile != 8) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.thread_tile == 4 && opt.block_size != 0 && opt.block_size != 64) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.block_size == 256 && with_pred) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.arith < 0 || opt.arith > 2) return APSP_ERROR_INVALID_ARGUMENT;
-    return APSP_SUCCESS;
-}
 
 }  // namespace
 
