@@ -156,8 +156,11 @@ apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t d
 /* ---------------------------------------------------------------- steppers
  *
  * A solve issued a few rounds at a time (round-level preemption, for
- * serving: large solves yield the device between slices).  The launch
- * sequence of a solve never depends on the data (every data-dependent
+ * serving: large solves yield the device between slices).  The rounds are
+ * the blocked algorithm's rounds over k-blocks (Section "Data Locality":
+ * diagonal block, its block row and column, then the remaining blocks);
+ * the state between steps lives in device memory.  The launch sequence of
+ * a solve never depends on the data (every data-dependent
  * choice is a device word), so apsp_stepper_begin records the whole
  * sequence of apsp_solve_ex for (dist, pred, stream) without issuing
  * anything, and apsp_stepper_step issues the next `rounds` rounds of it
