@@ -154,3 +154,28 @@ def test_stepper_begin_while_unfinished_is_refused():
     D1, _, _, _ = _one_shot(W, False)
     assert np.array_equal(d.cpu().numpy(), D1)
     s.destroy()
+
+
+def test_stepper_empty_and_reuse():
+    """n = 0 records nothing and is done at once; a stepper solves several
+    graphs in turn (begin again after the last step)."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe("stepper empty and reuse")
+    s0 = apsp.Stepper(0, "int32")
+    s0.begin(torch.empty((0, 0), dtype=torch.int32, device="cuda"))
+    assert s0.rounds == 0 and s0.step(1)
+    s0.destroy()
+    s = apsp.Stepper(700, "float32", True)
+    for seed in (1, 2):
+        W = synth.single_f32int(700, p=0.2, seed=seed)
+        d = torch.from_numpy(W.copy()).cuda()
+        p = torch.empty((700, 700), dtype=torch.int32, device="cuda")
+        s.begin(d, p)
+        while not s.step(2):
+            pass
+        torch.cuda.synchronize()
+        D1, P1, _, _ = _one_shot(W, True)
+        assert np.array_equal(d.cpu().numpy(), D1) and np.array_equal(p.cpu().numpy(), P1)
+    s.destroy()
