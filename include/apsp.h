@@ -273,9 +273,13 @@ apsp_status_t apsp_pred_to_intermediate(const int32_t *pred, int64_t n, int32_t 
  * Many independent graphs of uneven size, solved by one persistent fused
  * launch that runs all three phases of every graph: each 256-thread
  * workgroup pulls graphs, largest first, from a device work counter; graphs
- * with n > 64 are solved by a whole workgroup with 64-wide k-blocks, graphs
- * with n <= 64 by a single wavefront in registers.  Same conventions and
- * results as apsp_solve, graph by graph.
+ * with n > 64 are solved by a whole workgroup with 64- or 128-wide k-blocks
+ * (the team configuration of the graph's size class, see autotuning),
+ * graphs with n <= 64 by a single wavefront in registers.  int32 distance
+ * batches run as two launches, the graphs whose weights rule float32
+ * arithmetic out (any negative weight, or |w|(n-1) >= 2^23) in int32
+ * arithmetic, the others in float32 (exact).  Same conventions and results
+ * as apsp_solve, graph by graph.
  *
  *   ns          host, sizes of the batch graphs, 1 <= ns[b] <= 1024
  *   offsets     host, element offset of graph b in the packed buffers;
@@ -289,7 +293,7 @@ apsp_status_t apsp_pred_to_intermediate(const int32_t *pred, int64_t n, int32_t 
  *               APSP_ERROR_NEGATIVE_CYCLE
  * A plan owns the device copy of the metadata, the per-workgroup work
  * matrices and the work counters (device memory of about
- * 2 x CUs x 64-padded max(n)^2 x 4 or 8 bytes).  It may be executed any
+ * 2 x CUs x (64- or 128-padded max n)^2 x 4 or 8 bytes).  It may be executed any
  * number of times, also from a captured hipGraph, but executions of one plan
  * must not overlap in time (use one plan per concurrent stream).  The plan
  * must outlive the work it enqueued.
