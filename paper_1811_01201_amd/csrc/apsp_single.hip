@@ -1112,11 +1112,12 @@ int auto_block(int64_t n, bool pred) {
 int auto_tile(int64_t n, int bs) { return (bs == 64 && n <= 4096) ? 4 : 8; }
 
 // int32 distance solves run in float32 arithmetic (exact while watched,
-// else redone in int32) when asked to, or automatically above n = 4096,
-// where phase 3 dominates and the skipped int32 launches cost little.
+// else redone in int32) when asked to, or automatically from n = 4096,
+// where phase 3 dominates and the skipped int32 launches cost little
+// (measured on MI355X: 4.08 vs 4.50 ms at n = 4096; slower at 3000 and below).
 bool use_f32w(int64_t n, apsp_dtype_t dtype, bool with_pred, int arith) {
     if (dtype != APSP_INT32 || with_pred || arith == 1) return false;
-    return arith == 2 || n > 4096;
+    return arith == 2 || n >= 4096;
 }
 
 // Predecessor solves: float32 distances + the key product (exact, with
