@@ -140,6 +140,22 @@ def batched_leg(replays: int):
         if r > 0:
             times.append(e0.elapsed_time(e1))
     med = float(np.median(times))
+    # the same launches captured once into a hipGraph and replayed
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.execute(d)
+    gtimes = []
+    for r in range(replays + 1):
+        d.copy_(pristine)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            gtimes.append(e0.elapsed_time(e1))
+    del graph
     views = [d[int(o):int(o) + int(n) * int(n)].view(int(n), int(n)) for n, o in zip(bt.ns, bt.offsets)]
     d.copy_(pristine)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -159,6 +175,8 @@ def batched_leg(replays: int):
         "batch_ms_p99": round(float(np.percentile(times, 99)), 3),
         "replays": replays,
         "gops": round(ops / (med / 1e3) / 1e9, 1),
+        "hipgraph_replay": {"batch_ms_median": round(float(np.median(gtimes)), 3),
+                            "batch_ms_p99": round(float(np.percentile(gtimes, 99)), 3)},
         "one_graph_per_launch": {"solves_per_s": round(4096 / (loop_ms / 1e3), 1), "batch_ms": round(loop_ms, 3)},
         "speedup_vs_one_graph_per_launch": round(loop_ms / med, 2),
     }

@@ -282,3 +282,58 @@ def test_autotune_on_workload_sizes(orc, tmp_path):
             assert st[b] == 0 and np.array_equal(D[o:o + n * n].reshape(n, n), D0)
     finally:
         apsp.tune_load(str(saved))
+
+
+@pytest.mark.parametrize("kind,pred", [("int", False), ("f32", True)])
+def test_batched_plan_in_captured_hipgraph(orc, kind, pred):
+    """The plan's launches captured once into a hipGraph (torch.cuda.graph)
+    and replayed several times, with eager work and synchronizations between
+    the replays; every replay equals the eager result and the oracle.  The
+    int32 batch holds a graph whose weights rule float32 arithmetic out, so
+    both of its launches solve graphs."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe(f"batched hipGraph replays {kind} pred={pred}")
+    sizes = [300, 17, 129, 64, 513, 200, 5, 256]
+    graphs = _graphs(kind, sizes, seed=23)
+    if kind == "int":
+        n = graphs[2].shape[0]
+        graphs[2] = graphs[2].copy()
+        graphs[2][4, 9] = (2 ** 23) // (n - 1) + 5  # float32 ruled out for this graph only
+    dtype = np.int32 if kind == "int" else np.float32
+    buf, ns, offs = _pack(graphs, dtype)
+    plan = apsp.BatchPlan(ns, offs, "int32" if kind == "int" else "float32", want_pred=pred)
+    pristine = torch.from_numpy(buf).cuda()
+    d = pristine.clone()
+    p = torch.full(d.shape, -7, dtype=torch.int32, device="cuda") if pred else None
+    st = torch.full((len(graphs),), -1, dtype=torch.int32, device="cuda")
+    plan.execute(d, p, st)
+    torch.cuda.synchronize()
+    D_e = d.cpu().numpy()
+    P_e = p.cpu().numpy() if pred else None
+    assert (st.cpu().numpy() == 0).all()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.execute(d, p, st)
+    for rep in range(3):
+        d.copy_(pristine)
+        if pred:
+            p.fill_(-7)
+        st.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(d.cpu().numpy(), D_e), rep
+        if pred:
+            assert np.array_equal(p.cpu().numpy(), P_e), rep
+        assert (st.cpu().numpy() == 0).all(), rep
+    for b, W in enumerate(graphs):
+        n = W.shape[0]
+        o = int(offs[b])
+        D0, P0, _ = orc.fw(W, pred=pred)
+        assert first_mismatch(D_e[o:o + n * n].reshape(n, n), D0) is None, (b, n)
+        if pred:
+            assert first_mismatch(P_e[o:o + n * n].reshape(n, n), P0) is None, (b, n)
+    del g
+    plan.destroy()
