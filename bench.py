@@ -113,7 +113,7 @@ def sweep_leg(sizes, modes):
     return rows
 
 
-def batched_leg(replays: int):
+def batched_leg(replays: int, graph_replays: bool = True):
     """4096 graphs (n uniform in [16, 512], p uniform in [0.05, 0.9], int32
     weights 1..1000) in the plan's fused launches per replay, against the same graphs
     solved one apsp_solve launch sequence per graph on one stream."""
@@ -141,11 +141,12 @@ def batched_leg(replays: int):
             times.append(e0.elapsed_time(e1))
     med = float(np.median(times))
     # the same launches captured once into a hipGraph and replayed
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        plan.execute(d)
     gtimes = []
-    for r in range(replays + 1):
+    if graph_replays:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.execute(d)
+    for r in range(replays + 1 if graph_replays else 0):
         d.copy_(pristine)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -155,7 +156,8 @@ def batched_leg(replays: int):
         torch.cuda.synchronize()
         if r > 0:
             gtimes.append(e0.elapsed_time(e1))
-    del graph
+    if graph_replays:
+        del graph
     views = [d[int(o):int(o) + int(n) * int(n)].view(int(n), int(n)) for n, o in zip(bt.ns, bt.offsets)]
     d.copy_(pristine)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -176,7 +178,7 @@ def batched_leg(replays: int):
         "replays": replays,
         "gops": round(ops / (med / 1e3) / 1e9, 1),
         "hipgraph_replay": {"batch_ms_median": round(float(np.median(gtimes)), 3),
-                            "batch_ms_p99": round(float(np.percentile(gtimes, 99)), 3)},
+                            "batch_ms_p99": round(float(np.percentile(gtimes, 99)), 3)} if gtimes else None,
         "one_graph_per_launch": {"solves_per_s": round(4096 / (loop_ms / 1e3), 1), "batch_ms": round(loop_ms, 3)},
         "speedup_vs_one_graph_per_launch": round(loop_ms / med, 2),
     }
@@ -434,6 +436,8 @@ def main():
                     help="skip the n=8192 float32 + predecessors leg")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--batched-replays", type=int, default=10)
+    ap.add_argument("--no-batched-graph", action="store_true",
+                    help="skip the hipGraph replays of the batched plan (counter collection runs)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     args = ap.parse_args()
 
@@ -480,7 +484,7 @@ def main():
     batched = None
     if not args.skip_batched:
         log("[bench] batched leg")
-        batched = batched_leg(args.batched_replays)
+        batched = batched_leg(args.batched_replays, not args.no_batched_graph)
     serving = None
     if not args.skip_serving:
         log("[bench] serving leg")
