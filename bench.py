@@ -375,7 +375,7 @@ def single_leg(args, n):
     achieved = per_launch_ops / (avg_ms / 1e3) / 1e12
     roofline = {
         "bound": "alu",
-        "kernel": "phase3_kernel kRest (remaining-block min-plus products, 128x128 tiles, one launch per round from n=16384, two below)",
+        "kernel": "phase3_kernel kRest (remaining-block min-plus products, 128x128 tiles, one launch per round from n=10240, two below)",
         "achieved": round(achieved, 3),
         "peak": round(PEAK_OPS / 1e12, 3),
         "unit": "Tops/s (2 ops per (i,j,k) relaxation)",

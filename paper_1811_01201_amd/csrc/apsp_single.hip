@@ -1001,10 +1001,11 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     }
     // the blocked closure is slower on its own (one wavefront per SIMD) but
     // starts in any slot a phase-3 workgroup frees: it pays off where
-    // phase 3 is long enough to hide it (measured on MI355X: -3 % at
-    // n = 16384, -0.4 % at 32768, +20 % at 8192)
+    // phase 3 is long enough to hide it (measured on MI355X: -4 to -6 % at
+    // n = 10240 ... 12288, -3 % at 16384, -0.4 % at 32768; +7 % at 9216 and
+    // +23 % at 8192)
     constexpr bool kBlockedP1 = BS == 256 && sizeof(typename Ar::T) == 4 && std::is_same_v<Alt, NoAlt>;
-    const bool blocked_p1 = kBlockedP1 && ld >= 16384;
+    const bool blocked_p1 = kBlockedP1 && ld >= 10240;
     auto p1 = [&](int r) {
         ProfScope ps(prof ? kPhase1 : -1, bs3, s);
         if (blocked_p1) {

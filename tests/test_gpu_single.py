@@ -297,6 +297,29 @@ def test_full_size_n32768_potential_sampled_rows(orc):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("n,kind,pred", [(10300, "pot", False), (12288, "int", False), (10240, "f32", True)])
+def test_blocked_phase1_mid_sizes(orc, n, kind, pred):
+    """Sizes where phase 1 is the blocked closure of the diagonal block but
+    phase 3 is short (ld from 10240; n = 10300 pads to ld = 10496): the
+    automatic route against an independent configuration (BS = 128, int32 or
+    fp64-key arithmetic, rounds in order) on every element, and sampled
+    rows against the row oracle."""
+    describe(f"single blocked phase 1 n={n} {kind} pred={pred}")
+    W = _graph(kind, n, seed=n + 17)
+    D, P, st = gpu_solve(W, pred)
+    D1, P1, st1 = gpu_solve(W, pred, block_size=128, schedule=1, arith=1)
+    assert st == 0 and st1 == 0
+    assert first_mismatch(D, D1) is None, first_mismatch(D, D1)
+    if pred:
+        assert first_mismatch(P, P1) is None, first_mismatch(P, P1)
+    for src in (0, n // 2 + 3, n - 1):
+        dr, pr, s = orc.row(W, src, pred=pred)
+        assert s == 0
+        assert np.array_equal(D[src], dr.astype(D.dtype)), src
+        if pred:
+            assert np.array_equal(P[src], pr), src
+
+
 def test_maximum_size_n65536(orc):
     """n = 65536, the largest size the library accepts (the paper's largest),
     potential weights with negative edges: one sampled row against the row
