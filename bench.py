@@ -395,7 +395,8 @@ def single_leg(args, n):
 
     # algorithmic HBM bytes of one launch: its C elements read and written
     # once (8 bytes), plus the panel rows and columns they need, once
-    bs = args.block_size or (256 if n > 4096 else 128)
+    # (the library's automatic block size for distance solves)
+    bs = args.block_size or (64 if n <= 5888 else 128 if n < 7168 else 256)
     m = n - 2 * bs
     c_elems = p3["updates"] / max(1, p3["launches"]) / bs
     algo = int(c_elems * 8 + (c_elems / m + m) * bs * 4)

@@ -1104,13 +1104,23 @@ apsp_status_t run_rounds_bs(int bs, int tt, bool lookahead, void *X, int64_t ld,
     }
 }
 
+// Block size by n (measured on MI355X, int32 distances in float32
+// arithmetic, ms per solve for BS = 64 / 128 / 256): 5120: 6.52 / 7.78 /
+// 8.61; 5632: 8.14 / 8.74 / 9.57; 6144: 9.87 / 9.67 / 10.85; 6656: 11.93 /
+// 11.67 / 11.87; 7168: 14.24 / 13.90 / 13.59; 8192: 19.79 / 19.58 / 17.77.
+// Small blocks keep the phase-1 chain short while phase 3 is short too.
+// The fp64-key recurrence keeps BS = 128 above n = 4096.
 int auto_block(int64_t n, bool pred) {
     if (n <= 4096) return 64;
-    if (pred || n <= 4096) return 128;
+    if (pred) return 128;
+    if (n <= 5888) return 64;
+    if (n < 7168) return 128;
     return 256;
 }
 
-int auto_tile(int64_t n, int bs) { return (bs == 64 && n <= 4096) ? 4 : 8; }
+// 64-wide blocks take 4 x 4 register blocks (twice the workgroups of 8 x 8:
+// at n = 4096, 4.30 vs 6.45 ms)
+int auto_tile(int64_t, int bs) { return bs == 64 ? 4 : 8; }
 
 // int32 distance solves run in float32 arithmetic (exact while watched,
 // else redone in int32) when asked to, or automatically from n = 4096,

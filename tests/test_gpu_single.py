@@ -297,17 +297,22 @@ def test_full_size_n32768_potential_sampled_rows(orc):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("n,kind,pred", [(10300, "pot", False), (12288, "int", False), (10240, "f32", True)])
-def test_blocked_phase1_mid_sizes(orc, n, kind, pred):
-    """Sizes where phase 1 is the blocked closure of the diagonal block but
-    phase 3 is short (ld from 10240; n = 10300 pads to ld = 10496): the
-    automatic route against an independent configuration (BS = 128, int32 or
-    fp64-key arithmetic, rounds in order) on every element, and sampled
-    rows against the row oracle."""
-    describe(f"single blocked phase 1 n={n} {kind} pred={pred}")
+@pytest.mark.parametrize("n,kind,pred,alt_bs", [
+    (5000, "int", False, 128), (5700, "pot", False, 256), (5000, "f32", True, 128),
+    (6300, "pot", False, 64), (6144, "f32", True, 64),
+    (10300, "pot", False, 128), (12288, "int", False, 128), (10240, "f32", True, 128)])
+def test_auto_configuration_mid_sizes(orc, n, kind, pred, alt_bs):
+    """Sizes around the automatic configuration's switches: 64-wide blocks
+    with 4 x 4 register blocks up to n = 5888, 128-wide below 7168, 256-wide
+    above, and from ld = 10240 phase 1 as the blocked closure of the diagonal
+    block (n = 10300 pads to ld = 10496).  The automatic route against an
+    independent configuration (another block size, int32 or fp64-key
+    arithmetic, rounds in order) on every element, and sampled rows against
+    the row oracle."""
+    describe(f"single auto configuration n={n} {kind} pred={pred}")
     W = _graph(kind, n, seed=n + 17)
     D, P, st = gpu_solve(W, pred)
-    D1, P1, st1 = gpu_solve(W, pred, block_size=128, schedule=1, arith=1)
+    D1, P1, st1 = gpu_solve(W, pred, block_size=alt_bs, schedule=1, arith=1)
     assert st == 0 and st1 == 0
     assert first_mismatch(D, D1) is None, first_mismatch(D, D1)
     if pred:
