@@ -134,7 +134,7 @@ typedef struct {
                               does not, the device redoes the solve in int32 arithmetic.
                               Either way the result is the exact int32 result.
                               With predecessors (either dtype): 0 = automatic (the float32
-                              route above n = 4096), 1 = the exact fp64-key recurrence,
+                              route from n = 4096), 1 = the exact fp64-key recurrence,
                               2 = the float32 route at any n: exact float32 distances, then
                               the canonical predecessors read off one float32 min-plus
                               product of (D(i,v) 2^S + v) with (W(v,j) 2^S), S = bits of

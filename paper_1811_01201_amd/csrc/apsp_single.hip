@@ -1109,7 +1109,8 @@ apsp_status_t run_rounds_bs(int bs, int tt, bool lookahead, void *X, int64_t ld,
 // 8.61; 5632: 8.14 / 8.74 / 9.57; 6144: 9.87 / 9.67 / 10.85; 6656: 11.93 /
 // 11.67 / 11.87; 7168: 14.24 / 13.90 / 13.59; 8192: 19.79 / 19.58 / 17.77.
 // Small blocks keep the phase-1 chain short while phase 3 is short too.
-// The fp64-key recurrence keeps BS = 128 above n = 4096.
+// The fp64-key recurrence (the product route's fallback there) keeps
+// BS = 128 above n = 4096.
 int auto_block(int64_t n, bool pred) {
     if (n <= 4096) return 64;
     if (pred) return 128;
@@ -1133,12 +1134,13 @@ bool use_f32w(int64_t n, apsp_dtype_t dtype, bool with_pred, int arith) {
 
 // Predecessor solves: float32 distances + the key product (exact, with
 // the fp64-key recurrence as the device's fallback) when asked to, or
-// automatically above n = 4096, where the product costs less than the
-// recurrence's fp64 arithmetic (measured on MI355X: 1.4x faster at n = 8192
-// and 16384, even at n = 4096, slower below).
+// automatically from n = 4096, where the product costs less than the
+// recurrence's fp64 arithmetic (measured on MI355X, float32 / int32
+// weights: 6.35 vs 7.06 / 6.29 vs 6.57 ms at n = 4096, 1.4x faster at 5120
+// to 16384; even or slower at 3072 and below).
 bool use_pp(int64_t n, bool with_pred, int arith) {
     if (!with_pred || arith == 1) return false;
-    return arith == 2 || n > 4096;
+    return arith == 2 || n >= 4096;
 }
 
 int pp_bits(int64_t n) {
