@@ -121,7 +121,8 @@ typedef struct {
     int32_t block_size;    /* 0 = automatic; else 64, 128 or 256 (256: distances only) */
     int32_t thread_tile;   /* 0 = automatic; 8 (8 x 8 register blocks, throughput) or
                               4 (4 x 4, latency-bound small solves; block size 64 only) */
-    int32_t schedule;      /* 0 = automatic: for n >= 4096, phase 3 of round r is split so that
+    int32_t schedule;      /* 0 = automatic: for n >= 4096 (3072 for the fp64-key
+                              recurrence), phase 3 of round r is split so that
                               phases 1-2 of round r+1 run beside most of it on a library-owned
                               second stream; 1 = one stream, rounds in order */
     int32_t use_graph;     /* nonzero: capture the launch sequence once per shape into a

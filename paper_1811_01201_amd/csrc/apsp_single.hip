@@ -990,8 +990,12 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     int dev = 0;
     APSP_HIP(hipGetDevice(&dev));
     AuxStream *aux = nullptr;
-    // the split pays off once phase 3 is throughput- rather than latency-bound
-    if (lookahead && R >= 3 && ld >= 4096) {
+    // the split pays off once phase 3 is throughput- rather than latency-bound:
+    // from ld = 4096 for 4-byte elements, from 3072 for fp64 keys (measured
+    // on MI355X with predecessors: 3.58 vs 3.88 ms at n = 3072, 5.12 vs 5.32
+    // at 3584, slower at 2048; distances alone lose below 4096)
+    const int64_t split_from = sizeof(typename Ar::T) == 8 ? 3072 : 4096;
+    if (lookahead && R >= 3 && ld >= split_from) {
         if (t_aux) {
             aux = t_aux;
         } else {

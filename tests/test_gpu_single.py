@@ -298,11 +298,12 @@ def test_full_size_n32768_potential_sampled_rows(orc):
 
 
 @pytest.mark.parametrize("n,kind,pred,alt_bs", [
-    (4096, "int", True, 128), (5000, "int", False, 128), (5700, "pot", False, 256), (5000, "f32", True, 128),
+    (3500, "f32", True, 128), (4096, "int", True, 128), (5000, "int", False, 128), (5700, "pot", False, 256), (5000, "f32", True, 128),
     (6300, "pot", False, 64), (6144, "f32", True, 64),
     (10300, "pot", False, 128), (12288, "int", False, 128), (10240, "f32", True, 128)])
 def test_auto_configuration_mid_sizes(orc, n, kind, pred, alt_bs):
-    """Sizes around the automatic configuration's switches: predecessors
+    """Sizes around the automatic configuration's switches: the fp64-key
+    recurrence on two streams from ld = 3072, predecessors
     by the float32 key product from n = 4096, 64-wide blocks
     with 4 x 4 register blocks up to n = 5888, 128-wide below 7168, 256-wide
     above, and from ld = 10240 phase 1 as the blocked closure of the diagonal
