@@ -118,13 +118,17 @@ typedef struct {
     int32_t validate;      /* nonzero: check the weight preconditions on the device first;
                               on failure the solve is skipped and d_status gets
                               APSP_ERROR_INVALID_VALUE (dist/pred unchanged) */
-    int32_t block_size;    /* 0 = automatic; else 64, 128 or 256 (256: distances only) */
+    int32_t block_size;    /* 0 = automatic; else 64, 128 or 256 (256 with predecessors only
+                              on the float32 route, see arith: its distance rounds take
+                              256-wide blocks, its fallback recurrence 128-wide ones) */
     int32_t thread_tile;   /* 0 = automatic; 8 (8 x 8 register blocks, throughput) or
                               4 (4 x 4, latency-bound small solves; block size 64 only) */
     int32_t schedule;      /* 0 = automatic: for n >= 4096 (3072 for the fp64-key
                               recurrence), phase 3 of round r is split so that
                               phases 1-2 of round r+1 run beside most of it on a library-owned
-                              second stream; 1 = one stream, rounds in order */
+                              second stream; 1 = one stream, rounds in order; 2 = the
+                              two-stream split at any size with at least three rounds
+                              (the device-gated fallback passes always run in order) */
     int32_t use_graph;     /* nonzero: capture the launch sequence once per shape into a
                               hipGraph and replay it (fewer launch gaps for small n) */
     int32_t arith;         /* Distances only, int32 weights (ignored for float32 weights):
@@ -148,6 +152,14 @@ typedef struct {
     int32_t *d_arith;      /* device int32 or NULL: receives 1 if the result came from float32
                               arithmetic (with predecessors: the float32 route held), 0 if
                               from int32 arithmetic (the recurrence) */
+    int32_t phase1;        /* 0 = automatic: with 256-wide blocks from a padded order of
+                              10240, phase 1 is a blocked closure of the diagonal block
+                              inside one 256-thread workgroup (four 64-wide sub-rounds),
+                              and the two-stream split then issues the rest of phase 3 as
+                              one launch per round instead of two; 1 = always the
+                              one-step-per-barrier kernel; 2 = always the blocked closure
+                              (requires block_size 256; applies to the rounds on 4-byte
+                              distances, the fp64-key recurrence keeps the stepwise kernel) */
 } apsp_options_t;
 
 /* apsp_solve with options (NULL options = defaults = apsp_solve). */
@@ -213,6 +225,8 @@ typedef struct {
     apsp_kernel_time_t other;        /* set-up and wrap-up passes */
     apsp_kernel_time_t phase3_cross; /* two-stream schedule: the next round's block row/column */
     apsp_kernel_time_t pred_product; /* predecessors read off the float32 key product */
+    apsp_kernel_time_t phase1_blocked; /* the phase-1 launches (also counted in phase1) that
+                                          were the blocked closure of the diagonal block */
 } apsp_profile_t;
 
 apsp_status_t apsp_profile_begin(void);

@@ -144,6 +144,24 @@ class Oracle:
             st = self.L.oracle_row_f64(_ptr(W), n, src, _ptr(drow), _ptr(prow))
         return drow, prow, int(st)
 
+    def rows(self, W: np.ndarray, srcs, pred: bool = False, workers: int | None = None):
+        """row() for several sources at once, one source per host thread (the
+        C routine runs without the GIL).  Returns a list of (drow, prow, status)
+        in the order of srcs."""
+        from concurrent.futures import ThreadPoolExecutor
+        W = np.ascontiguousarray(W) if W.dtype == np.int32 else np.ascontiguousarray(W, dtype=np.float32)
+        workers = workers or default_threads()
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(lambda s: self.row(W, int(s), pred=pred), list(srcs)))
+
+    def fw_many(self, graphs, pred: bool = False, workers: int | None = None):
+        """fw() for many independent graphs, one graph per host thread (each
+        solve single-threaded).  Returns a list of (D, P or None, status)."""
+        from concurrent.futures import ThreadPoolExecutor
+        workers = workers or default_threads()
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(lambda W: self.fw(W, pred=pred, threads=1), list(graphs)))
+
 
 _default = None
 

@@ -43,7 +43,8 @@ class KernelTime(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("phase1", KernelTime), ("phase2", KernelTime), ("phase3", KernelTime),
-                ("other", KernelTime), ("phase3_cross", KernelTime), ("pred_product", KernelTime)]
+                ("other", KernelTime), ("phase3_cross", KernelTime), ("pred_product", KernelTime),
+                ("phase1_blocked", KernelTime)]
 
     def as_dict(self):
         out = {}
@@ -58,7 +59,8 @@ class Options(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("thread_tile", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("arith", ctypes.c_int32),
-                ("d_status", ctypes.c_void_p), ("d_arith", ctypes.c_void_p)]
+                ("d_status", ctypes.c_void_p), ("d_arith", ctypes.c_void_p),
+                ("phase1", ctypes.c_int32)]
 
 
 _lib = None
@@ -160,7 +162,8 @@ def _dtype_code(t):
 
 
 def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, status=None,
-          stream=None, check=True, schedule=0, thread_tile=0, arith=0, arith_used=None) -> int:
+          stream=None, check=True, schedule=0, thread_tile=0, arith=0, arith_used=None,
+          phase1=0) -> int:
     """Solve APSP in place on a square device tensor.
 
     dist   : torch.Tensor [n, n] int32/float32 on the GPU, contiguous (weights in,
@@ -176,6 +179,10 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
     arith_used : optional torch.Tensor [1] int32 on the device, receives 1 if the
              result came from float32 arithmetic (with pred: the product held),
              else 0.
+    schedule : 0 automatic, 1 rounds in order on one stream, 2 the two-stream
+             split at any size with three rounds or more.
+    phase1 : 0 automatic, 1 the stepwise diagonal kernel, 2 the blocked
+             closure of the diagonal block (block_size=256).
     Returns the host status of the enqueue (raises APSPError unless check=False).
     """
     assert dist.dim() == 2 and dist.shape[0] == dist.shape[1], "dist must be square"
@@ -189,7 +196,7 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
         pp = pred.data_ptr()
     opt = Options(int(validate), int(block_size), int(thread_tile), int(schedule), int(use_graph), int(arith),
                   status.data_ptr() if status is not None else None,
-                  arith_used.data_ptr() if arith_used is not None else None)
+                  arith_used.data_ptr() if arith_used is not None else None, int(phase1))
     st = lib().apsp_solve_ex(dist.data_ptr(), pp, n, _dtype_code(dist), _stream_ptr(stream),
                              ctypes.byref(opt))
     if check and st != SUCCESS:
@@ -204,12 +211,12 @@ class Stepper:
     everything is issued.  The final result equals solve()'s bit for bit."""
 
     def __init__(self, n: int, dtype: str = "int32", want_pred: bool = False, *, validate=False, block_size=0,
-                 thread_tile=0, schedule=0, arith=0, status=None, arith_used=None):
+                 thread_tile=0, schedule=0, arith=0, status=None, arith_used=None, phase1=0):
         self.n = int(n)
         self.want_pred = bool(want_pred)
         opt = Options(int(validate), int(block_size), int(thread_tile), int(schedule), 0, int(arith),
                       status.data_ptr() if status is not None else None,
-                      arith_used.data_ptr() if arith_used is not None else None)
+                      arith_used.data_ptr() if arith_used is not None else None, int(phase1))
         self._s = ctypes.c_void_p()
         st = lib().apsp_stepper_create(self.n, INT32 if dtype in ("int32", INT32) else FLOAT32,
                                        int(self.want_pred), ctypes.byref(opt), ctypes.byref(self._s))

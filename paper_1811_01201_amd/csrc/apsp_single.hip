@@ -844,7 +844,15 @@ apsp_status_t cached_workspace(int dev, hipStream_t s, size_t bytes, void **out)
 }
 
 // Optional per-launch timing (apsp_profile_begin / _end).
-enum KernelKind { kPhase1 = 0, kPhase2 = 1, kPhase3 = 2, kOther = 3, kPhase3Cross = 4, kPredProduct = 5 };
+enum KernelKind {
+    kPhase1 = 0,
+    kPhase2 = 1,
+    kPhase3 = 2,
+    kOther = 3,
+    kPhase3Cross = 4,
+    kPredProduct = 5,
+    kPhase1Blocked = 6  // counted under phase1 and phase1_blocked
+};
 struct ProfRecord {
     int kind;
     double updates;
@@ -978,9 +986,17 @@ inline void round_mark() {
 // starts where kRest's workgroups drain; kRest is therefore issued as
 // kRestChunks launches, whose boundaries let the caller stream's kernels
 // in (2 measured best: about 1.4 % at n = 32768, 6 % at n = 16384).
+// Schedule choices of one pass of rounds (apsp_options_t.schedule / .phase1:
+// 0 automatic by size, 1 rounds in order / the stepwise phase-1 kernel,
+// 2 the two-stream split / the blocked phase 1 wherever they apply).
+struct Sched {
+    int schedule = 0;
+    int phase1 = 0;
+};
+
 template <class Ar, class Alt, int BS, int TT>
 apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, const int32_t *mode,
-                         hipStream_t s, const int32_t *skip, bool lookahead, bool prof) {
+                         hipStream_t s, const int32_t *skip, Sched sc, bool prof) {
     constexpr int MT = BS >= 128 ? 128 : 64;
     constexpr int P2W = 64;
     const int R = (int)(ld / BS);
@@ -994,8 +1010,9 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     // from ld = 4096 for 4-byte elements, from 3072 for fp64 keys (measured
     // on MI355X with predecessors: 3.58 vs 3.88 ms at n = 3072, 5.12 vs 5.32
     // at 3584, slower at 2048; distances alone lose below 4096)
+    // (schedule 2 forces the split at any size with three rounds or more)
     const int64_t split_from = sizeof(typename Ar::T) == 8 ? 3072 : 4096;
-    if (lookahead && R >= 3 && ld >= split_from) {
+    if (sc.schedule != 1 && R >= 3 && (sc.schedule == 2 || ld >= split_from)) {
         if (t_aux) {
             aux = t_aux;
         } else {
@@ -1009,9 +1026,10 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     // n = 10240 ... 12288, -3 % at 16384, -0.4 % at 32768; +7 % at 9216 and
     // +23 % at 8192)
     constexpr bool kBlockedP1 = BS == 256 && sizeof(typename Ar::T) == 4 && std::is_same_v<Alt, NoAlt>;
-    const bool blocked_p1 = kBlockedP1 && ld >= 10240;
+    // (phase1 2 forces it wherever it applies, 1 keeps the stepwise kernel)
+    const bool blocked_p1 = kBlockedP1 && (sc.phase1 == 2 || (sc.phase1 == 0 && ld >= 10240));
     auto p1 = [&](int r) {
-        ProfScope ps(prof ? kPhase1 : -1, bs3, s);
+        ProfScope ps(!prof ? -1 : blocked_p1 ? kPhase1Blocked : kPhase1, bs3, s);
         if (blocked_p1) {
             if constexpr (kBlockedP1)
                 enq((phase1_blocked_kernel<Ar>), dim3(1), dim3(256), s, X, ld, (int64_t)r * BS,
@@ -1090,19 +1108,19 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
 // Kernel configurations: (block size, thread tile).  Thread tile 4 is the
 // latency configuration for small n (64-wide blocks only).
 template <class Ar, class Alt = NoAlt>
-apsp_status_t run_rounds_bs(int bs, int tt, bool lookahead, void *X, int64_t ld, const Ar &ar,
+apsp_status_t run_rounds_bs(int bs, int tt, Sched sc, void *X, int64_t ld, const Ar &ar,
                             hipStream_t s, const int32_t *skip, const Alt &alt = Alt{},
                             const int32_t *mode = nullptr, bool prof = true) {
     if (tt == 4) {
-        if (bs == 64) return run_rounds<Ar, Alt, 64, 4>(X, ld, ar, alt, mode, s, skip, lookahead, prof);
+        if (bs == 64) return run_rounds<Ar, Alt, 64, 4>(X, ld, ar, alt, mode, s, skip, sc, prof);
         return APSP_ERROR_INVALID_ARGUMENT;
     }
     switch (bs) {
-        case 64: return run_rounds<Ar, Alt, 64, 8>(X, ld, ar, alt, mode, s, skip, lookahead, prof);
-        case 128: return run_rounds<Ar, Alt, 128, 8>(X, ld, ar, alt, mode, s, skip, lookahead, prof);
+        case 64: return run_rounds<Ar, Alt, 64, 8>(X, ld, ar, alt, mode, s, skip, sc, prof);
+        case 128: return run_rounds<Ar, Alt, 128, 8>(X, ld, ar, alt, mode, s, skip, sc, prof);
         case 256:
             if constexpr (sizeof(typename Ar::T) == 4)
-                return run_rounds<Ar, Alt, 256, 8>(X, ld, ar, alt, mode, s, skip, lookahead, prof);
+                return run_rounds<Ar, Alt, 256, 8>(X, ld, ar, alt, mode, s, skip, sc, prof);
             return APSP_ERROR_INVALID_ARGUMENT;
         default: return APSP_ERROR_INVALID_ARGUMENT;
     }
@@ -1163,7 +1181,7 @@ struct PPShape {
 PPShape pp_shape(int64_t n, int opt_bs) {
     PPShape p;
     p.bsd = opt_bs ? opt_bs : auto_block(n, false);
-    p.bsf = opt_bs ? opt_bs : auto_block(n, true);
+    p.bsf = opt_bs ? std::min(opt_bs, 128) : auto_block(n, true);
     const int64_t m = std::max(p.bsd, 128);
     p.ld = (n + m - 1) / m * m;
     p.ldf = (n + p.bsf - 1) / p.bsf * p.bsf;
@@ -1193,7 +1211,9 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
     const int bs = opt.block_size ? opt.block_size : auto_block(n, with_pred);
     const int tt = opt.thread_tile ? opt.thread_tile : auto_tile(n, bs);
     if (tt == 4 && bs != 64) return APSP_ERROR_INVALID_ARGUMENT;
-    const bool lookahead = opt.schedule != 1;
+    const Sched lookahead{opt.schedule, opt.phase1};
+    // device-gated fallback passes run their rounds in order
+    const Sched in_order{1, opt.phase1};
     // caller-provided work memory (the server) or the per-stream cache
     auto workspace = [&](int d, hipStream_t st, size_t bytes, void **out) -> apsp_status_t {
         if (ext_ws) {
@@ -1203,7 +1223,7 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         }
         return cached_workspace(d, st, bytes, out);
     };
-    if (with_pred && bs == 256) return APSP_ERROR_INVALID_ARGUMENT;
+    if (with_pred && bs == 256 && !use_pp(n, true, opt.arith)) return APSP_ERROR_INVALID_ARGUMENT;
     const int64_t ld = (n + bs - 1) / bs * bs;
     int32_t *status = opt.d_status;
     const int32_t *skip = nullptr;
@@ -1246,7 +1266,7 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
             }
             // in order (3 launches per round): when the gate stays closed,
             // every launch still costs its dispatch
-            st = run_rounds_bs<ArI32>(bs, tt, false, Xi, ld, ArI32{}, s, gate, NoAlt{}, nullptr, false);
+            st = run_rounds_bs<ArI32>(bs, tt, in_order, Xi, ld, ArI32{}, s, gate, NoAlt{}, nullptr, false);
             if (st != APSP_SUCCESS) return st;
             enq((finalize_kernel<int32_t>), dim3(grid_for(n * n)), dim3(256), s, Xi, ld, dist,
                                n, status, gate);
@@ -1301,9 +1321,9 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         // in order (3 launches per round), as a closed gate still costs
         // every launch's dispatch
         if constexpr (std::is_same_v<T, float>)
-            st = run_rounds_bs<ArKey, ArLexF32>(sh.bsf, ttf, false, w, sh.ldf, ar, s, gate, ArLexF32{}, mode, false);
+            st = run_rounds_bs<ArKey, ArLexF32>(sh.bsf, ttf, in_order, w, sh.ldf, ar, s, gate, ArLexF32{}, mode, false);
         else
-            st = run_rounds_bs<ArKey>(sh.bsf, ttf, false, w, sh.ldf, ar, s, gate, NoAlt{}, nullptr, false);
+            st = run_rounds_bs<ArKey>(sh.bsf, ttf, in_order, w, sh.ldf, ar, s, gate, NoAlt{}, nullptr, false);
         if (st != APSP_SUCCESS) return st;
         enq((pred_unpack_kernel<T>), dim3(grid_for(n * n)), dim3(256), s, w, sh.ldf, dist, pred,
                            n, ar.S, mode, status, gate);
@@ -1378,12 +1398,12 @@ struct GraphKey {
     int dev;
     hipStream_t s;
     int64_t n;
-    int dtype, validate, bs, tt, schedule, arith;
+    int dtype, validate, bs, tt, schedule, arith, phase1;
     void *dist, *pred, *status, *ws, *arith_used;
     bool operator<(const GraphKey &o) const {
-        return std::tie(dev, s, n, dtype, validate, bs, tt, schedule, arith, dist, pred, status, ws,
+        return std::tie(dev, s, n, dtype, validate, bs, tt, schedule, arith, phase1, dist, pred, status, ws,
                         arith_used) < std::tie(o.dev, o.s, o.n, o.dtype, o.validate, o.bs, o.tt, o.schedule,
-                                               o.arith, o.dist, o.pred, o.status, o.ws, o.arith_used);
+                                               o.arith, o.phase1, o.dist, o.pred, o.status, o.ws, o.arith_used);
     }
 };
 std::mutex g_graph_mu;
@@ -1420,7 +1440,7 @@ apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dty
         apsp_status_t st = aux_stream(dev, s, &aux);
         if (st != APSP_SUCCESS) return st;
     }
-    GraphKey key{dev,  s,    n,    (int)dtype,   opt.validate, bs, tt, opt.schedule, opt.arith,
+    GraphKey key{dev,  s,    n,    (int)dtype,   opt.validate, bs, tt, opt.schedule, opt.arith, opt.phase1,
                  dist, pred, opt.d_status, w, opt.d_arith};
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
@@ -1463,9 +1483,15 @@ apsp_status_t check_options(int64_t n, apsp_dtype_t dtype, bool with_pred, const
         return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.thread_tile != 0 && opt.thread_tile != 4 && opt.thread_tile != 8) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.thread_tile == 4 && opt.block_size != 0 && opt.block_size != 64) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.block_size == 256 && with_pred) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.arith < 0 || opt.arith > 2) return APSP_ERROR_INVALID_ARGUMENT;
+    // 256-wide blocks hold 4-byte elements only: with predecessors they serve
+    // the distance rounds of the float32 route (its fallback recurrence
+    // takes 128-wide blocks)
+    if (opt.block_size == 256 && with_pred && !use_pp(n, true, opt.arith)) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.schedule < 0 || opt.schedule > 2) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.phase1 < 0 || opt.phase1 > 2) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.phase1 == 2 && opt.block_size != 256) return APSP_ERROR_INVALID_ARGUMENT;
     return APSP_SUCCESS;
 }
 
@@ -1542,8 +1568,8 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out) {
         recs.swap(g_prof);
     }
     *out = apsp_profile_t{};
-    apsp_kernel_time_t *slot[6] = {&out->phase1, &out->phase2, &out->phase3, &out->other,
-                                   &out->phase3_cross, &out->pred_product};
+    apsp_kernel_time_t *slot[7] = {&out->phase1,       &out->phase2,       &out->phase3,        &out->other,
+                                   &out->phase3_cross, &out->pred_product, &out->phase1_blocked};
     apsp_status_t st = APSP_SUCCESS;
     for (auto &r : recs) {
         float ms = 0.f;
@@ -1553,11 +1579,14 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out) {
             g_last_hip = (int)e;
             st = APSP_ERROR_HIP;
         }
-        apsp_kernel_time_t *k = slot[r.kind];
-        k->launches += 1;
-        k->total_ms += ms;
-        k->max_ms = std::max(k->max_ms, (double)ms);
-        k->updates += r.updates;
+        for (int kind : {r.kind == kPhase1Blocked ? (int)kPhase1 : -1, r.kind}) {
+            if (kind < 0) continue;
+            apsp_kernel_time_t *k = slot[kind];
+            k->launches += 1;
+            k->total_ms += ms;
+            k->max_ms = std::max(k->max_ms, (double)ms);
+            k->updates += r.updates;
+        }
         hipEventDestroy(r.start);
         hipEventDestroy(r.stop);
     }

@@ -59,6 +59,19 @@ def test_host_side_argument_errors():
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, tile4_bs128) == apsp.INVALID_ARGUMENT
     bad_arith = apsp.Options(0, 0, 0, 0, 0, 3, None)
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_arith) == apsp.INVALID_ARGUMENT
+    bad_schedule = apsp.Options(0, 0, 0, 3, 0, 0, None)
+    assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_schedule) == apsp.INVALID_ARGUMENT
+    bad_phase1 = apsp.Options(0, 256, 0, 0, 0, 0, None, None, 3)
+    assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_phase1) == apsp.INVALID_ARGUMENT
+    # the blocked diagonal closure needs 256-wide blocks
+    blocked_bs128 = apsp.Options(0, 128, 0, 0, 0, 0, None, None, 2)
+    assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, blocked_bs128) == apsp.INVALID_ARGUMENT
+    blocked_auto = apsp.Options(0, 0, 0, 0, 0, 0, None, None, 2)
+    assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, blocked_auto) == apsp.INVALID_ARGUMENT
+    # 256-wide blocks with predecessors only on the float32 route (arith 2, or
+    # automatically from n = 4096): the fp64-key recurrence holds 8-byte keys
+    pred256_keys = apsp.Options(0, 256, 0, 0, 0, 1, None)
+    assert apsp.solve_raw(fake, fake, 5000, apsp.INT32, None, pred256_keys) == apsp.INVALID_ARGUMENT
     assert L.apsp_status_string(3) == b"negative cycle"
     assert L.apsp_version() >= 100
 

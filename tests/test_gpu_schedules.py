@@ -1,0 +1,201 @@
+"""The production schedule against the full oracle at sizes the oracle solves
+whole.
+
+The automatic configuration uses the two-stream split (phase 3 of round r
+as the next round's panels plus the rest, the rest on a second stream beside
+phases 1-2 of round r+1) only from a padded order of 4096 (3072 for the
+fp64-key recurrence), and the blocked closure of the diagonal block with one
+launch of the remaining phase-3 tiles per round only from 10240.  The
+options schedule=2 and phase1=2 force both at any size, so the exact
+launch sequence the headline runs is compared here element by element with
+the oracle, for every arithmetic (int32, float32 watched with its int32
+redo, float32 weights, the float32 predecessor route and the fp64-key
+recurrence), distances and canonical predecessors, on 3 to 8 rounds.  The
+library's per-launch profile confirms that the split and the blocked
+closure really ran (Section "Data Locality": phase 1, then phases 2 and 3,
+per round; the split only reorders independent tiles)."""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+import synth
+from gpu_util import describe, first_mismatch, oracle_expect
+
+pytestmark = pytest.mark.gpu
+INF32 = synth.INF32
+
+_EXPECT = {}
+
+
+def _graph(kind, n):
+    seed = 4242 + n
+    if kind == "int":
+        return synth.single_int32(n, p=0.3, seed=seed)
+    if kind == "pot":
+        return synth.potential_int32(n, p=0.1, seed=seed)
+    if kind == "f32":
+        return synth.single_f32int(n, p=0.3, seed=seed)
+    if kind == "sparse":
+        return synth.single_int32(n, p=2.0 / n, seed=seed)
+    raise ValueError(kind)
+
+
+def _expect(orc, kind, n):
+    """Oracle distances and predecessors of one graph, computed once."""
+    key = (kind, n)
+    if key not in _EXPECT:
+        W = _graph(kind, n)
+        D0, P0, st0 = oracle_expect(orc, W, True)
+        assert st0 == oracle.OK
+        _EXPECT[key] = (W, D0, P0)
+    return _EXPECT[key]
+
+
+def _solve_profiled(W, pred, **kw):
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    d = torch.from_numpy(np.ascontiguousarray(W)).cuda()
+    p = torch.full(W.shape, -7, dtype=torch.int32, device="cuda") if pred else None
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    used = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    apsp.profile_begin()
+    apsp.solve(d, p, status=st, arith_used=used, **kw)
+    torch.cuda.synchronize()
+    prof = apsp.profile_end()
+    return (d.cpu().numpy(), p.cpu().numpy() if pred else None, int(st.item()), int(used.item()), prof)
+
+
+SIZES = [768, 1000, 1280, 2048]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("kind,arith", [("int", 1), ("int", 2), ("pot", 1), ("pot", 2), ("f32", 0)])
+def test_split_and_blocked_phase1_distances(orc, n, kind, arith):
+    """256-wide blocks, the blocked diagonal closure and one kRest launch per
+    round on the second stream, as at n = 32768."""
+    describe(f"schedule forced: distances n={n} {kind} arith={arith} bs=256 split+blocked")
+    W, D0, _ = _expect(orc, kind, n)
+    D, _, st, used, prof = _solve_profiled(W, False, block_size=256, schedule=2, phase1=2, arith=arith)
+    assert st == 0
+    assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+    R = (n + 255) // 256
+    assert prof["phase3_cross"]["launches"] == R - 1, prof["phase3_cross"]
+    assert prof["phase1_blocked"]["launches"] == R, prof["phase1_blocked"]
+    # one kRest launch per round but the last, plus the last round's whole phase 3
+    assert prof["phase3"]["launches"] == R, prof["phase3"]
+    if kind != "f32":
+        assert used == (1 if arith == 2 else 0)
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("kind", ["int", "pot", "f32"])
+def test_split_and_blocked_phase1_float32_predecessor_route(orc, n, kind):
+    """Predecessors by the float32 route with its distance rounds in the
+    production schedule (256-wide blocks, split, blocked closure), then the
+    key product."""
+    describe(f"schedule forced: float32 predecessor route n={n} {kind}")
+    W, D0, P0 = _expect(orc, kind, n)
+    D, P, st, used, prof = _solve_profiled(W, True, block_size=256, schedule=2, phase1=2, arith=2)
+    assert st == 0
+    assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+    assert first_mismatch(P, P0) is None, first_mismatch(P, P0)
+    R = (n + 255) // 256
+    assert prof["phase1_blocked"]["launches"] == R
+    assert prof["phase3_cross"]["launches"] == R - 1
+    assert used == 1
+
+
+def test_split_float32_predecessor_route_falls_back(orc):
+    """Negative weights together with keys D 2^S + v at or above 2^24 rule the
+    key product out: the fp64-key recurrence (128-wide blocks, rounds in
+    order) runs after a split float32 distance pass, exactly."""
+    describe("schedule forced: float32 predecessor route, fallback to the recurrence")
+    n = 1000
+    rng = np.random.default_rng(5)
+    B = pins.random_graph(rng, n, 0.01, 3000, 8000)
+    pot = (np.arange(n, dtype=np.int64) * 10000) // (n - 1)
+    W = np.where(B != INF32, B + pot[:, None] - pot[None, :], INF32)
+    np.fill_diagonal(W, 0)
+    W = W.astype(np.int32)
+    assert (W < 0).any()
+    D0, P0, st0 = orc.fw(W, pred=True)
+    assert st0 == oracle.OK and (D0[D0 != INF32] >= 2 ** 14).any()
+    D, P, st, used, prof = _solve_profiled(W, True, block_size=256, schedule=2, phase1=2, arith=2)
+    assert st == 0 and used == 0
+    assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+    assert first_mismatch(P, P0) is None, first_mismatch(P, P0)
+    assert prof["phase3_cross"]["launches"] == (n + 255) // 256 - 1
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("kind", ["int", "pot", "f32"])
+def test_split_fp64_key_recurrence(orc, n, kind):
+    """The exact fp64-key recurrence for predecessors on two streams
+    (128-wide blocks, the two-launch kRest)."""
+    describe(f"schedule forced: fp64-key recurrence n={n} {kind}")
+    W, D0, P0 = _expect(orc, kind, n)
+    D, P, st, used, prof = _solve_profiled(W, True, block_size=128, schedule=2, arith=1)
+    assert st == 0 and used == 0
+    assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+    assert first_mismatch(P, P0) is None, first_mismatch(P, P0)
+    R = (n + 127) // 128
+    assert prof["phase3_cross"]["launches"] == R - 1
+    assert prof["phase1_blocked"]["launches"] == 0
+
+
+@pytest.mark.parametrize("n,bs,tt", [(1000, 64, 4), (1280, 64, 8), (2048, 128, 8), (1000, 256, 8)])
+@pytest.mark.parametrize("kind", ["int", "f32", "sparse"])
+def test_split_two_launch_rest(orc, n, bs, tt, kind):
+    """The split with the stepwise diagonal kernel and kRest in two launches
+    per round (the automatic schedule from 4096 to 10240)."""
+    describe(f"schedule forced: split two-launch rest n={n} bs={bs} tt={tt} {kind}")
+    W, D0, _ = _expect(orc, kind, n)
+    kw = dict(block_size=bs, thread_tile=tt, schedule=2, phase1=1)
+    if kind != "f32":
+        kw["arith"] = 2
+    D, _, st, _, prof = _solve_profiled(W, False, **kw)
+    assert st == 0
+    assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+    R = (n + bs - 1) // bs
+    assert prof["phase3_cross"]["launches"] == R - 1
+    assert prof["phase1_blocked"]["launches"] == 0
+    assert prof["phase3"]["launches"] == 2 * (R - 1) + 1
+
+
+@pytest.mark.parametrize("case", ["chain", "long_paths"])
+def test_split_float32_pass_redone_in_int32(orc, case):
+    """Operands reaching 2^23 in the split float32 pass make the device redo
+    the solve in int32 (rounds in order, blocked closure): still exact.  A
+    chain of near-bound weights certainly passes 2^23; random long paths may
+    or may not."""
+    describe(f"schedule forced: float32 watch fallback {case}")
+    n = 900
+    rng = np.random.default_rng(11)
+    bound = (2 ** 28 - 1) // (n - 1)
+    if case == "chain":
+        W = pins.random_graph(rng, n, 0.002, bound // 2, bound)
+        for i in range(n - 1):
+            W[i, i + 1] = bound - (i % 7)
+    else:
+        W = pins.random_graph(rng, n, 0.05, max(1, bound // 2), bound)
+    D0, _, st0 = orc.fw(W)
+    assert st0 == oracle.OK
+    D, _, st, used, prof = _solve_profiled(W, False, block_size=256, schedule=2, phase1=2, arith=2)
+    assert st == 0
+    assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+    if case == "chain":
+        assert used == 0
+    assert prof["phase3_cross"]["launches"] == (n + 255) // 256 - 1
+
+
+def test_split_negative_cycle_reported():
+    describe("schedule forced: negative cycle")
+    n = 800
+    W = synth.single_int32(n, p=0.05, seed=12)
+    W[10, 600], W[600, 10] = 5, -9
+    for arith in (1, 2):
+        _, _, st, _, _ = _solve_profiled(W, False, block_size=256, schedule=2, phase1=2, arith=arith)
+        assert st == 3, arith

@@ -258,42 +258,82 @@ def test_full_size_n8192_f32_pred_sampled_rows(orc):
     assert (np.diag(D) == 0).all()
 
 
-def test_full_size_n32768_potential_sampled_rows(orc):
+@pytest.mark.parametrize("half", [0, 1])
+def test_full_size_n32768_potential_sampled_rows(orc, half):
     """The n=32768 int32 potential-weight workload (negative weights, no
     negative cycle) in the launch configuration the benchmark times
-    (automatic block size, two-stream schedule): sampled rows against the row
-    oracle exactly, and properties that hold at any size checked on every
-    element: zero diagonal, D <= W, and D(i,j) <= D(i,k) + D(k,j) for sampled k."""
+    (automatic block size 256, two-stream schedule, blocked phase 1): one row
+    in every other block row (the two halves together cover all 128 block
+    rows, at varying offsets inside the block) against the row oracle
+    exactly, and properties that hold at any size checked on every element:
+    zero diagonal, D <= W, and D(i,j) <= D(i,k) + D(k,j) for 32 values of k
+    spread over the block rows."""
     import torch
 
     import paper_1811_01201_amd as apsp
-    describe("single n=32768 int32 potential full size")
+    describe(f"single n=32768 int32 potential full size, block rows = {half} mod 2")
     n = 32768
     W = synth.potential_int32(n, p=0.1, seed=synth.BASE_SEED + 2)
     d = torch.from_numpy(W).cuda()
     st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
     used = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    apsp.profile_begin()
     apsp.solve(d, status=st, arith_used=used)
     torch.cuda.synchronize()
+    prof = apsp.profile_end()
     assert int(st.item()) == 0
     assert int(used.item()) == 1  # the float32 arithmetic held (exact)
-    for src in [0, 12345, n - 1]:
-        dr, _, s = orc.row(W, src)
+    assert prof["phase1_blocked"]["launches"] == n // 256 and prof["phase3_cross"]["launches"] == n // 256 - 1
+    srcs = [256 * r + (37 * r + 11 * half) % 256 for r in range(half, n // 256, 2)]
+    got = d[torch.tensor(srcs, device="cuda")].cpu().numpy()
+    for src, g, (dr, _, s) in zip(srcs, got, orc.rows(W, srcs)):
         assert s == 0
-        got = d[src].cpu().numpy()
-        assert np.array_equal(got, dr), (src, first_mismatch(got[None], dr[None]))
+        assert np.array_equal(g, dr), (src, first_mismatch(g[None], dr[None]))
     assert bool((torch.diagonal(d) == 0).all())
     w = torch.from_numpy(W).cuda()
-    ks = [0, 4321, n - 1]
+    ks = [1024 * q + (97 * q + half) % 1024 for q in range(32)]
     dk_rows = {k: d[k].long() for k in ks}
     for r0 in range(0, n, 2048):
         blk = d[r0:r0 + 2048]
         assert bool((blk <= w[r0:r0 + 2048]).all()), r0
         b64 = blk.long()
         for k in ks:
-            bound = d[r0:r0 + 2048, k].long()[:, None] + dk_rows[k][None, :]
+            bound = b64[:, k][:, None] + dk_rows[k][None, :]
             assert bool((b64 <= bound).all()), (r0, k)
     del d, w
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,rows", [(16384, 48), (32768, 32)])
+def test_paper_configuration_float32_pred_large_sampled_rows(orc, n, rows):
+    """The paper's configuration (float32 distances plus the path matrix) at
+    its larger sizes, integer weights 1..1000 with p = 0.3, in the automatic
+    launch configuration (float32 route: 256-wide distance rounds on two
+    streams with the blocked phase 1, then the key product): sampled rows
+    spread over all block rows against the row oracle, distances and
+    canonical predecessors exactly."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe(f"single n={n} float32 + predecessors sampled rows")
+    W = synth.single_f32int(n, p=0.3, seed=synth.BASE_SEED + 1 + n)
+    d = torch.from_numpy(W).cuda()
+    p = torch.full((n, n), -7, dtype=torch.int32, device="cuda")
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    used = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    apsp.solve(d, p, status=st, arith_used=used)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and int(used.item()) == 1
+    step = n // rows
+    srcs = [step * q + (53 * q) % step for q in range(rows)]
+    idx = torch.tensor(srcs, device="cuda")
+    gd, gp = d[idx].cpu().numpy(), p[idx].cpu().numpy()
+    for src, g, gq, (dr, pr, s) in zip(srcs, gd, gp, orc.rows(W, srcs, pred=True)):
+        assert s == 0
+        assert np.array_equal(g, dr.astype(np.float32)), (src, first_mismatch(g[None], dr[None]))
+        assert np.array_equal(gq, pr), (src, first_mismatch(gq[None], pr[None]))
+    assert bool((torch.diagonal(d) == 0).all()) and bool((torch.diagonal(p) == -1).all())
+    del d, p
     torch.cuda.empty_cache()
 
 
@@ -405,12 +445,21 @@ def test_real_valued_float32_pred_chains(orc):
                                             (1536, 256, "f32", False), (1300, 128, "sparse", False),
                                             (900, 64, "f32", True)])
 def test_lookahead_schedule_matches_in_order(orc, n, bs, kind, pred):
-    """Two-stream lookahead (default) == one stream in round order == oracle."""
+    """The two-stream lookahead (forced at these sizes with schedule=2; the
+    profile shows its next-round panel launches ran) == one stream in round
+    order == oracle."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
     describe(f"single schedules n={n} bs={bs} {kind} pred={pred}")
     W = _graph(kind, n, seed=n + bs)
     D0, P0, _ = oracle_expect(orc, W, pred)
-    Da, Pa, sa = gpu_solve(W, pred, block_size=bs)
-    Db, Pb, sb = gpu_solve(W, pred, block_size=bs, schedule=1)
+    torch.cuda.synchronize()
+    apsp.profile_begin()
+    Da, Pa, sa = gpu_solve(W, pred, block_size=bs, schedule=2, arith=1)
+    prof = apsp.profile_end()
+    assert prof["phase3_cross"]["launches"] == (n + bs - 1) // bs - 1, prof["phase3_cross"]
+    Db, Pb, sb = gpu_solve(W, pred, block_size=bs, schedule=1, arith=1)
     assert sa == 0 and sb == 0
     assert first_mismatch(Da, D0) is None and first_mismatch(Db, D0) is None
     if pred:

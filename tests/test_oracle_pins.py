@@ -304,6 +304,26 @@ def test_row_matches_full_and_dijkstra(orc, kind):
             assert [None if (x == INF32 or x == np.inf) else x for x in dr.tolist()] == ref
 
 
+@pytest.mark.parametrize("n,p,seed", [(160, 0.1, 34), (90, 0.3, 35), (200, 0.03, 36)])
+def test_row_real_valued_predecessors_pinned(orc, n, p, seed):
+    """Real-valued float32 weights: the row oracle's predecessors equal the
+    closed form of the canonical rule evaluated on distances from an
+    independent binary-heap Dijkstra (both sides add the float32 weights in
+    double precision along the path, so the distances agree exactly), and
+    every predecessor chain reproduces its distance."""
+    W = synth.single_f32real(n, p=p, lo=0.5, hi=100.0, seed=seed)
+    D, _, _ = orc.fw(W)
+    for src in [0, 1, n // 3, n - 1]:
+        dr, pr, st = orc.row(W, src, pred=True)
+        assert st == oracle.OK
+        ref = pins.dijkstra_row(W, src)
+        assert [None if x == np.inf else x for x in dr.tolist()] == ref
+        assert pr.tolist() == pins.canonical_pred_row(W, ref, src)
+        P = np.broadcast_to(pr, (n, n))
+        for j in range(n):
+            assert pins.walk_pred_chain(W, D, P, src, j, tol=1e-9), (src, j)
+
+
 def test_potential_graph_johnson_identity(orc):
     """Weights b + pi(i) - pi(j): D_w(i,j) = D_b(i,j) + pi(i) - pi(j)."""
     n = 220
