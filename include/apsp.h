@@ -166,6 +166,27 @@ typedef struct {
 apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype,
                             hipStream_t stream, const apsp_options_t *options);
 
+/* apsp_solve_ex for callers that cannot allocate memory (code under hipGraph
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, but every work matrix lives in a static device
+ * array of apsp_noalloc_scratch_bytes() bytes (one per device, held until the
+ * process ends) instead of library-allocated memory, and the call makes no
+ * hipMalloc, hipFree, stream, event or graph creation.
+ *   - The rounds run in order on the caller's stream: options->schedule must
+ *     be 0 or 1 and options->use_graph 0 (else APSP_ERROR_INVALID_ARGUMENT).
+ *   - Sizes whose work memory would exceed the array (any n <= 2048 fits)
+ *     return APSP_ERROR_INVALID_ARGUMENT with nothing enqueued.
+ *   - All calls on one device share that device's array, and its contents
+ *     are whatever the last call left (each solve initialises every word it
+ *     reads): calls whose work overlaps in time on one device race, so
+ *     serialise them (one stream, or events).
+ *   - No per-launch profiling (apsp_profile_*) is recorded for these calls.
+ * Arguments, layout and data-dependent outcomes are those of apsp_solve_ex. */
+apsp_status_t apsp_solve_noalloc(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype,
+                                 hipStream_t stream, const apsp_options_t *options);
+/* Size in bytes of apsp_solve_noalloc's static per-device array. */
+int64_t apsp_noalloc_scratch_bytes(void);
+
 /* ---------------------------------------------------------------- steppers
  *
  * A solve issued a few rounds at a time (round-level preemption, for

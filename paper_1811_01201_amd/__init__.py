@@ -89,6 +89,9 @@ def lib():
         L.apsp_weight_bound.argtypes = [i64]
         L.apsp_weight_bound.restype = i64
         L.apsp_release_workspace.restype = c_int
+        L.apsp_solve_noalloc.argtypes = [vp, vp, i64, c_int, vp, ctypes.POINTER(Options)]
+        L.apsp_solve_noalloc.restype = c_int
+        L.apsp_noalloc_scratch_bytes.restype = i64
         L.apsp_profile_begin.restype = c_int
         L.apsp_profile_end.argtypes = [ctypes.POINTER(Profile)]
         L.apsp_profile_end.restype = c_int
@@ -202,6 +205,32 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
     if check and st != SUCCESS:
         raise APSPError(st, "apsp_solve_ex")
     return st
+
+
+def solve_noalloc(dist, pred=None, *, validate=False, block_size=0, status=None, stream=None, check=True,
+                  thread_tile=0, arith=0, arith_used=None, phase1=0) -> int:
+    """solve() through apsp_solve_noalloc: the library allocates nothing (its
+    work memory is a static per-device array, see noalloc_scratch_bytes());
+    rounds in order on the stream.  Same arguments and results as solve()."""
+    assert dist.dim() == 2 and dist.shape[0] == dist.shape[1], "dist must be square"
+    assert dist.is_cuda and dist.is_contiguous()
+    n = dist.shape[0]
+    pp = None
+    if pred is not None:
+        assert pred.is_cuda and pred.is_contiguous() and tuple(pred.shape) == (n, n)
+        pp = pred.data_ptr()
+    opt = Options(int(validate), int(block_size), int(thread_tile), 1, 0, int(arith),
+                  status.data_ptr() if status is not None else None,
+                  arith_used.data_ptr() if arith_used is not None else None, int(phase1))
+    st = lib().apsp_solve_noalloc(dist.data_ptr(), pp, n, _dtype_code(dist), _stream_ptr(stream),
+                                  ctypes.byref(opt))
+    if check and st != SUCCESS:
+        raise APSPError(st, "apsp_solve_noalloc")
+    return st
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().apsp_noalloc_scratch_bytes())
 
 
 class Stepper:

@@ -863,6 +863,7 @@ bool g_prof_on = false;
 std::vector<ProfRecord> g_prof;
 
 thread_local bool t_capturing = false;  // launches are being recorded into a hipGraph
+thread_local bool t_noalloc = false;    // apsp_solve_noalloc: no event creation either
 
 // Operations of a solve recorded for a stepper (see enq below).
 struct Recorder {
@@ -880,7 +881,7 @@ struct ProfScope {
     ProfScope(int kind, double updates, hipStream_t stream) : s(stream) {
         {
             std::lock_guard<std::mutex> lk(g_prof_mu);
-            on = g_prof_on && !t_capturing && !t_rec && kind >= 0;
+            on = g_prof_on && !t_capturing && !t_rec && !t_noalloc && kind >= 0;
         }
         if (!on) return;
         rec.kind = kind;
@@ -1495,6 +1496,34 @@ apsp_status_t check_options(int64_t n, apsp_dtype_t dtype, bool with_pred, const
     return APSP_SUCCESS;
 }
 
+// Static work memory of apsp_solve_noalloc: the largest work matrix any
+// solve of n <= 2048 needs (2048^2 8-byte keys, or two 2048^2 float32
+// matrices, plus the route's status words).  One copy per device, held
+// until the process ends; in host code the name only stands for the
+// symbol, so kernels get the device address found by hipGetSymbolAddress.
+constexpr size_t kScratchBytes = (size_t)2048 * 2048 * 8 + 4096;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// The calling device's copy of scratch (looked up once per device).
+apsp_status_t scratch_ptr(void **out) {
+    int dev = 0;
+    APSP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return APSP_ERROR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        APSP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return APSP_ERROR_HIP;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return APSP_SUCCESS;
+}
+
 apsp_status_t solve_internal(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t s,
                              const apsp_options_t &opt, void *ws, size_t ws_bytes) {
     if (n == 0) return APSP_SUCCESS;
@@ -1546,6 +1575,34 @@ apsp_status_t apsp_solve_ex(void *dist, int32_t *pred, int64_t n, apsp_dtype_t d
 
 apsp_status_t apsp_solve(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t stream) {
     return apsp_solve_ex(dist, pred, n, dtype, stream, nullptr);
+}
+
+int64_t apsp_noalloc_scratch_bytes(void) { return (int64_t)kScratchBytes; }
+
+apsp_status_t apsp_solve_noalloc(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t stream,
+                                 const apsp_options_t *options) {
+    apsp_options_t opt{};
+    if (options) opt = *options;
+    const apsp_status_t bad = check_options(n, dtype, pred != nullptr, opt);
+    if (bad != APSP_SUCCESS) return bad;
+    // rounds in order on the caller's stream: the two-stream split would need a
+    // second stream and events, a hipGraph an instantiation
+    if (opt.use_graph || opt.schedule == 2) return APSP_ERROR_INVALID_ARGUMENT;
+    opt.schedule = 1;
+    if (n == 0) return APSP_SUCCESS;
+    if (!dist || ((uintptr_t)dist % 4) != 0 || ((uintptr_t)pred % 4) != 0) return APSP_ERROR_INVALID_ARGUMENT;
+    const size_t need =
+        work_bytes(n, pred != nullptr, opt.block_size, ((uintptr_t)dist % 16) == 0, dtype, opt.arith);
+    if (need > kScratchBytes) return APSP_ERROR_INVALID_ARGUMENT;  // beyond the static scratch
+    void *ws = nullptr;
+    if (need > 0) {
+        const apsp_status_t st = scratch_ptr(&ws);
+        if (st != APSP_SUCCESS) return st;
+    }
+    t_noalloc = true;
+    const apsp_status_t st = solve_direct(dist, pred, n, dtype, stream, opt, ws, kScratchBytes);
+    t_noalloc = false;
+    return st;
 }
 
 apsp_status_t apsp_profile_begin(void) {

@@ -72,6 +72,18 @@ def test_host_side_argument_errors():
     # automatically from n = 4096): the fp64-key recurrence holds 8-byte keys
     pred256_keys = apsp.Options(0, 256, 0, 0, 0, 1, None)
     assert apsp.solve_raw(fake, fake, 5000, apsp.INT32, None, pred256_keys) == apsp.INVALID_ARGUMENT
+    # the no-allocation entry point: sizes beyond its static array, the
+    # two-stream split and graph replay are refused before any HIP call
+    L.apsp_solve_noalloc.restype = ctypes.c_int
+    assert L.apsp_solve_noalloc(fake, fake, 4000, apsp.INT32, None, None) == apsp.INVALID_ARGUMENT
+    assert L.apsp_solve_noalloc(fake, None, 100, apsp.INT32, None, ctypes.byref(bad_schedule)) == \
+        apsp.INVALID_ARGUMENT
+    split = apsp.Options(0, 0, 0, 2, 0, 0, None)
+    assert L.apsp_solve_noalloc(fake, None, 100, apsp.INT32, None, ctypes.byref(split)) == apsp.INVALID_ARGUMENT
+    graph = apsp.Options(0, 0, 0, 0, 1, 0, None)
+    assert L.apsp_solve_noalloc(fake, None, 100, apsp.INT32, None, ctypes.byref(graph)) == apsp.INVALID_ARGUMENT
+    assert L.apsp_solve_noalloc(fake, None, 0, apsp.INT32, None, None) == apsp.SUCCESS
+    assert L.apsp_noalloc_scratch_bytes() >= 2048 * 2048 * 8
     assert L.apsp_status_string(3) == b"negative cycle"
     assert L.apsp_version() >= 100
 
