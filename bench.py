@@ -25,45 +25,93 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.32e12 lane-cycles/s; the
-# datasheet's 157.3 TFLOP/s float32 vector rate (an FMA counts 2 flops) is
-# 78.6e12 float32 VALU lane-instructions/s, two per lane-cycle.  Two k-steps
-# of one element take 3 instructions (2 float32 adds + 1 three-input
-# minimum): 1.5 instructions per (i,j,k) relaxation, 2 metric ops each.
-VALU_LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
-F32_VALU_INSTR_PER_S = 157.3e12 / 2.0
-PEAK_OPS = F32_VALU_INSTR_PER_S / 1.5 * 2.0            # 104.9e12 min-plus ops/s
-PEAK_ADD_MIN = VALU_LANE_CYCLES_PER_S                  # 39.3e12 (add + min at one instruction per cycle)
+# MI355X published float32 vector peak: 157.3 TFLOP/s = 256 CUs x 2.4 GHz x
+# 256 flops per CU-cycle (an FMA counts 2 flops).  A min-plus relaxation
+# (one add, one min) counts 2 ops the same way, so 157.3 T ops/s is the
+# published ALU peak this path is reported against.  The instruction-set
+# ceiling of the actual float32 min-plus step (2 v_add_f32 + 1 v_min3_f32 per
+# two relaxations; no fused add-min exists) is measured on the device by the
+# library's steady-state VALU probes and reported beside it.
+PEAK_F32_VECTOR = 157.3e12
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(W, budget_s: float):
-    """The oracle's recurrence on the host, first K iterations of k over the
-    full matrix (a bounded sample of the same solve), K grown until the
-    budget is spent.  Reports 2 n^2 K / t."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(W, budget_s: float, c1_W=None, batch=None):
+    """The oracle on the host, built here with gcc -O3 -march=native (OpenMP
+    over rows): (a) the headline input, first K iterations of k over the full
+    matrix (a bounded sample of the same solve), K grown until the budget is
+    spent, with all host threads and with one, reported as 2 n^2 K / t;
+    (b) the n=1024 workload solved whole, one thread and all threads;
+    (c) every graph of the 4096-graph batch, one graph per thread."""
+    import tempfile
+
+    import numpy as np
+
     import oracle  # test infrastructure: only this leg of the benchmark uses it
 
-    orc = oracle.default()
+    tmp = tempfile.mkdtemp(prefix="apsp_oracle_")
+    orc = oracle.Oracle(oracle.load(oracle.build_native(tmp)))
     n = W.shape[0]
-    D = W.copy()
     threads = oracle.default_threads()
-    k = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and k < n:
-        orc.fw_steps(D, k, k + 1, threads=threads)
-        k += 1
-    t = time.perf_counter() - t0
-    return {
-        "value": round(2.0 * n * n * k / t / 1e9, 3),
+
+    def sample(nthreads, budget):
+        D = W.copy()
+        k = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget and k < n:
+            orc.fw_steps(D, k, k + 1, threads=nthreads)
+            k += 1
+        t = time.perf_counter() - t0
+        return k, t
+
+    k_all, t_all = sample(threads, budget_s)
+    k_one, t_one = sample(1, budget_s / 3.0)
+    out = {
+        "value": round(2.0 * n * n * k_all / t_all / 1e9, 3),
         "unit": "GOPS",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"first {k} of {n} k-iterations of the oracle's plain triple loop on the same "
-                  f"n={n} int32 input ({t:.1f} s)",
+        "sample": f"first {k_all} of {n} k-iterations of the oracle's plain triple loop on the same "
+                  f"n={n} int32 input ({t_all:.1f} s, {threads} threads)",
+        "build": "gcc -O3 -march=native -fopenmp (the oracle source, built on this host)",
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
+        "affinity_cpus": len(os.sched_getaffinity(0)),
+        "one_thread": {"value": round(2.0 * n * n * k_one / t_one / 1e9, 3), "unit": "GOPS",
+                       "sample": f"first {k_one} k-iterations ({t_one:.1f} s)"},
     }
+    if c1_W is not None:
+        m = c1_W.shape[0]
+        res = {}
+        for label, nt in (("one_thread", 1), ("all_threads", threads)):
+            t0 = time.perf_counter()
+            orc.fw(c1_W, threads=nt)
+            t = time.perf_counter() - t0
+            res[label] = {"ms": round(t * 1e3, 2), "gops": round(2.0 * m ** 3 / t / 1e9, 2)}
+        out["c1_n1024_full"] = res
+    if batch is not None:
+        graphs = [batch.graph(b) for b in range(len(batch.ns))]
+        ops = float((2.0 * batch.ns.astype(np.float64) ** 3).sum())
+        t0 = time.perf_counter()
+        orc.fw_many(graphs, workers=threads)
+        t = time.perf_counter() - t0
+        out["batched_4096_graphs"] = {"s": round(t, 2), "solves_per_s": round(len(graphs) / t, 1),
+                                      "gops": round(ops / t / 1e9, 2), "threads": threads,
+                                      "mode": "one graph per thread"}
+    return out
 
 
 def sweep_leg(sizes, modes):
@@ -128,15 +176,19 @@ def batched_leg(replays: int, graph_replays: bool = True):
     d = torch.empty_like(pristine)
     plan = apsp.BatchPlan(bt.ns, bt.offsets, "int32")
     ops = float((2.0 * bt.ns.astype(np.float64) ** 3).sum())
+    status = torch.full((len(bt.ns),), -1, dtype=torch.int32, device="cuda")
     times = []
     for r in range(replays + 1):
         d.copy_(pristine)
+        status.fill_(-1)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        plan.execute(d)
+        plan.execute(d, status=status)
         e1.record()
         torch.cuda.synchronize()
+        if not bool((status == apsp.SUCCESS).all()):
+            raise RuntimeError("a batched solve reported a non-success status")
         if r > 0:
             times.append(e0.elapsed_time(e1))
     med = float(np.median(times))
@@ -184,11 +236,13 @@ def batched_leg(replays: int, graph_replays: bool = True):
     }
 
 
-def serving_leg(count: int):
+def serving_leg(count: int, rate_fractions=(0.25, 0.5, 0.75, 0.9, 1.1), per_rate_s: float = 6.0):
     """Poisson request streams (n log-uniform in [32, 8192], int32 / float32
     integer weights 1..1000 half each, p=0.2, predecessors for 30%) through
-    the server at its saturated rate and at 0.5x / 0.9x of it; the same
-    saturated stream through a FIFO one-request-at-a-time server."""
+    the continuous-batching server and a FIFO one-request-at-a-time server:
+    both saturated (all requests submitted at once), then both at the same
+    offered rates, fractions of the continuous-batching saturated rate
+    (about per_rate_s seconds of requests each)."""
     import threading
 
     import torch
@@ -250,11 +304,23 @@ def serving_leg(count: int):
         return out
 
     sat = run(None, count)
+    fifo_sat = run(None, count, fifo=True)
     out = {"workload": "Poisson stream, n=round(exp U[ln32,ln8192]), int32/float32 integer weights "
                        "[1,1000] half each, p=0.2, predecessors for 30%",
-           "continuous_batching": [sat], "fifo_one_at_a_time": [run(None, max(100, count // 2), fifo=True)]}
-    for f in (0.5, 0.9):
-        out["continuous_batching"].append(run(f * sat["solves_per_s"], count))
+           "continuous_batching": [sat], "fifo_one_at_a_time": [fifo_sat],
+           "saturated_speedup_vs_fifo": round(sat["solves_per_s"] / fifo_sat["solves_per_s"], 3)}
+    # the same Poisson streams (rates relative to the continuous-batching
+    # server's saturated rate) through both servers
+    for f in rate_fractions:
+        rate = f * sat["solves_per_s"]
+        m = max(200, min(count, int(rate * per_rate_s)))
+        log(f"[bench] serving at {f:.2f}x saturation ({rate:.0f}/s, {m} requests)")
+        cb = run(rate, m)
+        cb["load"] = f
+        ff = run(rate, m, fifo=True)
+        ff["load"] = f
+        out["continuous_batching"].append(cb)
+        out["fifo_one_at_a_time"].append(ff)
     # round-level preemption: large solves issued 4 rounds at a time
     out["continuous_batching_sliced"] = [run(0.9 * sat["solves_per_s"], count, slice_rounds=4)]
     return out
@@ -304,7 +370,7 @@ def paper_config_leg(steps: int):
         ms = pp["total_ms"] / pp["launches"]
         rate = 2.0 * pp["updates"] / pp["launches"] / (ms / 1e3) / 1e12
         out["key_product"] = {"avg_launch_ms": round(ms, 4), "achieved": round(rate, 2), "unit": "Tops/s",
-                              "frac": round(rate * 1e12 / PEAK_OPS, 4)}
+                              "frac": round(rate * 1e12 / PEAK_F32_VECTOR, 4)}
     del work, pristine, pred
     torch.cuda.empty_cache()
     return out
@@ -323,6 +389,24 @@ def device_state():
     return out
 
 
+def isa_ceiling():
+    """Steady-state VALU rates of the float32 min-plus step and of its two
+    instructions alone (library probes), and the ceilings they give in
+    metric ops per second (2 per relaxation)."""
+    import paper_1811_01201_amd as apsp
+    rates = {k: apsp.probe_valu(k)["lane_instr_per_s"] for k in ("mix_f32", "add_f32", "min3_f32")}
+    # two relaxations per lane take 3 instructions of the mix, or, issued one
+    # after another, 2 adds at the add rate and 1 three-input minimum at its rate
+    mix = rates["mix_f32"] * 2.0 / 3.0 * 2.0
+    serial = 2.0 * 2.0 / (2.0 / rates["add_f32"] + 1.0 / rates["min3_f32"])
+    return {"value": round(mix / 1e12, 3), "unit": "Tops/s",
+            "derivation": "measured rate of the float32 min-plus step (2 v_add_f32 + 1 v_min3_f32 per two "
+                          "relaxations, every CU busy, steady state) x 2/3 relaxations per instruction x 2 ops",
+            "from_single_instruction_rates": round(serial / 1e12, 3),
+            "lane_instr_per_s": {k: round(v / 1e12, 3) for k, v in rates.items()},
+            "lane_instr_unit": "1e12 lane-instructions/s"}, mix
+
+
 def single_leg(args, n):
     """Timed single-graph solves; returns (host weights, JSON fields)."""
     import torch
@@ -338,15 +422,18 @@ def single_leg(args, n):
     torch.cuda.synchronize()
 
     arith_used = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    status = torch.full((max(args.steps, args.warmup, 1),), -1, dtype=torch.int32, device="cuda")
 
-    def step():
+    def step(i):
         work.copy_(pristine)
-        apsp.solve(work, block_size=args.block_size, arith=args.arith, arith_used=arith_used)
+        apsp.solve(work, block_size=args.block_size, arith=args.arith, arith_used=arith_used,
+                   status=status[i:i + 1])
 
     for i in range(args.warmup):
         log(f"[bench] warmup {i + 1}/{args.warmup}")
-        step()
+        step(i)
     torch.cuda.synchronize()
+    status.fill_(-1)
 
     apsp.profile_begin()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -355,13 +442,16 @@ def single_leg(args, n):
     t0 = time.perf_counter()
     e0.record()
     for i in range(args.steps):
-        step()
+        step(i)
         log(f"[bench] step {i + 1}/{args.steps} enqueued")
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = apsp.profile_end()
     dev_state = device_state()
+    st = status[:args.steps].cpu().tolist()
+    if any(x != apsp.SUCCESS for x in st):
+        raise RuntimeError(f"timed solves reported status {st}: the line is not a valid measurement")
     t = e0.elapsed_time(e1) / 1e3
     ms_per_step = t / args.steps * 1e3
     gops = 2.0 * n ** 3 * args.steps / t / 1e9
@@ -373,25 +463,32 @@ def single_leg(args, n):
     per_launch_ops = 2.0 * p3["updates"] / max(1, p3["launches"])
     avg_ms = p3["total_ms"] / max(1, p3["launches"])
     achieved = per_launch_ops / (avg_ms / 1e3) / 1e12
+    ceiling, ceiling_ops = isa_ceiling()
+    if achieved * 1e12 <= ceiling_ops:
+        ceiling["frac"] = round(achieved * 1e12 / ceiling_ops, 4)
+    else:
+        ceiling["note"] = "the kernel ran faster than the probe's mix: no fraction is reported"
     roofline = {
         "bound": "alu",
-        "kernel": "phase3_kernel kRest (remaining-block min-plus products, 128x128 tiles, one launch per round from n=10240, two below)",
+        "kernel": "phase3_kernel kRest (remaining-block min-plus products, 128x128 tiles, one launch per round "
+                  "from n=10240, two below)",
         "achieved": round(achieved, 3),
-        "peak": round(PEAK_OPS / 1e12, 3),
-        "unit": "Tops/s (2 ops per (i,j,k) relaxation)",
-        "frac": round(achieved * 1e12 / PEAK_OPS, 4),
-        "frac_vs_add_min_peak": round(achieved * 1e12 / PEAK_ADD_MIN, 4),
+        "peak": round(PEAK_F32_VECTOR / 1e12, 1),
+        "unit": "TFLOP/s-equivalent: 2 ops per (i,j,k) relaxation (one add, one min), as an FMA counts 2 flops",
+        "frac": round(achieved * 1e12 / PEAK_F32_VECTOR, 4),
+        "peak_basis": "MI355X published float32 vector peak, 256 CUs x 2.4 GHz x 256 flops per CU-cycle",
+        "isa_ceiling": ceiling,
         "avg_launch_ms": round(avg_ms, 4),
         "launches": p3["launches"],
         "traffic": None,
     }
-    probe = apsp.probe_valu()
-    # the probe runs the kernel's own instruction mix (3 float32 instructions per 2 relaxations)
-    measured_peak = probe["lane_instr_per_s"] * 2.0 / 1.5
-    roofline["peak_measured"] = round(measured_peak / 1e12, 3)
-    roofline["frac_vs_measured_peak"] = round(achieved * 1e12 / measured_peak, 4)
-    phases = {k: {"launches": v["launches"], "ms_per_step": round(v["total_ms"] / args.steps, 3)}
+    # under the two-stream schedule the phases overlap: each figure is the
+    # summed span between the events around its launches (waiting for free
+    # compute units included), not its own work
+    phases = {k: {"launches": v["launches"], "event_span_ms_per_step": round(v["total_ms"] / args.steps, 3)}
               for k, v in prof.items() if v["launches"]}
+    phases["note"] = ("event spans of launches on two streams that overlap; phase 1 and 2 spans include "
+                      "waiting behind the other stream's remaining-block products")
 
     # algorithmic HBM bytes of one launch: its C elements read and written
     # once (8 bytes), plus the panel rows and columns they need, once
@@ -413,8 +510,49 @@ def single_leg(args, n):
     del work, pristine
     torch.cuda.empty_cache()
     return W, {"value": round(gops, 2), "ms_per_step": round(ms_per_step, 3), "wall_s": round(wall, 3),
-               "dtype": "f32" if int(arith_used.item()) == 1 else "int32",
+               "dtype": "f32" if int(arith_used.item()) == 1 else "int32", "step_status": "all success",
                "roofline": roofline, "phases": phases, "device": dev_state}
+
+
+def c1_leg(reps: int):
+    """The small single-graph workload: n=1024, p=0.5, int32 weights
+    1..1000, distances only; `reps` solves timed one by one (HIP events,
+    input restored by a device copy outside the events), median and p99,
+    eager and replayed from a captured hipGraph."""
+    import numpy as np
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    import synth
+
+    n = 1024
+    W = synth.single_int32(n, p=0.5, seed=synth.BASE_SEED + 0)
+    pristine = torch.from_numpy(W).cuda()
+    work = torch.empty_like(pristine)
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    out = {"workload": "single directed graph n=1024, edge prob 0.5, int32 weights [1,1000], distances only"}
+    with torch.cuda.stream(stream):
+        for label, kw in (("eager", {}), ("hipgraph_replay", {"use_graph": True})):
+            times = []
+            for r in range(reps + 2):
+                work.copy_(pristine)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                apsp.solve(work, status=st, **kw)
+                e1.record(stream)
+                stream.synchronize()
+                if int(st.item()) != apsp.SUCCESS:
+                    raise RuntimeError(f"n=1024 solve reported status {int(st.item())}")
+                if r >= 2:
+                    times.append(e0.elapsed_time(e1))
+            med = float(np.median(times))
+            out[label] = {"ms_median": round(med, 4), "ms_p99": round(float(np.percentile(times, 99)), 4),
+                          "gops": round(2.0 * n ** 3 / (med / 1e3) / 1e9, 1), "solves": reps}
+    del work, pristine
+    torch.cuda.empty_cache()
+    return out, W
 
 
 def main():
@@ -425,7 +563,7 @@ def main():
     ap.add_argument("--n", type=int, default=32768, help="override the graph size (quick runs)")
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--arith", type=int, default=0, help="0 automatic, 1 int32, 2 float32 (exact, checked)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-single", action="store_true", help="batched/serving legs only")
     ap.add_argument("--sweep", default="",
@@ -440,6 +578,10 @@ def main():
     ap.add_argument("--no-batched-graph", action="store_true",
                     help="skip the hipGraph replays of the batched plan (counter collection runs)")
     ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-rate-seconds", type=float, default=6.0,
+                    help="seconds of Poisson arrivals per offered rate")
+    ap.add_argument("--skip-c1", action="store_true", help="skip the n=1024 leg")
+    ap.add_argument("--c1-reps", type=int, default=20)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -478,6 +620,11 @@ def main():
     if not args.skip_single:
         W, single = single_leg(args, n)
         out.update(single)
+    c1 = None
+    c1_W = None
+    if not args.skip_c1:
+        log("[bench] n=1024 leg")
+        c1, c1_W = c1_leg(args.c1_reps)
     paper = None
     if not args.skip_single and not args.skip_paper_config:
         log("[bench] paper configuration leg (n=8192, float32 + predecessors)")
@@ -489,14 +636,16 @@ def main():
     serving = None
     if not args.skip_serving:
         log("[bench] serving leg")
-        serving = serving_leg(args.serving_requests)
+        serving = serving_leg(args.serving_requests, per_rate_s=args.serving_rate_seconds)
 
     cpu = None
     if not args.no_cpu_baseline and W is not None:
         log(f"[bench] cpu baseline ({args.cpu_seconds:.0f} s budget)")
-        cpu = cpu_baseline(W, args.cpu_seconds)
+        import synth
+        cpu = cpu_baseline(W, args.cpu_seconds, c1_W=c1_W, batch=None if args.skip_batched else synth.batch())
 
     out["cpu_baseline"] = cpu
+    out["c1_n1024"] = c1
     out["paper_config"] = paper
     out["batched"] = batched
     out["serving"] = serving

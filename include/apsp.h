@@ -253,14 +253,18 @@ typedef struct {
 apsp_status_t apsp_profile_begin(void);
 apsp_status_t apsp_profile_end(apsp_profile_t *out);
 
-/* Measures the device's 32-bit VALU throughput (lane-instructions per
- * second) with the instruction mix of the min-plus kernels (two float32
- * adds and one three-input float32 minimum per two relaxations, 8
- * independent accumulators per lane), every CU busy; synchronises the
- * device.  The benchmark reports kernel rates against this measured peak
- * beside the datasheet one (157.3 TFLOP/s float32 vector = 78.6e12 VALU
- * instructions per second). */
-apsp_status_t apsp_probe_valu(double *lane_instr_per_s, double *elapsed_ms);
+/* Measures one 32-bit VALU instruction rate of the device at its actual
+ * clock, in lane-instructions per second over the whole device (every CU
+ * busy, 8 wavefronts per SIMD, 8 independent accumulators per lane, a loop
+ * body of nothing but the measured instructions), in steady state (launches
+ * of N and 3N iterations, rate from the differences, best of three pairs).
+ *   kind 0  the float32 min-plus step of the phase-3 kernels: two v_add_f32
+ *           and one v_min3_f32 per two (i,j,k) relaxations
+ *   kind 1  v_add_f32      kind 2  v_min3_f32     kind 3  v_add_u32
+ *   kind 4  v_min_f32      kind 5  the int32 step: two v_add_u32, one v_min3_i32
+ * *elapsed_ms receives the duration of the longer launch.  Synchronises the
+ * device; allocates 16 bytes of device memory for the duration of the call. */
+apsp_status_t apsp_probe_valu(int32_t kind, double *lane_instr_per_s, double *elapsed_ms);
 
 /* Release the calling device's internal workspace and cached graphs.
  * Must not overlap with solves in flight on that device. */

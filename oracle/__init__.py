@@ -44,6 +44,15 @@ def build(verbose: bool = False, src: str = SRC_PATH, out: str = LIB_PATH) -> st
     return out
 
 
+def build_native(out_dir: str) -> str:
+    """The same source built for the host it runs on (gcc -O3 -march=native,
+    OpenMP over rows), for the benchmark's CPU baseline; tests use build()."""
+    out = os.path.join(out_dir, "liboracle_native.so")
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fPIC", "-shared", "-fopenmp", "-o", out,
+                           SRC_PATH, "-lm"])
+    return out
+
+
 def load(path: str = LIB_PATH):
     L = ctypes.CDLL(path)
     vp, i64, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int

@@ -118,7 +118,7 @@ def _bind_optional(L):
         "apsp_server_release": ([vp, u64], c_int),
         "apsp_server_stats": ([vp, vp], c_int),
         "apsp_server_destroy": ([vp], c_int),
-        "apsp_probe_valu": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], c_int),
+        "apsp_probe_valu": ([i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], c_int),
         "apsp_batch_plan_create_ex": ([vp, vp, i32, c_int, i32, vp, ctypes.POINTER(vp)], c_int),
         "apsp_batch_autotune": ([c_int, i32, i32, i32, ctypes.POINTER(ctypes.c_double)], c_int),
         "apsp_batch_autotune_sizes": ([vp, i32, c_int, i32, i32, ctypes.POINTER(ctypes.c_double)], c_int),
@@ -344,11 +344,15 @@ def profile_end() -> dict:
     return prof.as_dict()
 
 
-def probe_valu() -> dict:
-    """Measured 32-bit VALU lane-instructions per second (synchronises the device)."""
+PROBE_KINDS = ("mix_f32", "add_f32", "min3_f32", "add_u32", "min_f32", "mix_i32")
+
+
+def probe_valu(kind="mix_f32") -> dict:
+    """Measured VALU lane-instructions per second of one instruction kind
+    (see PROBE_KINDS and apsp_probe_valu; synchronises the device)."""
     r = ctypes.c_double()
     ms = ctypes.c_double()
-    st = lib().apsp_probe_valu(ctypes.byref(r), ctypes.byref(ms))
+    st = lib().apsp_probe_valu(PROBE_KINDS.index(kind), ctypes.byref(r), ctypes.byref(ms))
     if st != SUCCESS:
         raise APSPError(st, "apsp_probe_valu")
     return {"lane_instr_per_s": r.value, "elapsed_ms": ms.value}

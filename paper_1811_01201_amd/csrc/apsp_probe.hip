@@ -1,78 +1,146 @@
-// VALU throughput probe: the denominator the benchmark compares the
-// phase-3 kernel against, measured on the device at its actual clock.
+// VALU throughput probes: the instruction rates the min-plus kernels are
+// bound by, measured on the device at its actual clock.
 //
-// Every thread runs `iters` iterations of the phase-3 inner step on 8
-// independent accumulators: per accumulator two float32 adds of operands
-// that do not depend on it, then one three-input float32 minimum,
-// c = min3(c, a0 + b0, a1 + b1), i.e. two (i,j,k) relaxations per three
-// instructions, exactly the instruction mix of the min-plus kernels.  The
-// grid fills every CU with 8 wavefronts.
-// relaxations per second = threads * iters * 16 / elapsed.
+// Each probe kernel runs `iters` iterations of a loop body that holds
+// nothing but the measured VALU instructions (the loop counter is scalar):
+// 8 independent accumulators per lane, each visited 4 times per iteration.
+//   kind 0  float32 min-plus step: t0 = a0 + b0, t1 = a1 + b1,
+//           c = min3(c, t0, t1) -- the phase-3 inner loop, two (i,j,k)
+//           relaxations per three instructions
+//   kind 1  v_add_f32 alone (c = c + a)
+//   kind 2  v_min3_f32 alone (c = min3(c, a, b))
+//   kind 3  v_add_u32 alone
+//   kind 4  v_min_f32 alone
+//   kind 5  int32 min-plus step: two v_add_u32 and one v_min3_i32
+// The grid fills every CU with 8 wavefronts per SIMD.  The rate is taken in
+// steady state: two launches of N and 3N iterations, the difference of the
+// instructions issued divided by the difference of their durations, so the
+// launch and ramp-up cost cancel; the best of three such pairs is kept.
 #include <hip/hip_runtime.h>
 
 #include "apsp_internal.h"
 
 namespace apsp {
 
-#define APSP_PROBE_STEP(C, S0, S1)                 \
-    "v_add_f32_e32 " S0 ", %[a0], %[b0]\n\t"      \
-    "v_add_f32_e32 " S1 ", %[a1], %[b1]\n\t"      \
+namespace {
+
+constexpr int kRepeats = 4;  // visits of each of the 8 accumulators per iteration
+
+#define APSP_MIX_F32(C, S0, S1)                  \
+    "v_add_f32_e32 " S0 ", %[a0], %[b0]\n\t"     \
+    "v_add_f32_e32 " S1 ", %[a1], %[b1]\n\t"     \
     "v_min3_f32 " C ", " C ", " S0 ", " S1 "\n\t"
+#define APSP_MIX_I32(C, S0, S1)                  \
+    "v_add_u32_e32 " S0 ", %[a0], %[b0]\n\t"     \
+    "v_add_u32_e32 " S1 ", %[a1], %[b1]\n\t"     \
+    "v_min3_i32 " C ", " C ", " S0 ", " S1 "\n\t"
+#define APSP_ADD_F32(C, S0, S1) "v_add_f32_e32 " C ", " C ", %[a0]\n\t"
+#define APSP_MIN3_F32(C, S0, S1) "v_min3_f32 " C ", " C ", %[a0], %[a1]\n\t"
+#define APSP_ADD_U32(C, S0, S1) "v_add_u32_e32 " C ", " C ", %[a0]\n\t"
+#define APSP_MIN_F32(C, S0, S1) "v_min_f32_e32 " C ", " C ", %[a0]\n\t"
 
-__global__ void __launch_bounds__(256) valu_probe_kernel(int32_t *out, int iters, int32_t seed) {
-    float c0 = (float)(seed + (int)threadIdx.x), c1 = c0 + 1, c2 = c0 + 2, c3 = c0 + 3;
-    float c4 = c0 + 4, c5 = c0 + 5, c6 = c0 + 6, c7 = c0 + 7;
-    float a0 = (float)(seed ^ 0x55), a1 = (float)(seed ^ 0x33), b0 = (float)(seed + 7), b1 = (float)(seed - 9);
-    float t0, t1, t2, t3, t4, t5, t6, t7, t8, t9, t10, t11, t12, t13, t14, t15;
-    for (int i = 0; i < iters; ++i) {
-        asm volatile(APSP_PROBE_STEP("%[c0]", "%[t0]", "%[t1]") APSP_PROBE_STEP("%[c1]", "%[t2]", "%[t3]")
-                     APSP_PROBE_STEP("%[c2]", "%[t4]", "%[t5]") APSP_PROBE_STEP("%[c3]", "%[t6]", "%[t7]")
-                     APSP_PROBE_STEP("%[c4]", "%[t8]", "%[t9]") APSP_PROBE_STEP("%[c5]", "%[t10]", "%[t11]")
-                     APSP_PROBE_STEP("%[c6]", "%[t12]", "%[t13]")
-                     APSP_PROBE_STEP("%[c7]", "%[t14]", "%[t15]")
-                     : [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2), [c3] "+v"(c3), [c4] "+v"(c4),
-                       [c5] "+v"(c5), [c6] "+v"(c6), [c7] "+v"(c7), [t0] "=&v"(t0), [t1] "=&v"(t1),
-                       [t2] "=&v"(t2), [t3] "=&v"(t3), [t4] "=&v"(t4), [t5] "=&v"(t5), [t6] "=&v"(t6),
-                       [t7] "=&v"(t7), [t8] "=&v"(t8), [t9] "=&v"(t9), [t10] "=&v"(t10),
-                       [t11] "=&v"(t11), [t12] "=&v"(t12), [t13] "=&v"(t13), [t14] "=&v"(t14),
-                       [t15] "=&v"(t15)
-                     : [a0] "v"(a0), [a1] "v"(a1), [b0] "v"(b0), [b1] "v"(b1));
-        a0 += 1.0f;  // keeps the adds' operands changing between iterations
+#define APSP_EIGHT(OP)                                                                            \
+    OP("%[c0]", "%[t0]", "%[t1]") OP("%[c1]", "%[t2]", "%[t3]") OP("%[c2]", "%[t4]", "%[t5]")     \
+    OP("%[c3]", "%[t6]", "%[t7]") OP("%[c4]", "%[t8]", "%[t9]") OP("%[c5]", "%[t10]", "%[t11]")   \
+    OP("%[c6]", "%[t12]", "%[t13]") OP("%[c7]", "%[t14]", "%[t15]")
+
+// One kernel per kind; the asm block's outputs are all used (the
+// accumulators are reduced at the end, the temporaries are early-clobber
+// scratch registers written and read inside the block).
+#define APSP_PROBE_KERNEL(NAME, OP)                                                                \
+    __global__ void __launch_bounds__(256) NAME(int32_t *out, int iters, int32_t seed) {            \
+        float c0 = (float)(seed + (int)threadIdx.x), c1 = c0 + 1, c2 = c0 + 2, c3 = c0 + 3;        \
+        float c4 = c0 + 4, c5 = c0 + 5, c6 = c0 + 6, c7 = c0 + 7;                                  \
+        const float a0 = (float)(seed ^ 0x55), a1 = (float)(seed ^ 0x33), b0 = (float)(seed + 7),  \
+                    b1 = (float)(seed - 9);                                                        \
+        float t0, t1, t2, t3, t4, t5, t6, t7, t8, t9, t10, t11, t12, t13, t14, t15;                \
+        for (int i = 0; i < iters; ++i) {                                                          \
+            asm volatile(APSP_EIGHT(OP) APSP_EIGHT(OP) APSP_EIGHT(OP) APSP_EIGHT(OP)               \
+                         : [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2), [c3] "+v"(c3),             \
+                           [c4] "+v"(c4), [c5] "+v"(c5), [c6] "+v"(c6), [c7] "+v"(c7),             \
+                           [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3),         \
+                           [t4] "=&v"(t4), [t5] "=&v"(t5), [t6] "=&v"(t6), [t7] "=&v"(t7),         \
+                           [t8] "=&v"(t8), [t9] "=&v"(t9), [t10] "=&v"(t10), [t11] "=&v"(t11),     \
+                           [t12] "=&v"(t12), [t13] "=&v"(t13), [t14] "=&v"(t14), [t15] "=&v"(t15)  \
+                         : [a0] "v"(a0), [a1] "v"(a1), [b0] "v"(b0), [b1] "v"(b1));                \
+        }                                                                                          \
+        const float r = c0 + c1 + c2 + c3 + c4 + c5 + c6 + c7;                                     \
+        if (r == 12345.25f) out[0] = 1; /* keeps the chains live; practically never taken */       \
     }
-    const float r = c0 + c1 + c2 + c3 + c4 + c5 + c6 + c7;
-    if (r == 12345.25f) out[0] = 1;  // keeps the chains live; practically never taken
-}
 
-#undef APSP_PROBE_STEP
+APSP_PROBE_KERNEL(probe_mix_f32_kernel, APSP_MIX_F32)
+APSP_PROBE_KERNEL(probe_add_f32_kernel, APSP_ADD_F32)
+APSP_PROBE_KERNEL(probe_min3_f32_kernel, APSP_MIN3_F32)
+APSP_PROBE_KERNEL(probe_add_u32_kernel, APSP_ADD_U32)
+APSP_PROBE_KERNEL(probe_min_f32_kernel, APSP_MIN_F32)
+APSP_PROBE_KERNEL(probe_mix_i32_kernel, APSP_MIX_I32)
+
+#undef APSP_PROBE_KERNEL
+#undef APSP_EIGHT
+#undef APSP_MIX_F32
+#undef APSP_MIX_I32
+#undef APSP_ADD_F32
+#undef APSP_MIN3_F32
+#undef APSP_ADD_U32
+#undef APSP_MIN_F32
+
+using ProbeKernel = void (*)(int32_t *, int, int32_t);
+constexpr ProbeKernel kProbes[6] = {probe_mix_f32_kernel, probe_add_f32_kernel, probe_min3_f32_kernel,
+                                    probe_add_u32_kernel, probe_min_f32_kernel, probe_mix_i32_kernel};
+// VALU instructions per lane and iteration
+constexpr int kInstrPerIter[6] = {8 * 3 * kRepeats, 8 * kRepeats, 8 * kRepeats,
+                                  8 * kRepeats,     8 * kRepeats, 8 * 3 * kRepeats};
+
+}  // namespace
 
 }  // namespace apsp
 
 using namespace apsp;
 
-extern "C" apsp_status_t apsp_probe_valu(double *lane_instr_per_s, double *elapsed_ms) {
-    if (!lane_instr_per_s) return APSP_ERROR_INVALID_ARGUMENT;
+extern "C" apsp_status_t apsp_probe_valu(int32_t kind, double *lane_instr_per_s, double *elapsed_ms) {
+    if (!lane_instr_per_s || kind < 0 || kind >= 6) return APSP_ERROR_INVALID_ARGUMENT;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return APSP_ERROR_HIP;
     int32_t *out = nullptr;
-    hipEvent_t e0, e1;
+    hipEvent_t ev[4] = {};
     if (hipMalloc(&out, 16) != hipSuccess) return APSP_ERROR_OUT_OF_MEMORY;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
-    const int blocks = cus * 8, threads = 256, iters = 20000;
-    hipLaunchKernelGGL(valu_probe_kernel, dim3(blocks), dim3(threads), 0, nullptr, out, 100, 3);  // warm-up
-    hipEventRecord(e0, nullptr);
-    hipLaunchKernelGGL(valu_probe_kernel, dim3(blocks), dim3(threads), 0, nullptr, out, iters, 3);
-    hipEventRecord(e1, nullptr);
-    hipError_t e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(out);
-    if (e != hipSuccess || ms <= 0.f) return APSP_ERROR_HIP;
-    *lane_instr_per_s = (double)blocks * threads * iters * 24.0 / (ms * 1e-3);
-    if (elapsed_ms) *elapsed_ms = ms;
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < 4 && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
+    // 8 workgroups of 256 threads per CU = 8 wavefronts per SIMD
+    const int blocks = cus * 8, threads = 256, iters = 4000;
+    const ProbeKernel k = kProbes[kind];
+    double best = 0.0, best_ms = 0.0;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), 0, nullptr, out, 100, 3);  // warm-up
+        e = hipGetLastError();
+    }
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(ev[0], nullptr);
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), 0, nullptr, out, iters, 3);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], nullptr);
+        if (e == hipSuccess) e = hipEventRecord(ev[2], nullptr);
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), 0, nullptr, out, 3 * iters, 3);
+        if (e == hipSuccess) e = hipEventRecord(ev[3], nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+        float t1 = 0.f, t3 = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t1, ev[0], ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t3, ev[2], ev[3]);
+        if (e == hipSuccess && t3 > t1) {
+            const double instr = (double)blocks * threads * (2.0 * iters) * kInstrPerIter[kind];
+            const double rate = instr / ((double)(t3 - t1) * 1e-3);
+            if (rate > best) {
+                best = rate;
+                best_ms = t3;
+            }
+        }
+    }
+    for (auto x : ev)
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFree(out);
+    if (e != hipSuccess || best <= 0.0) return APSP_ERROR_HIP;
+    *lane_instr_per_s = best;
+    if (elapsed_ms) *elapsed_ms = best_ms;
     return APSP_SUCCESS;
 }
