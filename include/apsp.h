@@ -351,7 +351,12 @@ apsp_status_t apsp_batch_plan_destroy(apsp_batch_plan_t *plan);
  * (n > 64) forced: team_config[b] = 0 wavefront-private 64 x 64 tiles with
  * 8 x 8 registers per lane, 1 workgroup 64 x 64 tiles with 4 x 4 per thread,
  * 2 workgroup 128 x 128 tiles with 8 x 8 per thread and 128-wide k-blocks,
- * -1 = the tuning table's choice for the graph's size class.  NULL = all -1. */
+ * 3 (distances) the work matrix padded to 64 only, 128-wide k-blocks with a
+ * 64-wide last block and tiles of 128 or 64 rows by 128 or 64 columns,
+ * -1 = the tuning table's choice for the graph's size class.  NULL = all -1.
+ * A distance batch whose graphs above 64 vertices all have configuration 1
+ * or 3 runs in a kernel that holds only those two (and the n <= 64 path):
+ * one launch, no register spills.  Otherwise configuration 3 runs as 2. */
 apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offsets, int32_t batch,
                                         apsp_dtype_t dtype, int32_t want_pred, const int8_t *team_config,
                                         apsp_batch_plan_t **out_plan);
@@ -359,7 +364,8 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
 /* ------------------------------------------------------------- autotuning
  *
  * The batched launch picks a team configuration (tile size and per-thread
- * register block, see apsp_batch_plan_create_ex) per graph from a table
+ * register block, see apsp_batch_plan_create_ex; 3 for distances by default)
+ * per graph from a table
  * indexed by (dtype, predecessors, size class), 8 size classes n in
  * (64,128], (128,192], (192,256], (256,320], (320,384], (384,448],
  * (448,512], (512,1024].  The table starts from
@@ -369,8 +375,8 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
  * graphs_per_class graphs in every size class (0 = CU count) and, class by
  * class (coordinate descent, the other classes at their current choice),
  * times the whole batch with each configuration for that class (reps timed
- * executions, 0 = 3) and keeps the fastest.  ms_out[class * 3 + config]
- * (24 doubles)
+ * executions, 0 = 3) and keeps the fastest (configuration 3 only for
+ * distances).  ms_out[class * 4 + config] (32 doubles; 0 where not timed)
  * (when not NULL) receives the per-execution milliseconds of each trial.
  * It allocates device memory and synchronises its own stream.
  */
@@ -381,7 +387,8 @@ apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t
  * actually has, in its own mix.  Classes without graphs keep their entry. */
 apsp_status_t apsp_batch_autotune_sizes(const int32_t *ns, int32_t batch, apsp_dtype_t dtype,
                                         int32_t want_pred, int32_t reps, double *ms_out);
-/* Team configuration the table gives a graph of n vertices (-1: n <= 64, one wavefront). */
+/* Team configuration the table gives a graph of n vertices (-1: n <= 64, one wavefront; 0..3 as
+ * for apsp_batch_plan_create_ex). */
 int32_t apsp_batch_config(int64_t n, apsp_dtype_t dtype, int32_t want_pred);
 apsp_status_t apsp_tune_save(const char *path);
 apsp_status_t apsp_tune_load(const char *path);

@@ -539,7 +539,7 @@ class Server:
         self.destroy()
 
 
-TEAM_CONFIGS = ("wave_tiles_64", "group_tiles_64", "group_tiles_128")
+TEAM_CONFIGS = ("wave_tiles_64", "group_tiles_64", "group_tiles_128", "mixed_128")
 SIZE_CLASSES = (128, 192, 256, 320, 384, 448, 512, 1024)
 
 
@@ -549,7 +549,7 @@ def batch_autotune(dtype="int32", want_pred=False, graphs_per_class=0, reps=0, n
     sizes of the intended workload) the synthetic batch has exactly those
     sizes.  Returns {class_upper_bound: {config_name: ms, ..., "best": name}}
     (ms 0 for classes that were not timed)."""
-    ms = (ctypes.c_double * (len(SIZE_CLASSES) * 3))()
+    ms = (ctypes.c_double * (len(SIZE_CLASSES) * len(TEAM_CONFIGS)))()
     dt = INT32 if dtype in ("int32", INT32) else FLOAT32
     if ns is None:
         st = lib().apsp_batch_autotune(dt, int(want_pred), int(graphs_per_class), int(reps), ms)
@@ -561,7 +561,7 @@ def batch_autotune(dtype="int32", want_pred=False, graphs_per_class=0, reps=0, n
         raise APSPError(st, "apsp_batch_autotune")
     out = {}
     for c, hi in enumerate(SIZE_CLASSES):
-        row = {TEAM_CONFIGS[k]: ms[c * 3 + k] for k in range(3)}
+        row = {TEAM_CONFIGS[k]: ms[c * len(TEAM_CONFIGS) + k] for k in range(len(TEAM_CONFIGS))}
         row["best"] = TEAM_CONFIGS[lib().apsp_batch_config(hi, dt, int(want_pred))]
         out[hi] = row
     return out

@@ -42,7 +42,7 @@ struct BatchMeta {
 
 constexpr int kBatchBS = 64;
 constexpr int kBatchThreads = 256;
-enum TeamCfg { kWaveTiles64 = 0, kGroupTiles64 = 1, kGroupTiles128 = 2 };
+enum TeamCfg { kWaveTiles64 = 0, kGroupTiles64 = 1, kGroupTiles128 = 2, kMixed128 = 3 };
 
 // ------------------------------------------------ input/output conversion
 template <class Ar, class Tin>
@@ -301,7 +301,7 @@ __device__ void team_dispatch(int cfg, const Ar &ar, Tin *__restrict__ dist, int
 // n <= 64: the whole graph in one wavefront's registers (8 x 8 per lane).
 // CHECK as for team_solve.
 template <class Ar, class Tin, bool CHECK = false>
-__device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__restrict__ pred,
+__device__ __forceinline__ bool wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__restrict__ pred,
                            int32_t *__restrict__ status, int g, int64_t n, int64_t off,
                            typename Ar::T (*colbuf)[kBatchBS], typename Ar::T (*rowbuf)[kBatchBS]) {
     using T = typename Ar::T;
@@ -322,7 +322,7 @@ __device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
             c[m][q] = to_work(ar, w, inside, i, j);
         }
     if constexpr (CHECK) {
-        if (__any(ruled_out)) return;  // uniform over the wavefront
+        if (__any(ruled_out)) return false;  // uniform over the wavefront
     }
     const int ksteps = (int)((n + 15) / 16 * 16);  // vertices >= n are isolated
     phase1_steps<Ar, kBatchBS, true>(c, ksteps, ar, colbuf, rowbuf);
@@ -338,6 +338,7 @@ __device__ void wave_solve(const Ar &ar0, Tin *__restrict__ dist, int32_t *__res
         }
     neg = __any(neg);
     if (status && lane == 0) status[g] = neg ? APSP_ERROR_NEGATIVE_CYCLE : APSP_SUCCESS;
+    return true;
 }
 
 // Whether any weight of a graph (count elements from a 16-byte-aligned g)
@@ -473,6 +474,255 @@ batched_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ pre
     }
 }
 
+
+// ------------------------------------------------------ lean distance launch
+// Distance batches whose graphs above 64 vertices all take the padded-to-64
+// team path below run in a kernel that holds nothing else (plus the
+// one-wavefront path for n <= 64), so its register budget is that of one
+// 128 x 128 tile product: no scratch spills and three workgroups per CU.
+//
+// kMixed128: the work matrix is padded to a multiple of 64 (not 128); the
+// k-blocks are 128 wide except the last, which is 64 wide when the padded
+// order is an odd multiple of 64, and the C tiles follow the blocks, so a
+// tile is 128 or 64 rows by 128 or 64 columns.  Every tile is one
+// workgroup product with the A and B chunks brought into LDS by DMA.  In
+// the last round the k-range stops at n rounded up to 32 (the vertices
+// beyond n are isolated padding).  kGroupTiles64 runs the same code with
+// 64-wide blocks only.  Both arithmetics of an int32 batch are in the
+// kernel: the graph is copied in as float32 while its weights are checked,
+// and copied again and solved in int32 when a weight rules float32 out.
+template <class Ar>
+using LT11 = TileProductDMA<Ar, 128, 128, 16, 8, 8>;
+template <class Ar>
+using LT10 = TileProductDMA<Ar, 128, 64, 16, 8, 4>;
+template <class Ar>
+using LT01 = TileProductDMA<Ar, 64, 128, 16, 4, 8>;
+template <class Ar>
+using LT00 = TileProductDMA<Ar, 64, 64, 16, 4, 4>;
+
+// LDS of the lean kernel: four distinct chunk buffers shared by every tile
+// shape (distinct arrays, so the compiler keeps a chunk copy in flight
+// while the other buffer is read), the phase-1 publications and the
+// one-wavefront path's buffers.
+constexpr int kLeanChunk = 128 * 16;  // elements of the largest A or B chunk
+template <class T>
+struct LeanLds {
+    T *a0, *a1, *b0, *b1;
+    T *p1;    // 8 x 128: 4 column + 4 row publications
+    T *wave;  // 4 wavefronts x 8 x 64
+};
+
+// C (h x w at crow, ccol) <- min(C, A (h x kc at crow, k0) (x) B (kc x w at k0, ccol)); h, w in {64, 128}
+template <class Ar>
+__device__ __forceinline__ void lean_tile(const LeanLds<typename Ar::T> &sm, typename Ar::T *X, int64_t ldp,
+                                          int64_t crow, int64_t ccol, int h, int w, int64_t k0, int kc,
+                                          const Ar &ar) {
+    if (h == 128) {
+        if (w == 128)
+            LT11<Ar>::run_in(sm.a0, sm.a1, sm.b0, sm.b1, X, ldp, crow, ccol, k0, kc, ar);
+        else
+            LT10<Ar>::run_in(sm.a0, sm.a1, sm.b0, sm.b1, X, ldp, crow, ccol, k0, kc, ar);
+    } else {
+        if (w == 128)
+            LT01<Ar>::run_in(sm.a0, sm.a1, sm.b0, sm.b1, X, ldp, crow, ccol, k0, kc, ar);
+        else
+            LT00<Ar>::run_in(sm.a0, sm.a1, sm.b0, sm.b1, X, ldp, crow, ccol, k0, kc, ar);
+    }
+}
+
+// Copies graph (n x n at src, leading dimension n) into X (ldp x ldp) in the
+// policy's form, padding vertices isolated; CHECK: returns, uniformly over
+// the workgroup, whether a weight rules float32 arithmetic out.
+template <class Ar, class Tin, bool CHECK>
+__device__ __forceinline__ bool lean_copy_in(const Ar &ar, const Tin *__restrict__ src, int n, int ldp,
+                                             typename Ar::T *__restrict__ X) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool ruled_out = false;
+    const uint32_t lim = f32_limit(n);
+    // one row per wavefront at a time, all of its loads issued before the
+    // first is used (a row has at most 16 64-wide pieces)
+    for (int i = wave; i < ldp; i += kBatchThreads / 64) {
+        for (int j0 = 0; j0 < ldp; j0 += 8 * 64) {
+            Tin w[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = j0 + t * 64 + lane;
+                w[t] = (i < n && j < n) ? src[(uint32_t)i * (uint32_t)n + (uint32_t)j] : Tin(0);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = j0 + t * 64 + lane;
+                const bool inside = i < n && j < n;
+                if constexpr (CHECK) ruled_out |= inside & f32_ruled_out(w[t], lim);
+                if (j < ldp) X[(uint32_t)i * (uint32_t)ldp + (uint32_t)j] = to_work(ar, w[t], inside, i, j);
+            }
+        }
+    }
+    if constexpr (CHECK) return __syncthreads_or(ruled_out);
+    __syncthreads();
+    return false;
+}
+
+// The rounds of one graph on X (ldp x ldp, ldp a multiple of 64); BMAX is
+// the block width (128: kMixed128, 64: kGroupTiles64).
+template <class Ar, int BMAX>
+__device__ __forceinline__ void lean_rounds(const Ar &ar, typename Ar::T *__restrict__ X, int n, int ldp,
+                                            const LeanLds<typename Ar::T> &sm) {
+    using T = typename Ar::T;
+    const int R = (ldp + BMAX - 1) / BMAX;
+    auto width = [&](int q) { return min(BMAX, ldp - q * BMAX); };
+    for (int r = 0; r < R; ++r) {
+        const int r0 = r * BMAX, wr = width(r);
+        // the last block's k-range stops at n, rounded up to 32 (whole pairs
+        // of 16-wide chunks): the vertices beyond n are isolated padding
+        const int kc = r + 1 < R ? wr : min(wr, (n - r0 + 31) / 32 * 32);
+        if (BMAX == 128 && wr == 128)
+            phase1_body<Ar, 128, false, 8>(X, ldp, r0, ar, reinterpret_cast<T(*)[128]>(sm.p1),
+                                           reinterpret_cast<T(*)[128]>(sm.p1) + 4, kc);
+        else
+            phase1_body<Ar, 64, false, 4>(X, ldp, r0, ar, reinterpret_cast<T(*)[64]>(sm.p1),
+                                          reinterpret_cast<T(*)[64]>(sm.p1) + 4, kc);
+        __syncthreads();
+        // phase 2: block row r against the closed diagonal block (A = that
+        // block, B = the tile itself) and block column r (A = the tile
+        // itself, B = the block); each tile spans the whole block in the
+        // direction it reads from itself
+        for (int q = 0; q < R; ++q) {
+            if (q == r) continue;
+            const int wq = width(q);
+            lean_tile<Ar>(sm, X, ldp, r0, (int64_t)q * BMAX, wr, wq, r0, kc, ar);
+            lean_tile<Ar>(sm, X, ldp, (int64_t)q * BMAX, r0, wq, wr, r0, kc, ar);
+        }
+        __syncthreads();
+        // phase 3: every other tile from its row's and column's panel tiles
+        for (int p = 0; p < R; ++p) {
+            if (p == r) continue;
+            for (int q = 0; q < R; ++q) {
+                if (q == r) continue;
+                lean_tile<Ar>(sm, X, ldp, (int64_t)p * BMAX, (int64_t)q * BMAX, width(p), width(q), r0, kc, ar);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Writes graph g's result from X, and its status.
+template <class Ar, class Tin>
+__device__ __forceinline__ void lean_copy_out(const Ar &ar, const typename Ar::T *__restrict__ X, int n, int ldp,
+                                              Tin *__restrict__ dst, int32_t *__restrict__ status, int g) {
+    using T = typename Ar::T;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool neg = false;
+    for (int i = wave; i < n; i += kBatchThreads / 64) {
+        for (int j0 = 0; j0 < n; j0 += 8 * 64) {
+            T v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = j0 + t * 64 + lane;
+                v[t] = j < n ? X[(uint32_t)i * (uint32_t)ldp + (uint32_t)j] : T(0);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = j0 + t * 64 + lane;
+                if (j < n)
+                    neg |= from_work(ar, v[t], i, j, dst + ((uint32_t)i * (uint32_t)n + (uint32_t)j),
+                                     (int32_t *)nullptr);
+            }
+        }
+    }
+    neg = __syncthreads_or(neg);
+    if (status && threadIdx.x == 0) status[g] = neg ? APSP_ERROR_NEGATIVE_CYCLE : APSP_SUCCESS;
+    __syncthreads();
+}
+
+// One team graph: Ar first (checked against Alt's rule when Alt is not
+// NoAlt), Alt when a weight rules Ar out.
+template <class Tin, class Ar, class Alt, int BMAX>
+__device__ __forceinline__ void lean_team(const Ar &ar, const Alt &alt, Tin *__restrict__ dist,
+                                          int32_t *__restrict__ status, int g, int n, int64_t off, void *scratch,
+                                          const LeanLds<typename Ar::T> &sm) {
+    constexpr bool kDual = !std::is_same_v<Alt, NoAlt>;
+    const int ldp = (n + 63) / 64 * 64;
+    Tin *const src = dist + off;
+    typename Ar::T *const X = (typename Ar::T *)scratch;
+    if (!lean_copy_in<Ar, Tin, kDual>(ar, src, n, ldp, X)) {
+        lean_rounds<Ar, BMAX>(ar, X, n, ldp, sm);
+        lean_copy_out<Ar, Tin>(ar, X, n, ldp, src, status, g);
+        return;
+    }
+    if constexpr (kDual) {
+        static_assert(sizeof(typename Alt::T) == sizeof(typename Ar::T), "one work-matrix layout");
+        using TA = typename Alt::T;
+        typename Alt::T *const Y = (TA *)scratch;
+        const LeanLds<TA> sa{(TA *)sm.a0, (TA *)sm.a1, (TA *)sm.b0, (TA *)sm.b1, (TA *)sm.p1, (TA *)sm.wave};
+        lean_copy_in<Alt, Tin, false>(alt, src, n, ldp, Y);
+        lean_rounds<Alt, BMAX>(alt, Y, n, ldp, sa);
+        lean_copy_out<Alt, Tin>(alt, Y, n, ldp, src, status, g);
+    }
+}
+
+// counters[0]: next team graph, [1]: next wavefront graph, [2]: finished
+// workgroups (the last one resets all three).  Distances only.
+template <class Tin, class Ar, class Alt>
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(3)))
+batched_lean_kernel(BatchMeta meta, Tin *__restrict__ dist, int32_t *__restrict__ status,
+                    void *__restrict__ scratch, int32_t *__restrict__ counters, Ar ar, Alt alt) {
+    static_assert(sizeof(typename Ar::T) == 4, "distance policies");
+    constexpr bool kDual = !std::is_same_v<Alt, NoAlt>;
+    using TR = typename Ar::T;
+    __shared__ alignas(16) TR la0[kLeanChunk];
+    __shared__ alignas(16) TR la1[kLeanChunk];
+    __shared__ alignas(16) TR lb0[kLeanChunk];
+    __shared__ alignas(16) TR lb1[kLeanChunk];
+    __shared__ alignas(16) TR lp1[8 * 128];
+    __shared__ alignas(16) TR lwave[4 * 8 * kBatchBS];
+    const LeanLds<TR> sm{la0, la1, lb0, lb1, lp1, lwave};
+    __shared__ int s_q;
+    const int tid = threadIdx.x;
+    void *const my_scratch = (char *)scratch + (int64_t)blockIdx.x * meta.scratch_elems * 4;
+    for (;;) {
+        if (tid == 0) s_q = atomicAdd(&counters[0], 1);
+        __syncthreads();
+        const int q = s_q;
+        __syncthreads();
+        if (q >= meta.n_team) break;
+        const int g = meta.order[q];
+        const int n = meta.ns[g];
+        const int64_t off = meta.offsets[g];
+        if (meta.cfg[g] == kGroupTiles64)
+            lean_team<Tin, Ar, Alt, 64>(ar, alt, dist, status, g, n, off, my_scratch, sm);
+        else
+            lean_team<Tin, Ar, Alt, 128>(ar, alt, dist, status, g, n, off, my_scratch, sm);
+    }
+    // small graphs: every wavefront on its own
+    const int wave = tid >> 6, lane = tid & 63;
+    for (;;) {
+        int q = 0;
+        if (lane == 0) q = atomicAdd(&counters[1], 1);
+        q = __shfl(q, 0) + meta.n_team;
+        if (q >= meta.batch) break;
+        const int g = meta.order[q];
+        const int64_t n = meta.ns[g], off = meta.offsets[g];
+        TR(*buf)[kBatchBS] = reinterpret_cast<TR(*)[kBatchBS]>(lwave + wave * 8 * kBatchBS);
+        if (wave_solve<Ar, Tin, kDual>(ar, dist, nullptr, status, g, n, off, buf, buf + 4)) continue;
+        if constexpr (kDual) {
+            using TA = typename Alt::T;
+            TA(*abuf)[kBatchBS] = reinterpret_cast<TA(*)[kBatchBS]>(lwave + wave * 8 * kBatchBS);
+            wave_solve<Alt, Tin>(alt, dist, nullptr, status, g, n, off, abuf, abuf + 4);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(&counters[2], 1) == (int)gridDim.x - 1) {
+            counters[0] = 0;
+            counters[1] = 0;
+            counters[2] = 0;
+            __threadfence();
+        }
+    }
+}
+
 }  // namespace apsp
 
 // --------------------------------------------------------------- plans
@@ -486,6 +736,7 @@ struct apsp_batch_plan {
     int32_t n_team = 0;
     int grid = 0;
     int64_t scratch_elems = 0;
+    bool lean = false;         // the lean distance kernel (see batch_meta)
     int64_t max_end = 0;       // elements the packed buffers must hold
     void *dev_meta = nullptr;  // order | ns | offsets
     void *scratch = nullptr;
@@ -545,13 +796,55 @@ apsp_status_t launch(const BatchLaunch &L, void *dist, int32_t *pred, int32_t *s
     return APSP_SUCCESS;
 }
 
+template <class Tin, class Ar, class Alt>
+apsp_status_t launch_lean(const BatchLaunch &L, void *dist, int32_t *status, hipStream_t s, Ar ar, Alt alt,
+                          int32_t *counters) {
+    BatchMeta m;
+    m.order = (const int32_t *)L.meta;
+    m.ns = m.order + L.batch;
+    m.offsets = (const int64_t *)((const char *)L.meta + (size_t)L.batch * 8);
+    m.cfg = (const int8_t *)((const char *)L.meta + (size_t)L.batch * 16);
+    m.batch = L.batch;
+    m.n_team = L.n_team;
+    m.scratch_elems = L.scratch_elems;
+    hipLaunchKernelGGL((batched_lean_kernel<Tin, Ar, Alt>), dim3(L.grid), dim3(kBatchThreads), 0, s, m,
+                       (Tin *)dist, status, L.scratch, counters, ar, alt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        t_last_hip = (int)e;
+        return APSP_ERROR_HIP;
+    }
+    return APSP_SUCCESS;
+}
+
 }  // namespace
 
 namespace apsp {
 
+// Workgroups of a batched launch resident on one CU (the plan's grid is
+// CUs times this).
+int batched_blocks_per_cu(apsp_dtype_t dtype, bool lean) {
+    int blocks = 0;
+    hipError_t e = hipSuccess;
+    if (lean && dtype == APSP_INT32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_lean_kernel<int32_t, ArF32, ArI32>,
+                                                         kBatchThreads, 0);
+    else if (lean)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batched_lean_kernel<float, ArF32, NoAlt>,
+                                                         kBatchThreads, 0);
+    else
+        return 2;
+    return (e == hipSuccess && blocks > 0) ? blocks : 2;
+}
+
 apsp_status_t batched_launch(const BatchLaunch &L, apsp_dtype_t dtype, bool want_pred, void *dist,
                              int32_t *pred, int32_t *status, hipStream_t s) {
     if (L.batch == 0) return APSP_SUCCESS;
+    if (L.lean) {  // distances; one launch with both arithmetics for int32 weights
+        if (dtype == APSP_INT32)
+            return launch_lean<int32_t>(L, dist, status, s, ArF32{}, ArI32{}, L.counters);
+        return launch_lean<float>(L, dist, status, s, ArF32{}, NoAlt{}, L.counters);
+    }
     if (dtype == APSP_INT32) {
         if (want_pred) return launch<int32_t>(L, dist, pred, status, s, ArKey{7}, NoAlt{}, L.counters);
         // int32 arithmetic for the graphs that need it, then float32 for the
@@ -577,21 +870,19 @@ void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, 
 // ------------------------------------------------------- tuning table
 // Team configuration per (dtype, predecessors, size class); size classes
 // are n in (64,128], (128,192], ..., (448,512] (64 wide, so a class pads
-// its graphs to one multiple of 64) and (512,1024].  Distance defaults
-// (measured on MI355X, graphs of one size per batch): 128 x 128 group tiles
-// where the 64-padded size is a multiple of 128 (their padding is then no
-// larger and they run 9-14 % faster: n = 256, 384, 512), wavefront tiles
-// elsewhere above 128, 64 x 64 group tiles up to 128.  8-byte keys keep
-// the 64-wide configurations.
+// its graphs to one multiple of 64) and (512,1024].  Distances default to
+// kMixed128 (the lean kernel: padding to 64, 128-wide blocks, no spills);
+// 8-byte keys keep the 64-wide configurations of the general kernel.
 constexpr int kClasses = 8;
 constexpr int kClassHi[kClasses] = {128, 192, 256, 320, 384, 448, 512, 1024};
 std::mutex g_tune_mu;
 constexpr int8_t kW = kWaveTiles64, kG = kGroupTiles64, kG2 = kGroupTiles128;
+constexpr int8_t kM = kMixed128;
 int8_t g_tune[2][2][kClasses] = {
     // int32: distances, predecessors
-    {{kG, kW, kG2, kW, kG2, kW, kG2, kW}, {kG, kG, kG, kW, kW, kW, kW, kW}},
+    {{kM, kM, kM, kM, kM, kM, kM, kM}, {kG, kG, kG, kW, kW, kW, kW, kW}},
     // float32
-    {{kG, kW, kG2, kW, kG2, kW, kG2, kW}, {kG, kG, kG, kW, kW, kW, kW, kW}}};
+    {{kM, kM, kM, kM, kM, kM, kM, kM}, {kG, kG, kG, kW, kW, kW, kW, kW}}};
 bool g_tune_env_checked = false;
 
 int size_class(int64_t n) {
@@ -615,7 +906,7 @@ int8_t batch_config(int64_t n, apsp_dtype_t dtype, bool pred) {
 
 // JSON form of the table:
 //   {"version": 2, "classes": [128, 192, 256, 320, 384, 448, 512, 1024],
-//    "configs": ["wave_tiles_64", "group_tiles_64", "group_tiles_128"],
+//    "configs": ["wave_tiles_64", "group_tiles_64", "group_tiles_128", "mixed_128"],
 //    "table": {"int32": {"dist": [c0..c7], "pred": [..]}, "float32": {...}}}
 apsp_status_t tune_load_locked(const char *path) {
     FILE *f = std::fopen(path, "rb");
@@ -639,7 +930,7 @@ apsp_status_t tune_load_locked(const char *path) {
             for (int c = 0; c < kClasses; ++c) {
                 char *end = nullptr;
                 const long v = std::strtol(q, &end, 10);
-                if (end == q || v < kWaveTiles64 || v > kGroupTiles128) return APSP_ERROR_INVALID_VALUE;
+                if (end == q || v < kWaveTiles64 || v > kMixed128) return APSP_ERROR_INVALID_VALUE;
                 t[d][m][c] = (int8_t)v;
                 q = end;
                 while (*q == ' ' || *q == ',' || *q == '\n') ++q;
@@ -656,7 +947,7 @@ apsp_status_t tune_save_locked(const char *path) {
     std::fprintf(f, "{\"version\": 2, \"classes\": [");
     for (int c = 0; c < kClasses; ++c) std::fprintf(f, "%s%d", c ? ", " : "", kClassHi[c]);
     std::fprintf(f, "],\n");
-    std::fprintf(f, " \"configs\": [\"wave_tiles_64\", \"group_tiles_64\", \"group_tiles_128\"],\n");
+    std::fprintf(f, " \"configs\": [\"wave_tiles_64\", \"group_tiles_64\", \"group_tiles_128\", \"mixed_128\"],\n");
     std::fprintf(f, " \"table\": {");
     const char *dts[2] = {"int32", "float32"};
     for (int d = 0; d < 2; ++d) {
@@ -703,8 +994,15 @@ __global__ void tune_fill_kernel(T *buf, const int64_t *offs, const int32_t *ns,
 //   order[B] int32 | ns[B] int32 | offsets[B] int64 | cfg[B] int8
 // with the team configuration of every graph (forced or from the table),
 // and the work-matrix elements one workgroup needs.
+//
+// lean (out): the batch runs in the lean distance kernel, which takes the
+// graphs above 64 vertices when every one of them has configuration
+// kMixed128 or kGroupTiles64 (work matrices padded to 64) and there are no
+// predecessors; otherwise the general kernel runs, which solves kMixed128
+// graphs as kGroupTiles128 (padded to 128).
 void batch_meta(const int32_t *ns, const int64_t *offsets, int32_t B, apsp_dtype_t dtype, bool pred,
-                const int8_t *forced, std::vector<char> &bytes, int32_t &n_team, int64_t &scratch_elems) {
+                const int8_t *forced, std::vector<char> &bytes, int32_t &n_team, int64_t &scratch_elems,
+                bool &lean) {
     std::vector<int32_t> order;
     batch_order(ns, B, order, n_team);
     bytes.assign(std::max<size_t>((size_t)B * 17 + 16, 32), 0);
@@ -712,12 +1010,17 @@ void batch_meta(const int32_t *ns, const int64_t *offsets, int32_t B, apsp_dtype
     std::copy(ns, ns + B, (int32_t *)bytes.data() + B);
     std::copy(offsets, offsets + B, (int64_t *)(bytes.data() + (size_t)B * 8));
     int8_t *cfg = (int8_t *)(bytes.data() + (size_t)B * 16);
+    lean = !pred;
+    for (int32_t b = 0; b < B; ++b) {
+        const int8_t c = forced && forced[b] >= 0 ? forced[b] : batch_config(ns[b], dtype, pred);
+        cfg[b] = c;
+        if (ns[b] > kBatchBS && c != kMixed128 && c != kGroupTiles64) lean = false;
+    }
     scratch_elems = 0;
     for (int32_t b = 0; b < B; ++b) {
-        int8_t c = forced && forced[b] >= 0 ? forced[b] : batch_config(ns[b], dtype, pred);
-        cfg[b] = c;
+        if (!lean && cfg[b] == kMixed128) cfg[b] = kGroupTiles128;
         if (ns[b] > kBatchBS) {
-            const int64_t bs = team_bs(c), ldp = (ns[b] + bs - 1) / bs * bs;
+            const int64_t bs = lean ? 64 : team_bs(cfg[b]), ldp = (ns[b] + bs - 1) / bs * bs;
             scratch_elems = std::max(scratch_elems, ldp * ldp);
         }
     }
@@ -755,7 +1058,7 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
     for (int32_t b = 0; b < batch; ++b) {
         if (ns[b] < 1 || ns[b] > 1024 || offsets[b] < 0 || offsets[b] % 4 != 0)
             return APSP_ERROR_INVALID_ARGUMENT;
-        if (team_config && (team_config[b] < -1 || team_config[b] > kGroupTiles128))
+        if (team_config && (team_config[b] < -1 || team_config[b] > kMixed128))
             return APSP_ERROR_INVALID_ARGUMENT;
         const int64_t end = offsets[b] + (int64_t)ns[b] * ns[b];
         max_end = std::max(max_end, end);
@@ -778,8 +1081,8 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
     std::vector<char> host;
-    batch_meta(ns, offsets, batch, dtype, p->want_pred, team_config, host, p->n_team, p->scratch_elems);
-    p->grid = std::max(1, 2 * cus);
+    batch_meta(ns, offsets, batch, dtype, p->want_pred, team_config, host, p->n_team, p->scratch_elems, p->lean);
+    p->grid = std::max(1, batched_blocks_per_cu(dtype, p->lean) * cus);
     const size_t elem = p->want_pred ? 8 : 4;
     if (hipMalloc(&p->dev_meta, host.size()) != hipSuccess ||
         hipMalloc((void **)&p->counters, 8 * sizeof(int32_t)) != hipSuccess ||
@@ -810,7 +1113,7 @@ apsp_status_t apsp_batch_plan_execute(const apsp_batch_plan_t *plan, void *packe
         return APSP_ERROR_INVALID_ARGUMENT;
     if ((uintptr_t)packed_dist % 16 || (uintptr_t)packed_pred % 16) return APSP_ERROR_INVALID_ARGUMENT;
     BatchLaunch L{plan->dev_meta, plan->batch, plan->n_team, plan->scratch_elems, plan->scratch,
-                  plan->counters, plan->grid};
+                  plan->counters, plan->grid, plan->lean};
     return batched_launch(L, plan->dtype, plan->want_pred, packed_dist, packed_pred, d_status, stream);
 }
 
@@ -914,13 +1217,15 @@ apsp_status_t autotune_on(const std::vector<int32_t> &sizes, apsp_dtype_t dtype,
         if (!present[c]) continue;
         double best_ms = 1e300;
         int best = choice[c];
-        for (int cfg = kWaveTiles64; cfg <= kGroupTiles128 && result == APSP_SUCCESS; ++cfg) {
+        // the mixed configuration is a distance configuration (the lean kernel)
+        const int last = want_pred ? kGroupTiles128 : kMixed128;
+        for (int cfg = kWaveTiles64; cfg <= last && result == APSP_SUCCESS; ++cfg) {
             int8_t trial[kClasses];
             std::memcpy(trial, choice, sizeof trial);
             trial[c] = (int8_t)cfg;
             double ms = 0.0;
             result = time_batch(trial, ms);
-            if (ms_out) ms_out[c * 3 + cfg] = ms;
+            if (ms_out) ms_out[c * 4 + cfg] = ms;
             if (result == APSP_SUCCESS && ms < best_ms) {
                 best_ms = ms;
                 best = cfg;

@@ -58,6 +58,7 @@ struct BatchLaunch {
     void *scratch;          // grid * scratch_elems * (4 or 8 bytes)
     int32_t *counters;      // 8 int32 (two launches' counters), zero before the first launch
     int grid;
+    bool lean;              // distances in the lean kernel (one launch)
 };
 apsp_status_t batched_launch(const BatchLaunch &L, apsp_dtype_t dtype, bool want_pred, void *dist,
                              int32_t *pred, int32_t *status, hipStream_t s);
@@ -65,7 +66,9 @@ apsp_status_t batched_launch(const BatchLaunch &L, apsp_dtype_t dtype, bool want
 // (order | ns | offsets | per-graph team configuration).
 void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, int32_t &n_team);
 void batch_meta(const int32_t *ns, const int64_t *offsets, int32_t B, apsp_dtype_t dtype, bool pred,
-                const int8_t *forced, std::vector<char> &bytes, int32_t &n_team, int64_t &scratch_elems);
+                const int8_t *forced, std::vector<char> &bytes, int32_t &n_team, int64_t &scratch_elems,
+                bool &lean);
+int batched_blocks_per_cu(apsp_dtype_t dtype, bool lean);
 
 // ---------------------------------------------------------------------------
 // Arithmetic policies.  Each supplies the element type T, the number of
@@ -289,7 +292,9 @@ struct TileProductDMA {
     __device__ __forceinline__ static void copy_chunk(T *__restrict__ la, T *__restrict__ lb,
                                                       const T *__restrict__ Abase,
                                                       const T *__restrict__ Bbase, uint32_t ld) {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        // the wavefront index is uniform: read it into a scalar register so the
+        // LDS destinations (the M0 operand of each copy) need no vector registers
+        const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 #pragma unroll
         for (int j = 0; j < IA / NWAVES; ++j) {
             const int i = wave * (IA / NWAVES) + j;
@@ -359,18 +364,54 @@ struct TileProductDMA {
     __device__ __forceinline__ static void accumulate(Smem &sm, T (&c)[TM][TN], const T *__restrict__ Abase,
                                                       const T *__restrict__ Bbase, uint32_t ld, int kcount,
                                                       int tx, int ty, const Ar &ar) {
+        accumulate_in(sm.a0, sm.a1, sm.b0, sm.b1, c, Abase, Bbase, ld, kcount, tx, ty, ar);
+    }
+
+    // The same on caller-provided chunk buffers (each at least MT*KC or KC*NT
+    // elements).  Four distinct LDS arrays let the compiler see that the copy
+    // into one buffer never aliases the reads of the other, so the copy stays
+    // in flight across the computation.
+    __device__ __forceinline__ static void accumulate_in(T *__restrict__ a0, T *__restrict__ a1,
+                                                         T *__restrict__ b0, T *__restrict__ b1, T (&c)[TM][TN],
+                                                         const T *__restrict__ Abase, const T *__restrict__ Bbase,
+                                                         uint32_t ld, int kcount, int tx, int ty, const Ar &ar) {
         const int nch = kcount / KC;
         const int64_t bstep = (int64_t)KC * ld;
-        copy_chunk(sm.a0, sm.b0, Abase, Bbase, ld);
-        copies_done(sm.a0, ar);
+        copy_chunk(a0, b0, Abase, Bbase, ld);
+        copies_done(a0, ar);
         for (int ch = 0; ch < nch; ch += 2) {
-            copy_chunk(sm.a1, sm.b1, Abase + (ch + 1) * KC, Bbase + (ch + 1) * bstep, ld);
-            compute(c, sm.a0, sm.b0, tx, ty, ar);
-            copies_done(sm.a1, ar);
-            if (ch + 2 < nch) copy_chunk(sm.a0, sm.b0, Abase + (ch + 2) * KC, Bbase + (ch + 2) * bstep, ld);
-            compute(c, sm.a1, sm.b1, tx, ty, ar);
-            if (ch + 2 < nch) copies_done(sm.a0, ar);
+            copy_chunk(a1, b1, Abase + (ch + 1) * KC, Bbase + (ch + 1) * bstep, ld);
+            compute(c, a0, b0, tx, ty, ar);
+            copies_done(a1, ar);
+            if (ch + 2 < nch) copy_chunk(a0, b0, Abase + (ch + 2) * KC, Bbase + (ch + 2) * bstep, ld);
+            compute(c, a1, b1, tx, ty, ar);
+            if (ch + 2 < nch) copies_done(a0, ar);
         }
+    }
+
+    // run() on caller-provided chunk buffers (see accumulate_in).
+    __device__ __forceinline__ static void run_in(T *__restrict__ a0, T *__restrict__ a1, T *__restrict__ b0,
+                                                  T *__restrict__ b1, T *__restrict__ D, int64_t ld64, int64_t crow,
+                                                  int64_t ccol, int64_t k0, int kcount, const Ar &ar) {
+        const int tid = threadIdx.x;
+        const int tx = tid % TX, ty = tid / TX;
+        const uint32_t ld = (uint32_t)ld64;
+        T *const Cbase = D + crow * ld64 + ccol;
+        const T *const Abase = D + crow * ld64 + k0;
+        const T *const Bbase = D + k0 * ld64 + ccol;
+        const uint32_t coff = (uint32_t)ty * ld + (uint32_t)tx * VW;
+        T c[TM][TN];
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+#pragma unroll
+            for (int g = 0; g < GN; ++g)
+                ld16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
+        accumulate_in(a0, a1, b0, b1, c, Abase, Bbase, ld, kcount, tx, ty, ar);
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+#pragma unroll
+            for (int g = 0; g < GN; ++g)
+                st16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
     }
 
     // WATCH: check the tile's inputs and outputs with the policy (see ArF32W)

@@ -319,7 +319,8 @@ void apsp_server::launch_group(std::vector<Request *> &batch) {
     std::vector<char> meta_host;
     int32_t n_team = 0;
     int64_t need_scratch = 0;
-    batch_meta(ns.data(), offs.data(), B, g->dtype, g->want_pred, nullptr, meta_host, n_team, need_scratch);
+    bool lean = false;
+    batch_meta(ns.data(), offs.data(), B, g->dtype, g->want_pred, nullptr, meta_host, n_team, need_scratch, lean);
     const size_t meta_bytes = round_up(meta_host.size(), 256);
     g->pred_off_bytes = (int64_t)dist_bytes;
     g->status_off_bytes = (int64_t)(dist_bytes + pred_bytes);
@@ -353,7 +354,10 @@ void apsp_server::launch_group(std::vector<Request *> &batch) {
             st = APSP_ERROR_HIP;
     }
     if (st == APSP_SUCCESS) {
-        BatchLaunch L{meta, B, n_team, batch_scratch_elems, batch_scratch, batch_counters, batch_grid};
+        // the scratch holds 2 x CUs work matrices of 8-byte elements, i.e.
+        // 4 x CUs of 4-byte ones: room for the lean kernel's workgroups
+        const int grid = lean ? std::min(4, batched_blocks_per_cu(g->dtype, true)) * cus : batch_grid;
+        BatchLaunch L{meta, B, n_team, batch_scratch_elems, batch_scratch, batch_counters, grid, lean};
         st = batched_launch(L, g->dtype, g->want_pred, arena,
                             g->want_pred ? (int32_t *)(arena + g->pred_off_bytes) : nullptr,
                             (int32_t *)(arena + g->status_off_bytes), s);
