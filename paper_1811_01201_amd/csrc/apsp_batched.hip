@@ -542,15 +542,15 @@ __device__ __forceinline__ bool lean_copy_in(const Ar &ar, const Tin *__restrict
     // one row per wavefront at a time, all of its loads issued before the
     // first is used (a row has at most 16 64-wide pieces)
     for (int i = wave; i < ldp; i += kBatchThreads / 64) {
-        for (int j0 = 0; j0 < ldp; j0 += 8 * 64) {
-            Tin w[8];
+        for (int j0 = 0; j0 < ldp; j0 += 16 * 64) {
+            Tin w[16];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < 16; ++t) {
                 const int j = j0 + t * 64 + lane;
                 w[t] = (i < n && j < n) ? src[(uint32_t)i * (uint32_t)n + (uint32_t)j] : Tin(0);
             }
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < 16; ++t) {
                 const int j = j0 + t * 64 + lane;
                 const bool inside = i < n && j < n;
                 if constexpr (CHECK) ruled_out |= inside & f32_ruled_out(w[t], lim);
@@ -614,15 +614,15 @@ __device__ __forceinline__ void lean_copy_out(const Ar &ar, const typename Ar::T
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     bool neg = false;
     for (int i = wave; i < n; i += kBatchThreads / 64) {
-        for (int j0 = 0; j0 < n; j0 += 8 * 64) {
-            T v[8];
+        for (int j0 = 0; j0 < n; j0 += 16 * 64) {
+            T v[16];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < 16; ++t) {
                 const int j = j0 + t * 64 + lane;
                 v[t] = j < n ? X[(uint32_t)i * (uint32_t)ldp + (uint32_t)j] : T(0);
             }
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < 16; ++t) {
                 const int j = j0 + t * 64 + lane;
                 if (j < n)
                     neg |= from_work(ar, v[t], i, j, dst + ((uint32_t)i * (uint32_t)n + (uint32_t)j),
@@ -870,9 +870,11 @@ void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, 
 // ------------------------------------------------------- tuning table
 // Team configuration per (dtype, predecessors, size class); size classes
 // are n in (64,128], (128,192], ..., (448,512] (64 wide, so a class pads
-// its graphs to one multiple of 64) and (512,1024].  Distances default to
-// kMixed128 (the lean kernel: padding to 64, 128-wide blocks, no spills);
-// 8-byte keys keep the 64-wide configurations of the general kernel.
+// its graphs to one multiple of 64) and (512,1024].  Distances run in the
+// lean kernel (padding to 64): 64-wide blocks up to n = 192, kMixed128
+// above (measured on MI355X, 4096 graphs of one size: n = 128 0.81 vs
+// 1.00 ms, 192 2.06 vs 2.23, 256 3.80 vs 3.81, 384 in 3072 graphs 10.1 vs
+// 8.9); 8-byte keys keep the 64-wide configurations of the general kernel.
 constexpr int kClasses = 8;
 constexpr int kClassHi[kClasses] = {128, 192, 256, 320, 384, 448, 512, 1024};
 std::mutex g_tune_mu;
@@ -880,9 +882,9 @@ constexpr int8_t kW = kWaveTiles64, kG = kGroupTiles64, kG2 = kGroupTiles128;
 constexpr int8_t kM = kMixed128;
 int8_t g_tune[2][2][kClasses] = {
     // int32: distances, predecessors
-    {{kM, kM, kM, kM, kM, kM, kM, kM}, {kG, kG, kG, kW, kW, kW, kW, kW}},
+    {{kG, kG, kM, kM, kM, kM, kM, kM}, {kG, kG, kG, kW, kW, kW, kW, kW}},
     // float32
-    {{kM, kM, kM, kM, kM, kM, kM, kM}, {kG, kG, kG, kW, kW, kW, kW, kW}}};
+    {{kG, kG, kM, kM, kM, kM, kM, kM}, {kG, kG, kG, kW, kW, kW, kW, kW}}};
 bool g_tune_env_checked = false;
 
 int size_class(int64_t n) {
