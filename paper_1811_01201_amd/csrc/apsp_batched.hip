@@ -26,6 +26,7 @@
 #include <numeric>
 #include <vector>
 
+#include "apsp_batch_host.h"
 #include "apsp_internal.h"
 
 namespace apsp {
@@ -40,9 +41,6 @@ struct BatchMeta {
     int64_t scratch_elems;   // work-matrix elements per workgroup
 };
 
-constexpr int kBatchBS = 64;
-constexpr int kBatchThreads = 256;
-enum TeamCfg { kWaveTiles64 = 0, kGroupTiles64 = 1, kGroupTiles128 = 2, kMixed128 = 3 };
 
 // ------------------------------------------------ input/output conversion
 template <class Ar, class Tin>
@@ -859,14 +857,6 @@ apsp_status_t batched_launch(const BatchLaunch &L, apsp_dtype_t dtype, bool want
     return launch<float>(L, dist, nullptr, status, s, ArF32{}, NoAlt{}, L.counters);
 }
 
-void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, int32_t &n_team) {
-    order.resize(batch);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ns[a] > ns[b]; });
-    n_team = 0;
-    while (n_team < batch && ns[order[n_team]] > kBatchBS) ++n_team;
-}
-
 // ------------------------------------------------------- tuning table
 // Team configuration per (dtype, predecessors, size class); size classes
 // are n in (64,128], (128,192], ..., (448,512] (64 wide, so a class pads
@@ -875,25 +865,14 @@ void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, 
 // above (measured on MI355X, 4096 graphs of one size: n = 128 0.81 vs
 // 1.00 ms, 192 2.06 vs 2.23, 256 3.80 vs 3.81, 384 in 3072 graphs 10.1 vs
 // 8.9); 8-byte keys keep the 64-wide configurations of the general kernel.
-constexpr int kClasses = 8;
-constexpr int kClassHi[kClasses] = {128, 192, 256, 320, 384, 448, 512, 1024};
 std::mutex g_tune_mu;
-constexpr int8_t kW = kWaveTiles64, kG = kGroupTiles64, kG2 = kGroupTiles128;
-constexpr int8_t kM = kMixed128;
+constexpr int8_t kW = kWaveTiles64, kG = kGroupTiles64, kM = kMixed128;
 int8_t g_tune[2][2][kClasses] = {
     // int32: distances, predecessors
     {{kG, kG, kM, kM, kM, kM, kM, kM}, {kG, kG, kG, kW, kW, kW, kW, kW}},
     // float32
     {{kG, kG, kM, kM, kM, kM, kM, kM}, {kG, kG, kG, kW, kW, kW, kW, kW}}};
 bool g_tune_env_checked = false;
-
-int size_class(int64_t n) {
-    for (int c = 0; c < kClasses; ++c)
-        if (n <= kClassHi[c]) return c;
-    return kClasses - 1;
-}
-
-int team_bs(int cfg) { return cfg == kGroupTiles128 ? 128 : 64; }
 
 apsp_status_t tune_load_locked(const char *path);
 
@@ -992,40 +971,13 @@ __global__ void tune_fill_kernel(T *buf, const int64_t *offs, const int32_t *ns,
     }
 }
 
-// Host image of a batch's device metadata:
-//   order[B] int32 | ns[B] int32 | offsets[B] int64 | cfg[B] int8
-// with the team configuration of every graph (forced or from the table),
-// and the work-matrix elements one workgroup needs.
-//
-// lean (out): the batch runs in the lean distance kernel, which takes the
-// graphs above 64 vertices when every one of them has configuration
-// kMixed128 or kGroupTiles64 (work matrices padded to 64) and there are no
-// predecessors; otherwise the general kernel runs, which solves kMixed128
-// graphs as kGroupTiles128 (padded to 128).
+// Device metadata image of a batch (see batch_meta_with) with the tuning
+// table's configurations.
 void batch_meta(const int32_t *ns, const int64_t *offsets, int32_t B, apsp_dtype_t dtype, bool pred,
                 const int8_t *forced, std::vector<char> &bytes, int32_t &n_team, int64_t &scratch_elems,
                 bool &lean) {
-    std::vector<int32_t> order;
-    batch_order(ns, B, order, n_team);
-    bytes.assign(std::max<size_t>((size_t)B * 17 + 16, 32), 0);
-    std::copy(order.begin(), order.end(), (int32_t *)bytes.data());
-    std::copy(ns, ns + B, (int32_t *)bytes.data() + B);
-    std::copy(offsets, offsets + B, (int64_t *)(bytes.data() + (size_t)B * 8));
-    int8_t *cfg = (int8_t *)(bytes.data() + (size_t)B * 16);
-    lean = !pred;
-    for (int32_t b = 0; b < B; ++b) {
-        const int8_t c = forced && forced[b] >= 0 ? forced[b] : batch_config(ns[b], dtype, pred);
-        cfg[b] = c;
-        if (ns[b] > kBatchBS && c != kMixed128 && c != kGroupTiles64) lean = false;
-    }
-    scratch_elems = 0;
-    for (int32_t b = 0; b < B; ++b) {
-        if (!lean && cfg[b] == kMixed128) cfg[b] = kGroupTiles128;
-        if (ns[b] > kBatchBS) {
-            const int64_t bs = lean ? 64 : team_bs(cfg[b]), ldp = (ns[b] + bs - 1) / bs * bs;
-            scratch_elems = std::max(scratch_elems, ldp * ldp);
-        }
-    }
+    batch_meta_with(ns, offsets, B, pred, forced, [&](int64_t n) { return batch_config(n, dtype, pred); }, bytes,
+                    n_team, scratch_elems, lean);
 }
 
 // wait == true: block until every retired plan can be freed.
@@ -1052,23 +1004,10 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
     if (!out_plan) return APSP_ERROR_INVALID_ARGUMENT;
     sweep_retired(false);
     *out_plan = nullptr;
-    if (batch < 0 || (batch > 0 && (!ns || !offsets))) return APSP_ERROR_INVALID_ARGUMENT;
     if (dtype != APSP_INT32 && dtype != APSP_FLOAT32) return APSP_ERROR_INVALID_ARGUMENT;
     int64_t max_end = 0;
-    std::vector<std::pair<int64_t, int64_t>> spans;
-    spans.reserve(batch);
-    for (int32_t b = 0; b < batch; ++b) {
-        if (ns[b] < 1 || ns[b] > 1024 || offsets[b] < 0 || offsets[b] % 4 != 0)
-            return APSP_ERROR_INVALID_ARGUMENT;
-        if (team_config && (team_config[b] < -1 || team_config[b] > kMixed128))
-            return APSP_ERROR_INVALID_ARGUMENT;
-        const int64_t end = offsets[b] + (int64_t)ns[b] * ns[b];
-        max_end = std::max(max_end, end);
-        spans.push_back({offsets[b], end});
-    }
-    std::sort(spans.begin(), spans.end());
-    for (size_t i = 1; i < spans.size(); ++i)
-        if (spans[i].first < spans[i - 1].second) return APSP_ERROR_INVALID_ARGUMENT;  // overlap
+    const apsp_status_t bad = plan_args_check(ns, offsets, batch, team_config, &max_end);
+    if (bad != APSP_SUCCESS) return bad;
 
     auto *p = new (std::nothrow) apsp_batch_plan_t();
     if (!p) return APSP_ERROR_OUT_OF_MEMORY;

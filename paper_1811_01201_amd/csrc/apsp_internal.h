@@ -62,9 +62,9 @@ struct BatchLaunch {
 };
 apsp_status_t batched_launch(const BatchLaunch &L, apsp_dtype_t dtype, bool want_pred, void *dist,
                              int32_t *pred, int32_t *status, hipStream_t s);
-// Host side of a plan: largest-first order, and the device metadata image
-// (order | ns | offsets | per-graph team configuration).
-void batch_order(const int32_t *ns, int32_t batch, std::vector<int32_t> &order, int32_t &n_team);
+// Host side of a plan: the device metadata image (order | ns | offsets |
+// per-graph team configuration) with the tuning table's choices; the
+// host-only planning itself is apsp_batch_host.h.
 void batch_meta(const int32_t *ns, const int64_t *offsets, int32_t B, apsp_dtype_t dtype, bool pred,
                 const int8_t *forced, std::vector<char> &bytes, int32_t &n_team, int64_t &scratch_elems,
                 bool &lean);
