@@ -80,7 +80,7 @@ typedef enum {
     APSP_ERROR_QUEUE_FULL = 6,       /* server: admission queue is full */
     APSP_ERROR_NOT_READY = 7,        /* server: request still running */
     APSP_ERROR_CANCELLED = 8,        /* server: request cancelled or server destroyed */
-    APSP_ERROR_TIMEOUT = 9,          /* server: wait timed out */
+    APSP_ERROR_TIMEOUT = 9,          /* server: wait timed out; single-launch barrier wait ran out */
     APSP_ERROR_UNKNOWN_TICKET = 10   /* server: no such (unreleased) request */
 } apsp_status_t;
 
@@ -128,7 +128,18 @@ typedef struct {
                               phases 1-2 of round r+1 run beside most of it on a library-owned
                               second stream; 1 = one stream, rounds in order; 2 = the
                               two-stream split at any size with at least three rounds
-                              (the device-gated fallback passes always run in order) */
+                              (the device-gated fallback passes always run in order);
+                              3 = every round in one cooperative launch whose workgroups
+                              (all resident at once) meet at device-wide barriers, two per
+                              round, or, where one workgroup per 64 x 64 block fits,
+                              waiting per block only for the panels it reads --
+                              automatic (0) for distance solves up to a padded
+                              order of 4096 issued directly (not under use_graph, a
+                              stepper or apsp_solve_noalloc).  3 requires distances only,
+                              n <= 16384, block_size 0 or 64, thread_tile 0 or 4, use_graph 0 and, for
+                              int32 weights, arith 0 or 1 (int32 arithmetic), else
+                              APSP_ERROR_INVALID_ARGUMENT; the values equal those of the
+                              other schedules bit for bit */
     int32_t use_graph;     /* nonzero: capture the launch sequence once per shape into a
                               hipGraph and replay it (fewer launch gaps for small n) */
     int32_t arith;         /* Distances only, int32 weights (ignored for float32 weights):
@@ -148,7 +159,11 @@ typedef struct {
                               distance equal to D(i,j)); if not, it runs the recurrence on
                               the original weights instead.  The results are the same. */
     int32_t *d_status;     /* device int32 or NULL: receives APSP_SUCCESS,
-                              APSP_ERROR_INVALID_VALUE or APSP_ERROR_NEGATIVE_CYCLE */
+                              APSP_ERROR_INVALID_VALUE or APSP_ERROR_NEGATIVE_CYCLE, or
+                              APSP_ERROR_TIMEOUT if a barrier wait of the single-launch
+                              schedule ran out (about a second; its workgroups are
+                              resident together, so only a faulty device gets there;
+                              dist is then partly updated) */
     int32_t *d_arith;      /* device int32 or NULL: receives 1 if the result came from float32
                               arithmetic (with predecessors: the float32 route held), 0 if
                               from int32 arithmetic (the recurrence) */
@@ -248,6 +263,7 @@ typedef struct {
     apsp_kernel_time_t pred_product; /* predecessors read off the float32 key product */
     apsp_kernel_time_t phase1_blocked; /* the phase-1 launches (also counted in phase1) that
                                           were the blocked closure of the diagonal block */
+    apsp_kernel_time_t single_launch;  /* the single-launch schedule's kernel (all rounds) */
 } apsp_profile_t;
 
 apsp_status_t apsp_profile_begin(void);

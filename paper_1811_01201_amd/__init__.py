@@ -44,7 +44,7 @@ class KernelTime(ctypes.Structure):
 class Profile(ctypes.Structure):
     _fields_ = [("phase1", KernelTime), ("phase2", KernelTime), ("phase3", KernelTime),
                 ("other", KernelTime), ("phase3_cross", KernelTime), ("pred_product", KernelTime),
-                ("phase1_blocked", KernelTime)]
+                ("phase1_blocked", KernelTime), ("single_launch", KernelTime)]
 
     def as_dict(self):
         out = {}
@@ -183,7 +183,9 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
              result came from float32 arithmetic (with pred: the product held),
              else 0.
     schedule : 0 automatic, 1 rounds in order on one stream, 2 the two-stream
-             split at any size with three rounds or more.
+             split at any size with three rounds or more, 3 all rounds in one
+             cooperative launch (distances, 64-wide blocks, int32 arithmetic
+             for int32; automatic for distance solves up to n = 4096).
     phase1 : 0 automatic, 1 the stepwise diagonal kernel, 2 the blocked
              closure of the diagonal block (block_size=256).
     Returns the host status of the enqueue (raises APSPError unless check=False).

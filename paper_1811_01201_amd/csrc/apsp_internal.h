@@ -262,8 +262,14 @@ __device__ __forceinline__ void st16(T *p, const T *in) {
 // row r are XOR-swizzled by ((r * KP) >> 3) & (KP - 1) (KP = pieces per
 // row) so the four rows a wavefront reads at one k fall into distinct LDS
 // bank groups (8 groups of 16 bytes).
+//
+// CPOL is the copies' cache policy (0: the default; kCpolDevice: coherent
+// at device scope, for kernels whose workgroups exchange data without a
+// launch boundary or a device-scope cache flush in between).
 // ---------------------------------------------------------------------------
-template <class Ar, int MT, int NT, int KC, int TM, int TN>
+constexpr int kCpolDevice = 16;  // sc1: device scope
+
+template <class Ar, int MT, int NT, int KC, int TM, int TN, int CPOL = 0>
 struct TileProductDMA {
     using T = typename Ar::T;
     static_assert(sizeof(T) == 4 || sizeof(T) == 8, "16-byte pieces of 4- or 8-byte elements");
@@ -292,6 +298,12 @@ struct TileProductDMA {
     __device__ __forceinline__ static void copy_chunk(T *__restrict__ la, T *__restrict__ lb,
                                                       const T *__restrict__ Abase,
                                                       const T *__restrict__ Bbase, uint32_t ld) {
+        copy_a(la, Abase, ld);
+        copy_b(lb, Bbase, ld);
+    }
+
+    // the A chunk alone (MT rows of KC elements, swizzled) ...
+    __device__ __forceinline__ static void copy_a(T *__restrict__ la, const T *__restrict__ Abase, uint32_t ld) {
         // the wavefront index is uniform: read it into a scalar register so the
         // LDS destinations (the M0 operand of each copy) need no vector registers
         const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -303,8 +315,13 @@ struct TileProductDMA {
             const T *g = Abase + ((uint32_t)row * ld + (uint32_t)((piece ^ swz(row)) * VW));
             __builtin_amdgcn_global_load_lds((const void *)g,
                                              (__attribute__((address_space(3))) void *)(la + i * 64 * VW),
-                                             16, 0, 0);
+                                             16, 0, CPOL);
         }
+    }
+
+    // ... and the B chunk alone (KC rows of NT elements)
+    __device__ __forceinline__ static void copy_b(T *__restrict__ lb, const T *__restrict__ Bbase, uint32_t ld) {
+        const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 #pragma unroll
         for (int j = 0; j < IB / NWAVES; ++j) {
             const int i = wave * (IB / NWAVES) + j;
@@ -313,7 +330,7 @@ struct TileProductDMA {
             const T *g = Bbase + ((uint32_t)row * ld + (uint32_t)(cv * VW));
             __builtin_amdgcn_global_load_lds((const void *)g,
                                              (__attribute__((address_space(3))) void *)(lb + i * 64 * VW),
-                                             16, 0, 0);
+                                             16, 0, CPOL);
         }
     }
 

@@ -260,6 +260,399 @@ phase3_kernel(void *X, int64_t ld, int r, int per_xcd, int seq0, int seq_end, Ar
     }
 }
 
+// ------------------------------------------------ single-launch schedule
+// Small graphs: all rounds in one cooperative launch of co-resident
+// workgroups that meet at device-wide barriers, in place of three dependent
+// launches per round, whose dispatch gaps rather than their arithmetic set
+// the time of a solve below n of a few thousand.  64 x 64 blocks and tiles;
+// every product stages its whole A and B (64 k each) in one LDS DMA pass.
+// The blocked schedule is kept as it is -- round r's panels read the closed
+// block r, its remaining blocks read round r's panels, each product over the
+// same operands -- so the values are the multi-launch schedule's, bit for
+// bit.  Lookahead: workgroup 0 takes round r's tile (r+1, r+1) first and
+// closes it at once (phase 1 of round r+1) while the others finish round
+// r's phase 3, so a round costs two barriers:
+//   [P2(r) tiles] barrier [P3(r) tiles; WG 0: tile (r+1,r+1), P1(r+1)] barrier
+//
+// Coherence without cache flushes: each XCD has its own L2, and a
+// device-scope release or acquire fence writes back or invalidates the
+// whole L2 -- one such operation per wavefront and barrier costs more than
+// the barrier itself once hundreds of workgroups take part.  Instead every
+// load and store of the matrix in this kernel is device-coherent (cache
+// policy sc1: stores write through, loads do not return lines another XCD
+// may have overwritten), so a barrier only waits for its own stores to
+// complete before arriving.
+//
+// Barrier words (all zeroed by single_init_kernel before the launch), each
+// barrier numbered b = 1, 2, ... within the launch:
+//   flags[w]      workgroup w arrived at barrier b (stores b; one word each,
+//                 so arrivals never contend on one address)
+//   release[x]    workgroup 0, having seen every flag at b, stores b into
+//                 all 8 copies (256 bytes apart); workgroup w polls copy w % 8
+//   fail          a wait ran out; every other wait then ends too
+constexpr int kSingleBS = 64;
+constexpr int kSingleThreads = 256;
+constexpr int kSingleMaxGroups = 2048;
+constexpr int kReleaseWords = kSingleMaxGroups;  // 8 copies, 64 words apart
+constexpr int kFailWord = kReleaseWords + 8 * 64;
+constexpr int kSingleWords = kFailWord + 64;
+constexpr size_t kSingleWordBytes = (size_t)kSingleWords * 4;
+// element offsets within the matrix are 32-bit
+constexpr int64_t kSingleMaxN = 16384;
+// Spins of one barrier wait before it gives up (about a second or more;
+// the workgroups are co-resident, so a wait ends long before unless the
+// device is broken).  A failed wait sets the fail word, which ends every
+// other wait, and the solve reports APSP_ERROR_TIMEOUT.
+constexpr uint32_t kBarrierSpins = 1u << 22;
+
+__global__ void single_init_kernel(uint32_t *words, int32_t *status) {
+    for (int i = threadIdx.x; i < kSingleWords; i += blockDim.x) words[i] = 0;
+    if (status && threadIdx.x == 0) *status = APSP_SUCCESS;
+}
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// this wavefront's loads and stores (device-coherent ones included) complete
+__device__ __forceinline__ void mem_done() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// Device-wide barrier number b; false if a wait ran out here or anywhere.
+// Data moves through device-coherent accesses only (see above), so arriving
+// needs no more than this workgroup's accesses completed.
+__device__ __forceinline__ bool grid_barrier(uint32_t *words, int groups, uint32_t b, int *ok_lds) {
+    mem_done();
+    __syncthreads();
+    const int w = (int)blockIdx.x;
+    if (threadIdx.x == 0) st_agent(&words[w], b);
+    if (w == 0) {
+        // every thread checks a share of the flags; the decision is block-wide
+        bool ok = true;
+        for (uint32_t spin = 0;; ++spin) {
+            bool mine = true;
+            for (int v = (int)threadIdx.x; v < groups; v += kSingleThreads) mine &= ld_agent(&words[v]) == b;
+            if (__syncthreads_and(mine)) break;
+            const bool failed = threadIdx.x == 0 && ld_agent(&words[kFailWord]) != 0;
+            if (__syncthreads_or(failed) || spin >= kBarrierSpins) {
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (threadIdx.x == 0) {
+            if (ok) {
+#pragma unroll
+                for (int x = 0; x < 8; ++x) st_agent(&words[kReleaseWords + 64 * x], b);
+            } else {
+                st_agent(&words[kFailWord], 1u);
+            }
+        }
+    } else if (threadIdx.x == 0) {
+        const uint32_t *rel = &words[kReleaseWords + 64 * (w & 7)];
+        for (uint32_t spin = 0; ld_agent(rel) != b; ++spin) {
+            if (spin >= kBarrierSpins) {
+                st_agent(&words[kFailWord], 1u);
+                break;
+            }
+            if (ld_agent(&words[kFailWord]) != 0) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    if (threadIdx.x == 0) *ok_lds = ld_agent(&words[kFailWord]) == 0;
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+// 16-byte device-coherent accesses (two 8-byte device-scope atomics, which
+// the compiler emits as dwordx2 loads and stores with sc1)
+template <class T>
+__device__ __forceinline__ void ld16_dev(const T *p, T *out) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    const uint64_t *q = (const uint64_t *)p;
+    const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    out[0] = __builtin_bit_cast(T, (uint32_t)a);
+    out[1] = __builtin_bit_cast(T, (uint32_t)(a >> 32));
+    out[2] = __builtin_bit_cast(T, (uint32_t)b);
+    out[3] = __builtin_bit_cast(T, (uint32_t)(b >> 32));
+}
+template <class T>
+__device__ __forceinline__ void st16_dev(T *p, const T *in) {
+    uint64_t *q = (uint64_t *)p;
+    const uint64_t a = (uint64_t)__builtin_bit_cast(uint32_t, in[0]) |
+                       ((uint64_t)__builtin_bit_cast(uint32_t, in[1]) << 32);
+    const uint64_t b = (uint64_t)__builtin_bit_cast(uint32_t, in[2]) |
+                       ((uint64_t)__builtin_bit_cast(uint32_t, in[3]) << 32);
+    __hip_atomic_store(q, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class Ar>
+__global__ void __launch_bounds__(kSingleThreads)
+rounds_single_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, int32_t *status,
+                     const int32_t *__restrict__ skip) {
+    using T = typename Ar::T;
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    using TP = TileProductDMA<Ar, kSingleBS, kSingleBS, kSingleBS, 4, 4, kCpolDevice>;
+    using PS = P1S<Ar, kSingleBS, 4>;
+    static_assert(TP::NTH == kSingleThreads && PS::NTH == kSingleThreads && PS::TM1 == 4 && PS::TN1 == 4,
+                  "one workgroup shape for products and closures");
+    if (skip && *skip != APSP_SUCCESS) return;
+    __shared__ alignas(16) T la[kSingleBS * kSingleBS];
+    __shared__ alignas(16) T lb[kSingleBS * kSingleBS];
+    __shared__ alignas(16) T p1c[4][kSingleBS];
+    __shared__ alignas(16) T p1r[4][kSingleBS];
+    __shared__ int ok_lds;
+    T *const D = (T *)Xv;
+    const uint32_t ldu = (uint32_t)ld;
+    const int R = (int)(ld / kSingleBS), m = R - 1;
+    const int G = (int)gridDim.x, w = (int)blockIdx.x;
+    const int tid = (int)threadIdx.x;
+    uint32_t bar = 0;  // barriers passed
+
+    // C <- min(C, A (x) B) on the tile at (crow, ccol), k-block at k0
+    auto product = [&](uint32_t crow, uint32_t ccol, uint32_t k0) __attribute__((always_inline)) {
+        const int tx = tid % TP::TX, ty = tid / TP::TX;
+        T *const c0 = D + ((crow + (uint32_t)ty) * ldu + ccol + (uint32_t)tx * TP::VW);
+        T c[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ld16_dev(c0 + (uint32_t)(TP::TY * i) * ldu, c[i]);
+        __syncthreads();  // the previous tile's LDS reads are done
+        TP::copy_chunk(la, lb, D + (size_t)crow * ldu + k0, D + (size_t)k0 * ldu + ccol, ldu);
+        TP::copies_done(la, ar);
+        TP::compute(c, la, lb, tx, ty, ar);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) st16_dev(c0 + (uint32_t)(TP::TY * i) * ldu, c[i]);
+    };
+    // phase 1 on block r (the stepwise closure's register layout)
+    auto close = [&](uint32_t r0) __attribute__((always_inline)) {
+        mem_done();
+        __syncthreads();  // this workgroup's stores to the block are complete
+        const int tx = tid % PS::TX, ty = tid / PS::TX;
+        T *const c0 = D + ((r0 + (uint32_t)ty * 4) * ldu + r0 + (uint32_t)tx * 4);
+        T c[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ld16_dev(c0 + (uint32_t)i * ldu, c[i]);
+        (void)phase1_steps<Ar, kSingleBS, false, 4>(c, kSingleBS, ar, p1c, p1r);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) st16_dev(c0 + (uint32_t)i * ldu, c[i]);
+    };
+
+    bool ok = true;
+    if (w == 0) close(0);
+    for (int r = 0; r < R && m > 0; ++r) {
+        const uint32_t r0 = (uint32_t)r * kSingleBS;
+        if (!(ok = grid_barrier(words, G, ++bar, &ok_lds))) break;
+        // phase 2: block row r (t < m), block column r (t >= m)
+        for (int t = w; t < 2 * m; t += G) {
+            int q = t < m ? t : t - m;
+            q += q >= r;
+            if (t < m)
+                product(r0, (uint32_t)q * kSingleBS, r0);
+            else
+                product((uint32_t)q * kSingleBS, r0, r0);
+        }
+        if (!(ok = grid_barrier(words, G, ++bar, &ok_lds))) break;
+        // phase 3 over the m x m blocks outside row and column r, numbered
+        // a = i' m + j' (i', j' skip r); tile (r+1, r+1) is a = r m + r
+        const int total = m * m;
+        const bool ahead = r + 1 < R;
+        const int lead = ahead ? r * m + r : -1;
+        auto p3 = [&](int a) __attribute__((always_inline)) {
+            int i = a / m, j = a - (a / m) * m;
+            i += i >= r;
+            j += j >= r;
+            product((uint32_t)i * kSingleBS, (uint32_t)j * kSingleBS, r0);
+        };
+        if (ahead && w == 0) {
+            p3(lead);
+            close(r0 + kSingleBS);
+        }
+        // the other tiles: over workgroups 1 .. G-1, or all on workgroup 0
+        const int first = (ahead && G > 1) ? 1 : 0, stride = G - first;
+        for (int t = w - first; w >= first && t < total - (ahead ? 1 : 0); t += stride)
+            p3(ahead && t >= lead ? t + 1 : t);
+    }
+    if (!ok && status && tid == 0) *status = APSP_ERROR_TIMEOUT;
+}
+
+// Dataflow form of the single launch, for padded orders whose R x R blocks
+// (R = ld / 64) fit one workgroup each on the device at once.  Workgroup
+// w = i R + j owns block (i, j) for the whole solve and keeps it in
+// registers (the stepwise closure's layout: thread (tx, ty) holds rows
+// 4 ty .. 4 ty + 3, columns 4 tx .. 4 tx + 3).  Per round r it does its one
+// task of the blocked schedule and then the next round's, waiting only for
+// the operands it reads:
+//   block (r, j), j != r   phase 2: waits for diag(r); B is its own block
+//   block (i, r), i != r   phase 2: waits for diag(r); A is its own block
+//   other blocks           phase 3: waits for panels (i, r) and (r, j)
+//   block (r+1, r+1)       after its phase 3, at once phase 1 of round r+1
+//                          (in registers), then publishes diag(r+1)
+// Panels and closed diagonal blocks are published, each exactly once, to
+// separate matrices (block row panels and diagonal blocks to P_row, block
+// column panels to P_col) with device-coherent stores, then a ready word
+// per published block is set; readers copy them with device-coherent LDS
+// DMA.  A block read by others is never written again in place, so no
+// reader can see a later round's value.  The operands of every product are
+// those of the multi-launch schedule, so the values are too, bit for bit.
+// Ready words: row(r, j) at r R + j, col(i, r) at R^2 + i R + r, diag(r) at
+// 2 R^2 + r, the fail word at flow_fail_word(R); all zeroed before the launch.
+__host__ __device__ constexpr int flow_fail_word(int R) { return 2 * R * R + R; }
+__host__ __device__ constexpr size_t flow_word_bytes(int R) { return ((size_t)flow_fail_word(R) + 64) * 4; }
+
+__global__ void flow_init_kernel(uint32_t *words, int count, int32_t *status) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) words[i] = 0;
+    if (status && blockIdx.x == 0 && threadIdx.x == 0) *status = APSP_SUCCESS;
+}
+
+// Waits until every nonzero-addressed word in w0, w1 reads nonzero (thread
+// 0 polls; the workgroup leaves together).  False if the wait ran out or
+// another wait did (the fail word).
+__device__ __forceinline__ bool flow_wait(const uint32_t *w0, const uint32_t *w1, uint32_t *fail, int *ok_lds) {
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        for (uint32_t spin = 0; ld_agent(w0) == 0 || (w1 && ld_agent(w1) == 0); ++spin) {
+            if (spin >= kBarrierSpins) {
+                st_agent(fail, 1u);
+                ok = 0;
+                break;
+            }
+            if (ld_agent(fail) != 0) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        *ok_lds = ok;
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+template <class Ar>
+__global__ void __launch_bounds__(kSingleThreads) __attribute__((amdgpu_waves_per_eu(4)))  // 4 per CU: n = 2048
+rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, void *pcol_v, int32_t *status,
+                   const int32_t *__restrict__ skip) {
+    using T = typename Ar::T;
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    constexpr int BS = kSingleBS;
+    using TP = TileProductDMA<Ar, BS, BS, BS, 4, 4, kCpolDevice>;  // its copies and LDS layouts
+    using PS = P1S<Ar, BS, 4>;
+    static_assert(PS::NTH == kSingleThreads && PS::TM1 == 4 && PS::TN1 == 4 && TP::VW == 4, "4 x 4 per thread");
+    if (skip && *skip != APSP_SUCCESS) return;
+    __shared__ alignas(16) T la[BS * BS];  // A: 64 rows of 64 k, 16-byte pieces swizzled per row
+    __shared__ alignas(16) T lb[BS * BS];  // B: 64 k rows of 64 columns
+    __shared__ alignas(16) T p1c[4][BS];
+    __shared__ alignas(16) T p1r[4][BS];
+    __shared__ int ok_lds;
+    T *const X = (T *)Xv;
+    T *const Prow = (T *)prow_v;
+    T *const Pcol = (T *)pcol_v;
+    const uint32_t ldu = (uint32_t)ld;
+    const int R = (int)(ld / BS);
+    const int bi = (int)blockIdx.x / R, bj = (int)blockIdx.x % R;
+    const int tid = (int)threadIdx.x, tx = tid % PS::TX, ty = tid / PS::TX;
+    uint32_t *const fail = words + flow_fail_word(R);
+    // block (p, q) of a matrix of order ld, and this thread's 4 x 4 piece of it
+    auto blk = [&](T *M, int p, int q) __attribute__((always_inline)) {
+        return M + ((uint32_t)p * BS * ldu + (uint32_t)q * BS);
+    };
+    auto at = [&](T *M, int p, int q) __attribute__((always_inline)) {
+        return blk(M, p, q) + ((uint32_t)ty * 4 * ldu + (uint32_t)tx * 4);
+    };
+    T c[4][4];
+    {
+        T *const src = at(X, bi, bj);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) ld16(src + (uint32_t)m * ldu, c[m]);
+    }
+    // c <- min(c, A (x) B), A in la, B in lb, once both are complete
+    auto multiply = [&]() __attribute__((always_inline)) {
+        TP::copies_done(la, ar);
+#pragma unroll 1
+        for (int kg = 0; kg < BS; kg += 4) {
+            T a[4][4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int row = ty * 4 + m;
+                ld16(&la[row * BS + (((kg >> 2) ^ TP::swz(row)) << 2)], a[m]);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 4; kk += 2) {
+                T b0[4], b1[4];
+                ld16(&lb[(kg + kk) * BS + tx * 4], b0);
+                ld16(&lb[(kg + kk + 1) * BS + tx * 4], b1);
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) c[m][n] = ar.relax2(c[m][n], a[m][kk], b0[n], a[m][kk + 1], b1[n]);
+            }
+        }
+    };
+    // stores this thread's piece into block (p, q) of M, then (once every
+    // wavefront's stores are complete) sets the ready word
+    auto publish = [&](T *M, int p, int q, uint32_t *ready) __attribute__((always_inline)) {
+        T *const dst = at(M, p, q);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) st16_dev(dst + (uint32_t)m * ldu, c[m]);
+        mem_done();
+        __syncthreads();
+        if (tid == 0) st_agent(ready, 1u);
+    };
+    auto close = [&]() __attribute__((always_inline)) {
+        (void)phase1_steps<Ar, BS, false, 4>(c, BS, ar, p1c, p1r);
+    };
+    uint32_t *const row_ready = words, *const col_ready = words + R * R, *const diag_ready = words + 2 * R * R;
+
+    bool ok = true;
+    if (bi == 0 && bj == 0) {
+        close();
+        publish(Prow, 0, 0, &diag_ready[0]);
+    }
+    for (int r = 0; r < R && ok; ++r) {
+        if (bi == r && bj == r) continue;  // closed one round earlier
+        if (bi == r) {
+            // block row r: c <- min(c, D(r,r)* (x) c)
+            if (!(ok = flow_wait(&diag_ready[r], nullptr, fail, &ok_lds))) break;
+            TP::copy_a(la, blk(Prow, r, r), ldu);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) st16(&lb[(ty * 4 + m) * BS + tx * 4], c[m]);
+            multiply();
+            publish(Prow, r, bj, &row_ready[r * R + bj]);
+        } else if (bj == r) {
+            // block column r: c <- min(c, c (x) D(r,r)*)
+            if (!(ok = flow_wait(&diag_ready[r], nullptr, fail, &ok_lds))) break;
+            TP::copy_b(lb, blk(Prow, r, r), ldu);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int row = ty * 4 + m;
+                st16(&la[row * BS + ((tx ^ TP::swz(row)) << 2)], c[m]);
+            }
+            multiply();
+            publish(Pcol, bi, r, &col_ready[bi * R + r]);
+        } else {
+            // the remaining blocks: c <- min(c, P_col(i, r) (x) P_row(r, j))
+            if (!(ok = flow_wait(&col_ready[bi * R + r], &row_ready[r * R + bj], fail, &ok_lds))) break;
+            TP::copy_chunk(la, lb, blk(Pcol, bi, r), blk(Prow, r, bj), ldu);
+            multiply();
+            if (bi == r + 1 && bj == r + 1) {
+                close();
+                publish(Prow, r + 1, r + 1, &diag_ready[r + 1]);
+            }
+        }
+        __syncthreads();  // LDS free for the next round's operands
+    }
+    if (ok) {
+        T *const dst = at(X, bi, bj);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) st16(dst + (uint32_t)m * ldu, c[m]);
+    } else if (status && tid == 0) {
+        *status = APSP_ERROR_TIMEOUT;
+    }
+}
+
 // ------------------------------------------------------ set-up / wrap-up
 __global__ void status_init_kernel(int32_t *status) { *status = APSP_SUCCESS; }
 
@@ -851,7 +1244,8 @@ enum KernelKind {
     kOther = 3,
     kPhase3Cross = 4,
     kPredProduct = 5,
-    kPhase1Blocked = 6  // counted under phase1 and phase1_blocked
+    kPhase1Blocked = 6,  // counted under phase1 and phase1_blocked
+    kSingle = 7          // the single-launch schedule's one kernel
 };
 struct ProfRecord {
     int kind;
@@ -1203,6 +1597,103 @@ size_t work_bytes(int64_t n, bool with_pred, int opt_bs, bool aligned, apsp_dtyp
     return (size_t)(ld * ld) * 4;
 }
 
+// Single-launch schedule: distances only, 64-wide blocks with 4 x 4 thread
+// tiles, 4-byte arithmetic without a watch (int32 in int32, float32),
+// issued directly (not while a graph or a stepper records, nor without
+// allocations); automatic up to a padded order of kSingleMaxLd.  The launch
+// is cooperative (every workgroup resident at once).  Where one workgroup
+// per 64 x 64 block fits on the device, the dataflow kernel
+// (rounds_flow_kernel); otherwise the barrier-phased one
+// (rounds_single_kernel), whose workgroup count is the blocks of one
+// phase 3, capped at what the device holds.  (Measured on MI355X, int32
+// distances, ms per solve, rounds in order / dataflow / barrier-phased:
+// n = 1024: 0.435 / 0.383 / 0.438; 2048: 1.171 / 0.896 / 0.929; 3072:
+// 2.44 / - / 1.89; 4096: 4.49 / - / 3.95.)
+constexpr int64_t kSingleMaxLd = 4096;
+
+// Workgroups of `kernel` the device holds at once (0 without cooperative
+// launches), looked up once per device.
+apsp_status_t coop_capacity(const void *kernel, int dev, int *out) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({kernel, dev});
+    if (it == cache.end()) {
+        int coop = 0, cus = 0, per_cu = 0;
+        APSP_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        APSP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        APSP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kSingleThreads, 0));
+        it = cache.emplace(std::make_pair(kernel, dev), coop ? per_cu * cus : 0).first;
+    }
+    *out = it->second;
+    return APSP_SUCCESS;
+}
+
+inline bool single_applies(int64_t ld, int bs, int tt, bool with_pred, bool f32w, int schedule, bool ext_ws) {
+    if (with_pred || f32w || bs != kSingleBS || tt != 4 || ext_ws || t_capturing || t_rec || t_noalloc)
+        return false;
+    return schedule == 3 || (schedule == 0 && ld <= kSingleMaxLd);
+}
+
+// Which single-launch kernel serves padded order ld (0: neither fits).
+struct SinglePlan {
+    bool flow = false;
+    int groups = 0;
+    size_t word_bytes = 0;  // ready or barrier words
+    size_t pub_bytes = 0;   // the dataflow kernel's two publication matrices
+};
+template <class Ar>
+apsp_status_t single_plan(int dev, int64_t ld, SinglePlan *out) {
+    int flow_cap = 0, phased_cap = 0;
+    apsp_status_t st = coop_capacity(reinterpret_cast<const void *>(&rounds_flow_kernel<Ar>), dev, &flow_cap);
+    if (st == APSP_SUCCESS)
+        st = coop_capacity(reinterpret_cast<const void *>(&rounds_single_kernel<Ar>), dev, &phased_cap);
+    if (st != APSP_SUCCESS) return st;
+    const int64_t R = ld / kSingleBS, m = R - 1;
+    SinglePlan p;
+#ifndef APSP_SINGLE_PHASED_ONLY
+    if (R * R <= flow_cap) {
+        p.flow = true;
+        p.groups = (int)(R * R);
+        p.word_bytes = flow_word_bytes((int)R);
+        p.pub_bytes = 2 * (size_t)(ld * ld) * 4;
+        *out = p;
+        return APSP_SUCCESS;
+    }
+#endif
+    if (phased_cap > 0) {
+        const int64_t want = std::max<int64_t>(1, std::max(m * m, 2 * m));
+        p.groups = (int)std::min<int64_t>(std::min<int64_t>(want, phased_cap), kSingleMaxGroups);
+        p.word_bytes = kSingleWordBytes;
+    }
+    *out = p;
+    return APSP_SUCCESS;
+}
+
+template <class Ar>
+apsp_status_t run_single(void *X, int64_t ld, const Ar &ar, const SinglePlan &plan, void *ws, int32_t *status,
+                         const int32_t *skip, hipStream_t s) {
+    ProfScope ps(kSingle, (double)ld * (double)ld * (double)ld, s);
+    void *x = X;
+    int64_t l = ld;
+    Ar a = ar;
+    int32_t *stt = status;
+    const int32_t *sk = skip;
+    if (plan.flow) {
+        uint32_t *wd = (uint32_t *)((char *)ws + plan.pub_bytes);
+        void *prow = ws, *pcol = (char *)ws + plan.pub_bytes / 2;
+        void *args[] = {&x, &l, &a, &wd, &prow, &pcol, &stt, &sk};
+        APSP_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&rounds_flow_kernel<Ar>),
+                                            dim3(plan.groups), dim3(kSingleThreads), args, 0, s));
+    } else {
+        uint32_t *wd = (uint32_t *)ws;
+        void *args[] = {&x, &l, &a, &wd, &stt, &sk};
+        APSP_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&rounds_single_kernel<Ar>),
+                                            dim3(plan.groups), dim3(kSingleThreads), args, 0, s));
+    }
+    return APSP_SUCCESS;
+}
+
 template <class T>
 apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
                           const apsp_options_t &opt, void *ext_ws, size_t ext_bytes) {
@@ -1228,14 +1719,41 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
     const int64_t ld = (n + bs - 1) / bs * bs;
     int32_t *status = opt.d_status;
     const int32_t *skip = nullptr;
-    if (status) enq(status_init_kernel, dim3(1), dim3(1), s, status);
+    const bool f32w = std::is_same_v<T, int32_t> && use_f32w(n, APSP_INT32, with_pred, opt.arith);
+    using ArPlain = std::conditional_t<std::is_same_v<T, int32_t>, ArI32, ArF32>;
+    bool single = single_applies(ld, bs, tt, with_pred, f32w, opt.schedule, ext_ws != nullptr);
+    SinglePlan plan;
+    if (single) {
+        apsp_status_t st = single_plan<ArPlain>(dev, ld, &plan);
+        if (st != APSP_SUCCESS) return st;
+        if (plan.groups <= 0) {
+            if (opt.schedule == 3) return APSP_ERROR_INVALID_ARGUMENT;
+            single = false;
+        }
+    }
+    // single-launch schedule: [work matrix if padded][publication matrices][words]
+    void *single_ws = nullptr, *single_aux = nullptr;
+    const size_t single_mat = (ld == n && (uintptr_t)dist % 16 == 0) ? 0 : (size_t)(ld * ld) * sizeof(T);
+    if (single) {
+        apsp_status_t st = workspace(dev, s, single_mat + plan.pub_bytes + plan.word_bytes, &single_ws);
+        if (st != APSP_SUCCESS) return st;
+        single_aux = (char *)single_ws + single_mat;
+        uint32_t *words = (uint32_t *)((char *)single_aux + plan.pub_bytes);
+        if (plan.flow) {
+            const int count = (int)(plan.word_bytes / 4);
+            enq(flow_init_kernel, dim3(std::min(64, (count + 255) / 256)), dim3(256), s, words, count, status);
+        } else {
+            enq(single_init_kernel, dim3(1), dim3(256), s, words, status);
+        }
+    } else if (status) {
+        enq(status_init_kernel, dim3(1), dim3(1), s, status);
+    }
     if (opt.validate) {
         enq((validate_kernel<T>), dim3(grid_for(n * n)), dim3(256), s, dist, n,
                            apsp_weight_bound(n), status);
         skip = status;
     }
     constexpr T inf = std::is_same_v<T, int32_t> ? T(kInf32) : T(__builtin_huge_valf());
-    const bool f32w = std::is_same_v<T, int32_t> && use_f32w(n, APSP_INT32, with_pred, opt.arith);
     if (!f32w && opt.d_arith) enq(store_word_kernel, dim3(1), dim3(1), s, opt.d_arith, 0);
     if constexpr (std::is_same_v<T, int32_t>) {
         if (f32w) {
@@ -1335,21 +1853,24 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         T *X = dist;
         const bool inplace = (ld == n) && ((uintptr_t)dist % 16 == 0);
         if (!inplace) {
-            void *w = nullptr;
-            apsp_status_t st = workspace(dev, s, (size_t)(ld * ld) * sizeof(T), &w);
-            if (st != APSP_SUCCESS) return st;
+            void *w = single_ws;
+            if (!single) {
+                apsp_status_t st = workspace(dev, s, (size_t)(ld * ld) * sizeof(T), &w);
+                if (st != APSP_SUCCESS) return st;
+            }
             X = (T *)w;
             enq((pad_in_kernel<T>), dim3(grid_for(ld * ld)), dim3(256), s, dist, n, X,
                                ld, inf, skip);
         }
         apsp_status_t st;
-        if constexpr (std::is_same_v<T, int32_t>)
-            st = run_rounds_bs<ArI32>(bs, tt, lookahead, X, ld, ArI32{}, s, skip);
+        if (single)
+            st = run_single<ArPlain>(X, ld, ArPlain{}, plan, single_aux, status, skip, s);
         else
-            st = run_rounds_bs<ArF32>(bs, tt, lookahead, X, ld, ArF32{}, s, skip);
+            st = run_rounds_bs<ArPlain>(bs, tt, lookahead, X, ld, ArPlain{}, s, skip);
         if (st != APSP_SUCCESS) return st;
+        // (a failed single-launch wait leaves APSP_ERROR_TIMEOUT in status: no wrap-up then)
         enq((finalize_kernel<T>), dim3(grid_for(n * n)), dim3(256), s, X, ld, dist, n,
-                           status, skip);
+                           status, single && status ? (const int32_t *)status : skip);
     } else {
         // ld^2 8-byte elements, then one int32 mode word
         void *w = nullptr;
@@ -1387,7 +1908,13 @@ size_t solve_work_bytes(int64_t n, apsp_dtype_t dtype, bool with_pred) {
 namespace {
 
 apsp_status_t solve_direct(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dtype, hipStream_t s,
-                           const apsp_options_t &opt, void *ws, size_t ws_bytes) {
+                           const apsp_options_t &opt_in, void *ws, size_t ws_bytes) {
+    apsp_options_t opt = opt_in;
+    if (opt.schedule == 3) {  // the single-launch schedule's one configuration
+        opt.block_size = 64;
+        opt.thread_tile = 4;
+        if (dtype == APSP_INT32) opt.arith = 1;
+    }
     if (dtype == APSP_INT32) return solve_typed<int32_t>((int32_t *)dist, pred, n, s, opt, ws, ws_bytes);
     return solve_typed<float>((float *)dist, pred, n, s, opt, ws, ws_bytes);
 }
@@ -1490,7 +2017,13 @@ apsp_status_t check_options(int64_t n, apsp_dtype_t dtype, bool with_pred, const
     // takes 128-wide blocks)
     if (opt.block_size == 256 && with_pred && !use_pp(n, true, opt.arith)) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.schedule < 0 || opt.schedule > 2) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.schedule < 0 || opt.schedule > 3) return APSP_ERROR_INVALID_ARGUMENT;
+    // the single-launch schedule: distances on 64-wide blocks with 4 x 4 thread
+    // tiles, int32 weights in int32 arithmetic, issued directly
+    if (opt.schedule == 3 &&
+        (with_pred || n > kSingleMaxN || (opt.block_size != 0 && opt.block_size != 64) ||
+         (opt.thread_tile != 0 && opt.thread_tile != 4) || opt.use_graph || (dtype == APSP_INT32 && opt.arith == 2)))
+        return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.phase1 < 0 || opt.phase1 > 2) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.phase1 == 2 && opt.block_size != 256) return APSP_ERROR_INVALID_ARGUMENT;
     return APSP_SUCCESS;
@@ -1587,7 +2120,7 @@ apsp_status_t apsp_solve_noalloc(void *dist, int32_t *pred, int64_t n, apsp_dtyp
     if (bad != APSP_SUCCESS) return bad;
     // rounds in order on the caller's stream: the two-stream split would need a
     // second stream and events, a hipGraph an instantiation
-    if (opt.use_graph || opt.schedule == 2) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.use_graph || opt.schedule >= 2) return APSP_ERROR_INVALID_ARGUMENT;
     opt.schedule = 1;
     if (n == 0) return APSP_SUCCESS;
     if (!dist || ((uintptr_t)dist % 4) != 0 || ((uintptr_t)pred % 4) != 0) return APSP_ERROR_INVALID_ARGUMENT;
@@ -1625,8 +2158,9 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out) {
         recs.swap(g_prof);
     }
     *out = apsp_profile_t{};
-    apsp_kernel_time_t *slot[7] = {&out->phase1,       &out->phase2,       &out->phase3,        &out->other,
-                                   &out->phase3_cross, &out->pred_product, &out->phase1_blocked};
+    apsp_kernel_time_t *slot[8] = {&out->phase1,       &out->phase2,       &out->phase3,
+                                   &out->other,        &out->phase3_cross, &out->pred_product,
+                                   &out->phase1_blocked, &out->single_launch};
     apsp_status_t st = APSP_SUCCESS;
     for (auto &r : recs) {
         float ms = 0.f;
@@ -1706,6 +2240,7 @@ apsp_status_t stepper_create(int64_t n, apsp_dtype_t dtype, bool want_pred, cons
     opt.use_graph = 0;  // a stepper issues recorded operations itself
     apsp_status_t st = check_options(n, dtype, want_pred, opt);
     if (st != APSP_SUCCESS) return st;
+    if (opt.schedule == 3) return APSP_ERROR_INVALID_ARGUMENT;  // one launch has no slices
     auto *p = new apsp_stepper();
     p->n = n;
     p->dtype = dtype;

@@ -59,8 +59,23 @@ def test_host_side_argument_errors():
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, tile4_bs128) == apsp.INVALID_ARGUMENT
     bad_arith = apsp.Options(0, 0, 0, 0, 0, 3, None)
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_arith) == apsp.INVALID_ARGUMENT
-    bad_schedule = apsp.Options(0, 0, 0, 3, 0, 0, None)
+    bad_schedule = apsp.Options(0, 0, 0, 4, 0, 0, None)
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_schedule) == apsp.INVALID_ARGUMENT
+    # the single-launch schedule (3): distances, 64-wide blocks, 4 x 4 thread
+    # tiles, int32 arithmetic for int32 weights, issued directly
+    for kw in (dict(block_size=128), dict(thread_tile=8), dict(use_graph=1), dict(arith=2)):
+        o = apsp.Options(0, kw.get("block_size", 0), kw.get("thread_tile", 0), 3, kw.get("use_graph", 0),
+                         kw.get("arith", 0), None)
+        assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, o) == apsp.INVALID_ARGUMENT, kw
+    single = apsp.Options(0, 0, 0, 3, 0, 0, None)
+    assert apsp.solve_raw(fake, None, 16385, apsp.INT32, None, single) == apsp.INVALID_ARGUMENT
+    assert apsp.solve_raw(fake, fake, 10, apsp.INT32, None, single) == apsp.INVALID_ARGUMENT
+    float_arith2 = apsp.Options(0, 0, 0, 3, 0, 2, None)  # arith is ignored for float32 weights
+    assert apsp.solve_raw(fake, fake, 10, apsp.FLOAT32, None, float_arith2) == apsp.INVALID_ARGUMENT
+    L.apsp_stepper_create.restype = ctypes.c_int
+    stp = ctypes.c_void_p()
+    assert L.apsp_stepper_create(100, apsp.INT32, 0, ctypes.byref(single), ctypes.byref(stp)) == \
+        apsp.INVALID_ARGUMENT
     bad_phase1 = apsp.Options(0, 256, 0, 0, 0, 0, None, None, 3)
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_phase1) == apsp.INVALID_ARGUMENT
     # the blocked diagonal closure needs 256-wide blocks
@@ -80,6 +95,7 @@ def test_host_side_argument_errors():
         apsp.INVALID_ARGUMENT
     split = apsp.Options(0, 0, 0, 2, 0, 0, None)
     assert L.apsp_solve_noalloc(fake, None, 100, apsp.INT32, None, ctypes.byref(split)) == apsp.INVALID_ARGUMENT
+    assert L.apsp_solve_noalloc(fake, None, 100, apsp.INT32, None, ctypes.byref(single)) == apsp.INVALID_ARGUMENT
     graph = apsp.Options(0, 0, 0, 0, 1, 0, None)
     assert L.apsp_solve_noalloc(fake, None, 100, apsp.INT32, None, ctypes.byref(graph)) == apsp.INVALID_ARGUMENT
     assert L.apsp_solve_noalloc(fake, None, 0, apsp.INT32, None, None) == apsp.SUCCESS
