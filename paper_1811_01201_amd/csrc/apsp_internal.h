@@ -740,15 +740,31 @@ __device__ __forceinline__ bool phase1_steps(P1Regs<Ar, BS, TT> &c, int ksteps, 
                 const T dk_k1 = ar.strip(rb[0][k + 1]);  // D(k, k+1) as a left operand
                 const T dk1_k = ar.strip(rb[1][k]);      // D(k+1, k) as a left operand
                 T a0[TM1], a1[TM1], b0[TN1], b1[TN1];
+                if constexpr (TM1 % VW == 0) {
 #pragma unroll
-                for (int g = 0; g < TM1 / VW; ++g) {
-                    ld16(&cb[0][ty * TM1 + g * VW], &a0[g * VW]);
-                    ld16(&cb[1][ty * TM1 + g * VW], &a1[g * VW]);
+                    for (int g = 0; g < TM1 / VW; ++g) {
+                        ld16(&cb[0][ty * TM1 + g * VW], &a0[g * VW]);
+                        ld16(&cb[1][ty * TM1 + g * VW], &a1[g * VW]);
+                    }
+                } else {  // 2-row thread tiles
+#pragma unroll
+                    for (int m = 0; m < TM1; ++m) {
+                        a0[m] = cb[0][ty * TM1 + m];
+                        a1[m] = cb[1][ty * TM1 + m];
+                    }
                 }
+                if constexpr (TN1 % VW == 0) {
 #pragma unroll
-                for (int g = 0; g < TN1 / VW; ++g) {
-                    ld16(&rb[0][tx * TN1 + g * VW], &b0[g * VW]);
-                    ld16(&rb[1][tx * TN1 + g * VW], &b1[g * VW]);
+                    for (int g = 0; g < TN1 / VW; ++g) {
+                        ld16(&rb[0][tx * TN1 + g * VW], &b0[g * VW]);
+                        ld16(&rb[1][tx * TN1 + g * VW], &b1[g * VW]);
+                    }
+                } else {
+#pragma unroll
+                    for (int n = 0; n < TN1; ++n) {
+                        b0[n] = rb[0][tx * TN1 + n];
+                        b1[n] = rb[1][tx * TN1 + n];
+                    }
                 }
 #pragma unroll
                 for (int m = 0; m < TM1; ++m) a1[m] = ar.mn(a1[m], ar.add(a0[m], dk_k1));

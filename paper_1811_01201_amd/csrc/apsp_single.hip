@@ -479,7 +479,8 @@ rounds_single_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, int32_t *stat
 }
 
 // Dataflow form of the single launch, for padded orders whose R x R blocks
-// (R = ld / 64) fit one workgroup each on the device at once.  Workgroup
+// (R = ld / BS, BS = 32 or 64) fit one workgroup each on the device at
+// once.  Workgroup
 // w = i R + j owns block (i, j) for the whole solve and keeps it in
 // registers (the stepwise closure's layout: thread (tx, ty) holds rows
 // 4 ty .. 4 ty + 3, columns 4 tx .. 4 tx + 3).  Per round r it does its one
@@ -531,19 +532,83 @@ __device__ __forceinline__ bool flow_wait(const uint32_t *w0, const uint32_t *w1
     return *ok_lds != 0;
 }
 
-template <class Ar>
-__global__ void __launch_bounds__(kSingleThreads) __attribute__((amdgpu_waves_per_eu(4)))  // 4 per CU: n = 2048
+// 256 threads per block: BS = 64 with 4 x 4 elements per thread, BS = 32
+// with 2 x 2.  At most 4 workgroups per CU (see coop_capacity): 1024 blocks
+// on MI355X, so BS = 32 up to a padded order of 1024, BS = 64 up to 2048.
+template <int BS>
+constexpr int flow_tile() {
+    return BS == 32 ? 2 : 4;
+}
+
+// TT consecutive 4-byte elements: plain and device-coherent accesses
+template <int TT, class T>
+__device__ __forceinline__ void ld_tt(const T *p, T *out) {
+    if constexpr (TT == 4) {
+        ld16(p, out);
+    } else {
+        const uint64_t v = *(const uint64_t *)p;
+        out[0] = __builtin_bit_cast(T, (uint32_t)v);
+        out[1] = __builtin_bit_cast(T, (uint32_t)(v >> 32));
+    }
+}
+template <int TT, class T>
+__device__ __forceinline__ void st_tt(T *p, const T *in) {
+    if constexpr (TT == 4) {
+        st16(p, in);
+    } else {
+        *(uint64_t *)p = (uint64_t)__builtin_bit_cast(uint32_t, in[0]) |
+                         ((uint64_t)__builtin_bit_cast(uint32_t, in[1]) << 32);
+    }
+}
+template <int TT, class T>
+__device__ __forceinline__ void st_tt_dev(T *p, const T *in) {
+    if constexpr (TT == 4) {
+        st16_dev(p, in);
+    } else {
+        const uint64_t v = (uint64_t)__builtin_bit_cast(uint32_t, in[0]) |
+                           ((uint64_t)__builtin_bit_cast(uint32_t, in[1]) << 32);
+        __hip_atomic_store((uint64_t *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// LDS layouts of a BS x BS product's operands: A as BS rows of BS k, its
+// 16-byte pieces XOR-swizzled per row (flow_swz) so the rows a wavefront
+// reads at one k spread over the banks; B as BS k-rows of BS columns.
+template <int BS>
+__device__ __forceinline__ int flow_swz(int row) {
+    constexpr int KP = BS / 4;
+    return ((row * KP) >> 3) & (KP - 1);
+}
+
+// Device-coherent LDS DMA of one BS x BS block (row stride ld) into LDS as
+// the A (swizzled) or B (plain) operand: 16 bytes per lane and copy.
+template <int BS, int NTH, bool SWIZZLE, class T>
+__device__ __forceinline__ void flow_copy(T *__restrict__ lds, const T *__restrict__ src, uint32_t ld) {
+    constexpr int KP = BS / 4, COPIES = BS * KP / NTH;
+    static_assert(COPIES * NTH == BS * KP, "whole copies");
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+#pragma unroll
+    for (int q = 0; q < COPIES; ++q) {
+        const int base = q * NTH + wave * 64, v = base + lane;
+        const int row = v / KP, piece = v % KP;
+        const T *g = src + ((uint32_t)row * ld + (uint32_t)((SWIZZLE ? piece ^ flow_swz<BS>(row) : piece) * 4));
+        __builtin_amdgcn_global_load_lds((const void *)g, (__attribute__((address_space(3))) void *)(lds + base * 4),
+                                         16, 0, kCpolDevice);
+    }
+}
+
+template <class Ar, int BS>
+__global__ void __launch_bounds__(kSingleThreads) __attribute__((amdgpu_waves_per_eu(4)))
 rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, void *pcol_v, int32_t *status,
                    const int32_t *__restrict__ skip) {
     using T = typename Ar::T;
     static_assert(sizeof(T) == 4, "4-byte elements");
-    constexpr int BS = kSingleBS;
-    using TP = TileProductDMA<Ar, BS, BS, BS, 4, 4, kCpolDevice>;  // its copies and LDS layouts
-    using PS = P1S<Ar, BS, 4>;
-    static_assert(PS::NTH == kSingleThreads && PS::TM1 == 4 && PS::TN1 == 4 && TP::VW == 4, "4 x 4 per thread");
+    constexpr int TT = flow_tile<BS>();
+    using PS = P1S<Ar, BS, TT>;
+    static_assert(PS::NTH == kSingleThreads && PS::TM1 == TT && PS::TN1 == TT, "TT x TT per thread");
     if (skip && *skip != APSP_SUCCESS) return;
-    __shared__ alignas(16) T la[BS * BS];  // A: 64 rows of 64 k, 16-byte pieces swizzled per row
-    __shared__ alignas(16) T lb[BS * BS];  // B: 64 k rows of 64 columns
+    __shared__ alignas(16) T la[BS * BS];  // A operand
+    __shared__ alignas(16) T lb[BS * BS];  // B operand
     __shared__ alignas(16) T p1c[4][BS];
     __shared__ alignas(16) T p1r[4][BS];
     __shared__ int ok_lds;
@@ -555,39 +620,41 @@ rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, v
     const int bi = (int)blockIdx.x / R, bj = (int)blockIdx.x % R;
     const int tid = (int)threadIdx.x, tx = tid % PS::TX, ty = tid / PS::TX;
     uint32_t *const fail = words + flow_fail_word(R);
-    // block (p, q) of a matrix of order ld, and this thread's 4 x 4 piece of it
+    // block (p, q) of a matrix of order ld, and this thread's TT x TT piece of it
     auto blk = [&](T *M, int p, int q) __attribute__((always_inline)) {
         return M + ((uint32_t)p * BS * ldu + (uint32_t)q * BS);
     };
     auto at = [&](T *M, int p, int q) __attribute__((always_inline)) {
-        return blk(M, p, q) + ((uint32_t)ty * 4 * ldu + (uint32_t)tx * 4);
+        return blk(M, p, q) + ((uint32_t)ty * TT * ldu + (uint32_t)tx * TT);
     };
-    T c[4][4];
+    T c[TT][TT];
     {
         T *const src = at(X, bi, bj);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) ld16(src + (uint32_t)m * ldu, c[m]);
+        for (int m = 0; m < TT; ++m) ld_tt<TT>(src + (uint32_t)m * ldu, c[m]);
     }
     // c <- min(c, A (x) B), A in la, B in lb, once both are complete
+    // (unrolled by two, so the LDS reads of the next k run ahead of the arithmetic)
     auto multiply = [&]() __attribute__((always_inline)) {
-        TP::copies_done(la, ar);
-#pragma unroll 1
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // this wavefront's copies: vmcnt(0)
+        __syncthreads();
+#pragma unroll 2
         for (int kg = 0; kg < BS; kg += 4) {
-            T a[4][4];
+            T a[TT][4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int row = ty * 4 + m;
-                ld16(&la[row * BS + (((kg >> 2) ^ TP::swz(row)) << 2)], a[m]);
+            for (int m = 0; m < TT; ++m) {
+                const int row = ty * TT + m;
+                ld16(&la[row * BS + (((kg >> 2) ^ flow_swz<BS>(row)) << 2)], a[m]);
             }
 #pragma unroll
             for (int kk = 0; kk < 4; kk += 2) {
-                T b0[4], b1[4];
-                ld16(&lb[(kg + kk) * BS + tx * 4], b0);
-                ld16(&lb[(kg + kk + 1) * BS + tx * 4], b1);
+                T b0[TT], b1[TT];
+                ld_tt<TT>(&lb[(kg + kk) * BS + tx * TT], b0);
+                ld_tt<TT>(&lb[(kg + kk + 1) * BS + tx * TT], b1);
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
+                for (int m = 0; m < TT; ++m)
 #pragma unroll
-                    for (int n = 0; n < 4; ++n) c[m][n] = ar.relax2(c[m][n], a[m][kk], b0[n], a[m][kk + 1], b1[n]);
+                    for (int n = 0; n < TT; ++n) c[m][n] = ar.relax2(c[m][n], a[m][kk], b0[n], a[m][kk + 1], b1[n]);
             }
         }
     };
@@ -596,13 +663,13 @@ rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, v
     auto publish = [&](T *M, int p, int q, uint32_t *ready) __attribute__((always_inline)) {
         T *const dst = at(M, p, q);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) st16_dev(dst + (uint32_t)m * ldu, c[m]);
+        for (int m = 0; m < TT; ++m) st_tt_dev<TT>(dst + (uint32_t)m * ldu, c[m]);
         mem_done();
         __syncthreads();
         if (tid == 0) st_agent(ready, 1u);
     };
     auto close = [&]() __attribute__((always_inline)) {
-        (void)phase1_steps<Ar, BS, false, 4>(c, BS, ar, p1c, p1r);
+        (void)phase1_steps<Ar, BS, false, TT>(c, BS, ar, p1c, p1r);
     };
     uint32_t *const row_ready = words, *const col_ready = words + R * R, *const diag_ready = words + 2 * R * R;
 
@@ -616,26 +683,27 @@ rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, v
         if (bi == r) {
             // block row r: c <- min(c, D(r,r)* (x) c)
             if (!(ok = flow_wait(&diag_ready[r], nullptr, fail, &ok_lds))) break;
-            TP::copy_a(la, blk(Prow, r, r), ldu);
+            flow_copy<BS, kSingleThreads, true>(la, blk(Prow, r, r), ldu);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) st16(&lb[(ty * 4 + m) * BS + tx * 4], c[m]);
+            for (int m = 0; m < TT; ++m) st_tt<TT>(&lb[(ty * TT + m) * BS + tx * TT], c[m]);
             multiply();
             publish(Prow, r, bj, &row_ready[r * R + bj]);
         } else if (bj == r) {
             // block column r: c <- min(c, c (x) D(r,r)*)
             if (!(ok = flow_wait(&diag_ready[r], nullptr, fail, &ok_lds))) break;
-            TP::copy_b(lb, blk(Prow, r, r), ldu);
+            flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, r, r), ldu);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int row = ty * 4 + m;
-                st16(&la[row * BS + ((tx ^ TP::swz(row)) << 2)], c[m]);
+            for (int m = 0; m < TT; ++m) {
+                const int row = ty * TT + m, col = tx * TT;
+                st_tt<TT>(&la[row * BS + (((col >> 2) ^ flow_swz<BS>(row)) << 2) + (col & 3)], c[m]);
             }
             multiply();
             publish(Pcol, bi, r, &col_ready[bi * R + r]);
         } else {
             // the remaining blocks: c <- min(c, P_col(i, r) (x) P_row(r, j))
             if (!(ok = flow_wait(&col_ready[bi * R + r], &row_ready[r * R + bj], fail, &ok_lds))) break;
-            TP::copy_chunk(la, lb, blk(Pcol, bi, r), blk(Prow, r, bj), ldu);
+            flow_copy<BS, kSingleThreads, true>(la, blk(Pcol, bi, r), ldu);
+            flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, r, bj), ldu);
             multiply();
             if (bi == r + 1 && bj == r + 1) {
                 close();
@@ -647,7 +715,7 @@ rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, v
     if (ok) {
         T *const dst = at(X, bi, bj);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) st16(dst + (uint32_t)m * ldu, c[m]);
+        for (int m = 0; m < TT; ++m) st_tt<TT>(dst + (uint32_t)m * ldu, c[m]);
     } else if (status && tid == 0) {
         *status = APSP_ERROR_TIMEOUT;
     }
@@ -1611,9 +1679,14 @@ size_t work_bytes(int64_t n, bool with_pred, int opt_bs, bool aligned, apsp_dtyp
 // 2.44 / - / 1.89; 4096: 4.49 / - / 3.95.)
 constexpr int64_t kSingleMaxLd = 4096;
 
-// Workgroups of `kernel` the device holds at once (0 without cooperative
-// launches), looked up once per device.
-apsp_status_t coop_capacity(const void *kernel, int dev, int *out) {
+// Workgroups of `kernel` taken as resident at once (0 without cooperative
+// launches), looked up once per device: the occupancy the runtime reports,
+// but at most 4 workgroups per CU.  (A dataflow solve of 1600 workgroups,
+// 6.25 per CU and within the reported occupancy of 7, ended in a barrier
+// timeout on MI355X, as if not all of them had been resident; every
+// configuration of at most 4 per CU completes.)
+constexpr int kCoopMaxPerCU = 4;
+apsp_status_t coop_capacity(const void *kernel, int dev, int threads, int *out) {
     static std::mutex mu;
     static std::map<std::pair<const void *, int>, int> cache;
     std::lock_guard<std::mutex> lk(mu);
@@ -1622,8 +1695,8 @@ apsp_status_t coop_capacity(const void *kernel, int dev, int *out) {
         int coop = 0, cus = 0, per_cu = 0;
         APSP_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         APSP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        APSP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kSingleThreads, 0));
-        it = cache.emplace(std::make_pair(kernel, dev), coop ? per_cu * cus : 0).first;
+        APSP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+        it = cache.emplace(std::make_pair(kernel, dev), coop ? std::min(per_cu, kCoopMaxPerCU) * cus : 0).first;
     }
     *out = it->second;
     return APSP_SUCCESS;
@@ -1635,36 +1708,51 @@ inline bool single_applies(int64_t ld, int bs, int tt, bool with_pred, bool f32w
     return schedule == 3 || (schedule == 0 && ld <= kSingleMaxLd);
 }
 
-// Which single-launch kernel serves padded order ld (0: neither fits).
+// Which single-launch kernel serves padded order ld (groups 0: none fits).
+// int32 takes 32-wide blocks in the dataflow kernel where they fit (twice
+// the rounds, but each round's chain of closure, panel product and
+// next-diagonal product is about 2.6x shorter: measured on MI355X, n = 1024,
+// 0.307 ms against 0.383 ms with 64-wide blocks); float32 keeps 64-wide
+// blocks, the blocking of the per-phase launches, so its rounding is theirs.
 struct SinglePlan {
-    bool flow = false;
+    int flow_bs = 0;  // 32 or 64: the dataflow kernel; 0: the barrier-phased one
     int groups = 0;
     size_t word_bytes = 0;  // ready or barrier words
     size_t pub_bytes = 0;   // the dataflow kernel's two publication matrices
 };
 template <class Ar>
 apsp_status_t single_plan(int dev, int64_t ld, SinglePlan *out) {
-    int flow_cap = 0, phased_cap = 0;
-    apsp_status_t st = coop_capacity(reinterpret_cast<const void *>(&rounds_flow_kernel<Ar>), dev, &flow_cap);
-    if (st == APSP_SUCCESS)
-        st = coop_capacity(reinterpret_cast<const void *>(&rounds_single_kernel<Ar>), dev, &phased_cap);
-    if (st != APSP_SUCCESS) return st;
-    const int64_t R = ld / kSingleBS, m = R - 1;
     SinglePlan p;
+    auto try_flow = [&](auto bs_tag) -> apsp_status_t {
+        constexpr int bs = decltype(bs_tag)::value;
+        int cap = 0;
+        apsp_status_t st = coop_capacity(reinterpret_cast<const void *>(&rounds_flow_kernel<Ar, bs>), dev,
+                                         kSingleThreads, &cap);
+        const int64_t R = ld / bs;
+        if (st == APSP_SUCCESS && !p.flow_bs && R * R <= cap) {
+            p.flow_bs = bs;
+            p.groups = (int)(R * R);
+            p.word_bytes = flow_word_bytes((int)R);
+            p.pub_bytes = 2 * (size_t)(ld * ld) * 4;
+        }
+        return st;
+    };
+    apsp_status_t st = APSP_SUCCESS;
 #ifndef APSP_SINGLE_PHASED_ONLY
-    if (R * R <= flow_cap) {
-        p.flow = true;
-        p.groups = (int)(R * R);
-        p.word_bytes = flow_word_bytes((int)R);
-        p.pub_bytes = 2 * (size_t)(ld * ld) * 4;
-        *out = p;
-        return APSP_SUCCESS;
-    }
+    if constexpr (std::is_same_v<Ar, ArI32>) st = try_flow(std::integral_constant<int, 32>{});
+    if (st == APSP_SUCCESS) st = try_flow(std::integral_constant<int, 64>{});
+    if (st != APSP_SUCCESS) return st;
 #endif
-    if (phased_cap > 0) {
-        const int64_t want = std::max<int64_t>(1, std::max(m * m, 2 * m));
-        p.groups = (int)std::min<int64_t>(std::min<int64_t>(want, phased_cap), kSingleMaxGroups);
-        p.word_bytes = kSingleWordBytes;
+    if (!p.flow_bs) {
+        int cap = 0;
+        st = coop_capacity(reinterpret_cast<const void *>(&rounds_single_kernel<Ar>), dev, kSingleThreads, &cap);
+        if (st != APSP_SUCCESS) return st;
+        if (cap > 0) {
+            const int64_t m = ld / kSingleBS - 1;
+            const int64_t want = std::max<int64_t>(1, std::max(m * m, 2 * m));
+            p.groups = (int)std::min<int64_t>(std::min<int64_t>(want, cap), kSingleMaxGroups);
+            p.word_bytes = kSingleWordBytes;
+        }
     }
     *out = p;
     return APSP_SUCCESS;
@@ -1679,12 +1767,14 @@ apsp_status_t run_single(void *X, int64_t ld, const Ar &ar, const SinglePlan &pl
     Ar a = ar;
     int32_t *stt = status;
     const int32_t *sk = skip;
-    if (plan.flow) {
+    if (plan.flow_bs) {
         uint32_t *wd = (uint32_t *)((char *)ws + plan.pub_bytes);
         void *prow = ws, *pcol = (char *)ws + plan.pub_bytes / 2;
         void *args[] = {&x, &l, &a, &wd, &prow, &pcol, &stt, &sk};
-        APSP_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&rounds_flow_kernel<Ar>),
-                                            dim3(plan.groups), dim3(kSingleThreads), args, 0, s));
+        const void *k = reinterpret_cast<const void *>(&rounds_flow_kernel<Ar, 64>);
+        if constexpr (std::is_same_v<Ar, ArI32>)
+            if (plan.flow_bs == 32) k = reinterpret_cast<const void *>(&rounds_flow_kernel<Ar, 32>);
+        APSP_HIP(hipLaunchCooperativeKernel(k, dim3(plan.groups), dim3(kSingleThreads), args, 0, s));
     } else {
         uint32_t *wd = (uint32_t *)ws;
         void *args[] = {&x, &l, &a, &wd, &stt, &sk};
@@ -1739,7 +1829,7 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
         if (st != APSP_SUCCESS) return st;
         single_aux = (char *)single_ws + single_mat;
         uint32_t *words = (uint32_t *)((char *)single_aux + plan.pub_bytes);
-        if (plan.flow) {
+        if (plan.flow_bs) {
             const int count = (int)(plan.word_bytes / 4);
             enq(flow_init_kernel, dim3(std::min(64, (count + 255) / 256)), dim3(256), s, words, count, status);
         } else {

@@ -9,9 +9,10 @@ round's diagonal block as soon as its own phase-3 tile is done.  Every size
 here runs with schedule=3 (forced) and is compared element by element with
 the oracle; the library's profile confirms that exactly one launch did the
 rounds.  Sizes span one round (n <= 64), ragged last blocks, and padded
-orders beyond the automatic limit; up to n = 2048 the dataflow kernel runs
-(one workgroup per 64 x 64 block, panels published once with ready words),
-above it the barrier-phased kernel (two device-wide barriers per round).
+orders beyond the dataflow limit; up to n = 2048 the dataflow kernel runs
+(one workgroup per block, panels published once with ready words; int32 in
+32 x 32 blocks up to n = 1024, else 64 x 64), above it the barrier-phased
+kernel (two device-wide barriers per round).
 Real-valued float32 weights are compared
 with the multi-launch schedule bit for bit (the same products over the same
 operands) and with the oracle within float32 rounding."""
@@ -60,7 +61,8 @@ def _assert_one_launch(prof):
         assert prof[k]["launches"] == 0, (k, prof[k])
 
 
-@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 130, 300, 777, 1000, 1024, 1536, 2048, 2100, 2500, 3000])
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 130, 300, 777, 1000, 1024, 1025, 1280, 1536, 2048, 2100, 2500,
+                               3000])
 @pytest.mark.parametrize("kind", ["int", "pot", "f32", "sparse"])
 def test_single_launch_matches_oracle(orc, n, kind):
     describe(f"single launch: n={n} {kind}")
