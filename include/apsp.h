@@ -167,14 +167,23 @@ typedef struct {
     int32_t *d_arith;      /* device int32 or NULL: receives 1 if the result came from float32
                               arithmetic (with predecessors: the float32 route held), 0 if
                               from int32 arithmetic (the recurrence) */
-    int32_t phase1;        /* 0 = automatic: with 256-wide blocks from a padded order of
-                              10240, phase 1 is a blocked closure of the diagonal block
+    int32_t phase1;        /* 0 = automatic: the dataflow closure (3) on the exact routes
+                              with 128- or 256-wide blocks; elsewhere, with 256-wide blocks
+                              from a padded order of 10240, phase 1 is a blocked closure of
+                              the diagonal block
                               inside one 256-thread workgroup (four 64-wide sub-rounds),
                               and the two-stream split then issues the rest of phase 3 as
                               one launch per round instead of two; 1 = always the
                               one-step-per-barrier kernel; 2 = always the blocked closure
                               (requires block_size 256; applies to the rounds on 4-byte
-                              distances, the fp64-key recurrence keeps the stepwise kernel) */
+                              distances, the fp64-key recurrence keeps the stepwise kernel);
+                              3 = the dataflow closure: the diagonal block solved by the
+                              blocked schedule over 32-wide sub-blocks, one workgroup per
+                              sub-block in one launch (requires block_size 128 or 256;
+                              applies to the exact routes -- int32 arithmetic and float32
+                              arithmetic on integer data -- and is their automatic choice
+                              for 128- and 256-wide blocks, where the two-stream split then
+                              issues the rest of phase 3 as one launch per round) */
 } apsp_options_t;
 
 /* apsp_solve with options (NULL options = defaults = apsp_solve). */
@@ -264,6 +273,8 @@ typedef struct {
     apsp_kernel_time_t phase1_blocked; /* the phase-1 launches (also counted in phase1) that
                                           were the blocked closure of the diagonal block */
     apsp_kernel_time_t single_launch;  /* the single-launch schedule's kernel (all rounds) */
+    apsp_kernel_time_t phase1_flow;    /* the phase-1 launches (also counted in phase1) that
+                                          were the dataflow closure */
 } apsp_profile_t;
 
 apsp_status_t apsp_profile_begin(void);

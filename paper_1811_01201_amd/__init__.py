@@ -44,7 +44,7 @@ class KernelTime(ctypes.Structure):
 class Profile(ctypes.Structure):
     _fields_ = [("phase1", KernelTime), ("phase2", KernelTime), ("phase3", KernelTime),
                 ("other", KernelTime), ("phase3_cross", KernelTime), ("pred_product", KernelTime),
-                ("phase1_blocked", KernelTime), ("single_launch", KernelTime)]
+                ("phase1_blocked", KernelTime), ("single_launch", KernelTime), ("phase1_flow", KernelTime)]
 
     def as_dict(self):
         out = {}
@@ -187,7 +187,9 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
              cooperative launch (distances, 64-wide blocks, int32 arithmetic
              for int32; automatic for distance solves up to n = 4096).
     phase1 : 0 automatic, 1 the stepwise diagonal kernel, 2 the blocked
-             closure of the diagonal block (block_size=256).
+             closure of the diagonal block (block_size=256), 3 the dataflow
+             closure over 32-wide sub-blocks (block_size 128 or 256; exact
+             routes only, the stepwise kernel elsewhere).
     Returns the host status of the enqueue (raises APSPError unless check=False).
     """
     assert dist.dim() == 2 and dist.shape[0] == dist.shape[1], "dist must be square"

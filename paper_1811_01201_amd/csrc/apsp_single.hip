@@ -499,8 +499,12 @@ rounds_single_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, int32_t *stat
 // reader can see a later round's value.  The operands of every product are
 // those of the multi-launch schedule, so the values are too, bit for bit.
 // Ready words: row(r, j) at r R + j, col(i, r) at R^2 + i R + r, diag(r) at
-// 2 R^2 + r, the fail word at flow_fail_word(R); all zeroed before the launch.
+// 2 R^2 + r, the fail word at flow_fail_word(R), a count of finished
+// workgroups 32 words after it.  All are zero before a launch; the last
+// workgroup to finish zeroes them again, so a launch leaves them ready for
+// the next one.
 __host__ __device__ constexpr int flow_fail_word(int R) { return 2 * R * R + R; }
+__host__ __device__ constexpr int flow_done_word(int R) { return flow_fail_word(R) + 32; }
 __host__ __device__ constexpr size_t flow_word_bytes(int R) { return ((size_t)flow_fail_word(R) + 64) * 4; }
 
 __global__ void flow_init_kernel(uint32_t *words, int count, int32_t *status) {
@@ -599,8 +603,8 @@ __device__ __forceinline__ void flow_copy(T *__restrict__ lds, const T *__restri
 
 template <class Ar, int BS>
 __global__ void __launch_bounds__(kSingleThreads) __attribute__((amdgpu_waves_per_eu(4)))
-rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, void *pcol_v, int32_t *status,
-                   const int32_t *__restrict__ skip) {
+rounds_flow_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *words, void *prow_v, void *pcol_v,
+                   int32_t *status, const int32_t *__restrict__ skip) {
     using T = typename Ar::T;
     static_assert(sizeof(T) == 4, "4-byte elements");
     constexpr int TT = flow_tile<BS>();
@@ -615,23 +619,26 @@ rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, v
     T *const X = (T *)Xv;
     T *const Prow = (T *)prow_v;
     T *const Pcol = (T *)pcol_v;
-    const uint32_t ldu = (uint32_t)ld;
-    const int R = (int)(ld / BS);
+    const uint32_t ordu = (uint32_t)order, stru = (uint32_t)stride;
+    const int R = (int)(order / BS);
     const int bi = (int)blockIdx.x / R, bj = (int)blockIdx.x % R;
     const int tid = (int)threadIdx.x, tx = tid % PS::TX, ty = tid / PS::TX;
     uint32_t *const fail = words + flow_fail_word(R);
-    // block (p, q) of a matrix of order ld, and this thread's TT x TT piece of it
-    auto blk = [&](T *M, int p, int q) __attribute__((always_inline)) {
-        return M + ((uint32_t)p * BS * ldu + (uint32_t)q * BS);
+    // block (p, q) of a matrix with row stride ld (X: stride; the published
+    // matrices: order), and this thread's TT x TT piece of it
+    auto blk = [&](T *M, uint32_t ld, int p, int q) __attribute__((always_inline)) {
+        return M + ((uint32_t)p * BS * ld + (uint32_t)q * BS);
     };
-    auto at = [&](T *M, int p, int q) __attribute__((always_inline)) {
-        return blk(M, p, q) + ((uint32_t)ty * TT * ldu + (uint32_t)tx * TT);
+    auto at = [&](T *M, uint32_t ld, int p, int q) __attribute__((always_inline)) {
+        return blk(M, ld, p, q) + ((uint32_t)ty * TT * ld + (uint32_t)tx * TT);
     };
+    bool big = false;  // a watching policy saw an unsafe operand or result
     T c[TT][TT];
     {
-        T *const src = at(X, bi, bj);
+        T *const src = at(X, stru, bi, bj);
 #pragma unroll
-        for (int m = 0; m < TT; ++m) ld_tt<TT>(src + (uint32_t)m * ldu, c[m]);
+        for (int m = 0; m < TT; ++m) ld_tt<TT>(src + (uint32_t)m * stru, c[m]);
+        big |= any_big(ar, c);
     }
     // c <- min(c, A (x) B), A in la, B in lb, once both are complete
     // (unrolled by two, so the LDS reads of the next k run ahead of the arithmetic)
@@ -661,15 +668,16 @@ rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, v
     // stores this thread's piece into block (p, q) of M, then (once every
     // wavefront's stores are complete) sets the ready word
     auto publish = [&](T *M, int p, int q, uint32_t *ready) __attribute__((always_inline)) {
-        T *const dst = at(M, p, q);
+        big |= any_big(ar, c);
+        T *const dst = at(M, ordu, p, q);
 #pragma unroll
-        for (int m = 0; m < TT; ++m) st_tt_dev<TT>(dst + (uint32_t)m * ldu, c[m]);
+        for (int m = 0; m < TT; ++m) st_tt_dev<TT>(dst + (uint32_t)m * ordu, c[m]);
         mem_done();
         __syncthreads();
         if (tid == 0) st_agent(ready, 1u);
     };
     auto close = [&]() __attribute__((always_inline)) {
-        (void)phase1_steps<Ar, BS, false, TT>(c, BS, ar, p1c, p1r);
+        big |= phase1_steps<Ar, BS, false, TT>(c, BS, ar, p1c, p1r);
     };
     uint32_t *const row_ready = words, *const col_ready = words + R * R, *const diag_ready = words + 2 * R * R;
 
@@ -683,7 +691,7 @@ rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, v
         if (bi == r) {
             // block row r: c <- min(c, D(r,r)* (x) c)
             if (!(ok = flow_wait(&diag_ready[r], nullptr, fail, &ok_lds))) break;
-            flow_copy<BS, kSingleThreads, true>(la, blk(Prow, r, r), ldu);
+            flow_copy<BS, kSingleThreads, true>(la, blk(Prow, ordu, r, r), ordu);
 #pragma unroll
             for (int m = 0; m < TT; ++m) st_tt<TT>(&lb[(ty * TT + m) * BS + tx * TT], c[m]);
             multiply();
@@ -691,7 +699,7 @@ rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, v
         } else if (bj == r) {
             // block column r: c <- min(c, c (x) D(r,r)*)
             if (!(ok = flow_wait(&diag_ready[r], nullptr, fail, &ok_lds))) break;
-            flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, r, r), ldu);
+            flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, r), ordu);
 #pragma unroll
             for (int m = 0; m < TT; ++m) {
                 const int row = ty * TT + m, col = tx * TT;
@@ -702,8 +710,8 @@ rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, v
         } else {
             // the remaining blocks: c <- min(c, P_col(i, r) (x) P_row(r, j))
             if (!(ok = flow_wait(&col_ready[bi * R + r], &row_ready[r * R + bj], fail, &ok_lds))) break;
-            flow_copy<BS, kSingleThreads, true>(la, blk(Pcol, bi, r), ldu);
-            flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, r, bj), ldu);
+            flow_copy<BS, kSingleThreads, true>(la, blk(Pcol, ordu, bi, r), ordu);
+            flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, bj), ordu);
             multiply();
             if (bi == r + 1 && bj == r + 1) {
                 close();
@@ -713,12 +721,25 @@ rounds_flow_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, void *prow_v, v
         __syncthreads();  // LDS free for the next round's operands
     }
     if (ok) {
-        T *const dst = at(X, bi, bj);
+        T *const dst = at(X, stru, bi, bj);
 #pragma unroll
-        for (int m = 0; m < TT; ++m) st_tt<TT>(dst + (uint32_t)m * ldu, c[m]);
+        for (int m = 0; m < TT; ++m) st_tt<TT>(dst + (uint32_t)m * stru, c[m]);
+        if constexpr (Ar::kWatch) {
+            if (big || any_big(ar, c)) ar.raise();
+        }
     } else if (status && tid == 0) {
         *status = APSP_ERROR_TIMEOUT;
     }
+    // the last workgroup to get here clears the words for the next launch
+    // (every other workgroup has finished all its waits)
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t *const done = words + flow_done_word(R);
+        ok_lds = __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)(R * R) - 1;
+    }
+    __syncthreads();
+    if (ok_lds)
+        for (int i = tid; i < flow_fail_word(R) + 64; i += kSingleThreads) st_agent(&words[i], 0u);
 }
 
 // ------------------------------------------------------ set-up / wrap-up
@@ -1313,7 +1334,8 @@ enum KernelKind {
     kPhase3Cross = 4,
     kPredProduct = 5,
     kPhase1Blocked = 6,  // counted under phase1 and phase1_blocked
-    kSingle = 7          // the single-launch schedule's one kernel
+    kSingle = 7,         // the single-launch schedule's one kernel
+    kPhase1Flow = 8      // counted under phase1 and phase1_flow
 };
 struct ProfRecord {
     int kind;
@@ -1457,6 +1479,48 @@ struct Sched {
     int phase1 = 0;
 };
 
+// Phase 1 of 128- and 256-wide blocks as a dataflow closure: the diagonal
+// block is solved by the blocked schedule itself, over 32-wide sub-blocks,
+// in one launch of (BS/32)^2 workgroups (rounds_flow_kernel on the block in
+// place: its order is BS, its row stride ld).  In exact arithmetic (int32,
+// and float32 watched for exactness) its values are those of BS single
+// steps.  An ordinary launch: its few workgroups start as soon as compute
+// units free up, and every workgroup that another one waits for does start
+// (the others' kernels never wait on it), so no co-residency is required;
+// the waits are bounded all the same.  Per (device, stream) scratch: the
+// two 256 x 256 published matrices and the ready words, zeroed once at
+// allocation (each launch leaves its words zeroed again).
+template <class Ar, int BS, class Alt>
+constexpr bool kFlowP1 = (BS == 128 || BS == 256) && std::is_same_v<Alt, NoAlt> &&
+                         (std::is_same_v<Ar, ArI32> || std::is_same_v<Ar, ArF32W>);
+constexpr int kClosureBS = 32, kClosureMax = 256;
+constexpr size_t kClosurePub = (size_t)kClosureMax * kClosureMax * 4;
+constexpr size_t kClosureBytes = 2 * kClosurePub + flow_word_bytes(kClosureMax / kClosureBS);
+std::mutex g_closure_mu;
+std::map<std::pair<int, hipStream_t>, void *> g_closure;
+
+// The calling stream's closure scratch; allocates it unless `create` is
+// false (then *out is null where none exists yet).
+apsp_status_t closure_scratch(int dev, hipStream_t s, bool create, void **out) {
+    std::lock_guard<std::mutex> lk(g_closure_mu);
+    void *&p = g_closure[{dev, s}];
+    if (!p && create) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, kClosureBytes);
+        if (e == hipSuccess) e = hipMemset(q, 0, kClosureBytes);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            if (q) (void)hipFree(q);
+            return APSP_ERROR_OUT_OF_MEMORY;
+        }
+        p = q;
+    }
+    *out = p;
+    return APSP_SUCCESS;
+}
+
+thread_local int32_t *t_status = nullptr;  // the solve's status word (timeouts of the closure)
+
 template <class Ar, class Alt, int BS, int TT>
 apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, const int32_t *mode,
                          hipStream_t s, const int32_t *skip, Sched sc, bool prof) {
@@ -1489,10 +1553,36 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     // n = 10240 ... 12288, -3 % at 16384, -0.4 % at 32768; +7 % at 9216 and
     // +23 % at 8192)
     constexpr bool kBlockedP1 = BS == 256 && sizeof(typename Ar::T) == 4 && std::is_same_v<Alt, NoAlt>;
+    // The dataflow closure (phase1 3, and the automatic choice on the exact
+    // routes: measured on MI355X, int32 distances, ms per solve against the
+    // stepwise kernel / the blocked closure: n = 6144 8.68 / 9.39; 8192
+    // 15.77 / 17.36; 10240 29.16 / 31.36 / 29.67; 16384 111.2 / 113.8 /
+    // 112.0; 32768 882.0 / - / 886.1), where its scratch exists or may be
+    // created: not for apsp_solve_noalloc or a stepper's recording (whose
+    // operations outlive apsp_release_workspace), nor inside a graph capture
+    // that found none -- the other kernels give the same values there
+    // (exact arithmetic).
+    void *closure = nullptr;
+    if constexpr (kFlowP1<Ar, BS, Alt>) {
+        if (!t_noalloc && !t_rec && (sc.phase1 == 3 || sc.phase1 == 0)) {
+            apsp_status_t st = closure_scratch(dev, s, !t_capturing, &closure);
+            if (st != APSP_SUCCESS) return st;
+        }
+    }
     // (phase1 2 forces it wherever it applies, 1 keeps the stepwise kernel)
-    const bool blocked_p1 = kBlockedP1 && (sc.phase1 == 2 || (sc.phase1 == 0 && ld >= 10240));
+    const bool blocked_p1 = kBlockedP1 && (sc.phase1 == 2 || (sc.phase1 == 0 && ld >= 10240 && !closure));
     auto p1 = [&](int r) {
-        ProfScope ps(!prof ? -1 : blocked_p1 ? kPhase1Blocked : kPhase1, bs3, s);
+        ProfScope ps(!prof ? -1 : blocked_p1 ? kPhase1Blocked : closure ? kPhase1Flow : kPhase1, bs3, s);
+        if constexpr (kFlowP1<Ar, BS, Alt>) {
+            if (closure) {
+                constexpr int RC = BS / kClosureBS;
+                char *const c = (char *)closure;
+                enq((rounds_flow_kernel<Ar, kClosureBS>), dim3(RC * RC), dim3(kSingleThreads), s,
+                    (void *)((typename Ar::T *)X + (int64_t)r * BS * ld + (int64_t)r * BS), (int64_t)BS, ld, ar,
+                    (uint32_t *)(c + 2 * kClosurePub), (void *)c, (void *)(c + kClosurePub), t_status, skip);
+                return;
+            }
+        }
         if (blocked_p1) {
             if constexpr (kBlockedP1)
                 enq((phase1_blocked_kernel<Ar>), dim3(1), dim3(256), s, X, ld, (int64_t)r * BS,
@@ -1527,15 +1617,16 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
                                per_xcd, a, b, ar, alt, mode, skip);
     };
     auto p3 = [&](int r, int set, hipStream_t st) { p3_part(r, set, st, 0, p3_count(set, nt, pb)); };
-    // kRest in kRestChunks launches (one with the blocked phase 1): between them the caller stream's
-    // critical-path kernels find free compute units
+    // kRest in kRestChunks launches (one with the blocked phase 1 or the
+    // closure): between them the caller stream's critical-path kernels find
+    // free compute units
     // (one launch where phase 1 is the blocked closure: it fits in a slot a
     // kRest workgroup frees, so no launch boundary is needed to let it in,
     // and one launch has one tail instead of two; measured at n = 32768:
     // kRest 6.58 ms per round in one launch against 2 x 3.37 ms)
     auto p3_rest = [&](int r, hipStream_t st) {
         const int64_t total = p3_count(kRest, nt, pb);
-        const int C = blocked_p1 ? 1 : kRestChunks;
+        const int C = (blocked_p1 || closure) ? 1 : kRestChunks;  // (closure: n = 8192 17.0 -> 15.8 ms)
         for (int c = 0; c < C; ++c) p3_part(r, kRest, st, total * c / C, total * (c + 1) / C);
     };
     if (!aux) {
@@ -1770,7 +1861,7 @@ apsp_status_t run_single(void *X, int64_t ld, const Ar &ar, const SinglePlan &pl
     if (plan.flow_bs) {
         uint32_t *wd = (uint32_t *)((char *)ws + plan.pub_bytes);
         void *prow = ws, *pcol = (char *)ws + plan.pub_bytes / 2;
-        void *args[] = {&x, &l, &a, &wd, &prow, &pcol, &stt, &sk};
+        void *args[] = {&x, &l, &l, &a, &wd, &prow, &pcol, &stt, &sk};
         const void *k = reinterpret_cast<const void *>(&rounds_flow_kernel<Ar, 64>);
         if constexpr (std::is_same_v<Ar, ArI32>)
             if (plan.flow_bs == 32) k = reinterpret_cast<const void *>(&rounds_flow_kernel<Ar, 32>);
@@ -1808,6 +1899,7 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
     if (with_pred && bs == 256 && !use_pp(n, true, opt.arith)) return APSP_ERROR_INVALID_ARGUMENT;
     const int64_t ld = (n + bs - 1) / bs * bs;
     int32_t *status = opt.d_status;
+    t_status = status;
     const int32_t *skip = nullptr;
     const bool f32w = std::is_same_v<T, int32_t> && use_f32w(n, APSP_INT32, with_pred, opt.arith);
     using ArPlain = std::conditional_t<std::is_same_v<T, int32_t>, ArI32, ArF32>;
@@ -2058,6 +2150,11 @@ apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dty
         apsp_status_t st = aux_stream(dev, s, &aux);
         if (st != APSP_SUCCESS) return st;
     }
+    if (opt.phase1 != 1 && opt.phase1 != 2 && n > 2048) {  // and the phase-1 closure's scratch
+        void *c = nullptr;
+        apsp_status_t st = closure_scratch(dev, s, true, &c);
+        if (st != APSP_SUCCESS) return st;
+    }
     GraphKey key{dev,  s,    n,    (int)dtype,   opt.validate, bs, tt, opt.schedule, opt.arith, opt.phase1,
                  dist, pred, opt.d_status, w, opt.d_arith};
     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -2114,8 +2211,9 @@ apsp_status_t check_options(int64_t n, apsp_dtype_t dtype, bool with_pred, const
         (with_pred || n > kSingleMaxN || (opt.block_size != 0 && opt.block_size != 64) ||
          (opt.thread_tile != 0 && opt.thread_tile != 4) || opt.use_graph || (dtype == APSP_INT32 && opt.arith == 2)))
         return APSP_ERROR_INVALID_ARGUMENT;
-    if (opt.phase1 < 0 || opt.phase1 > 2) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.phase1 < 0 || opt.phase1 > 3) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.phase1 == 2 && opt.block_size != 256) return APSP_ERROR_INVALID_ARGUMENT;
+    if (opt.phase1 == 3 && opt.block_size != 128 && opt.block_size != 256) return APSP_ERROR_INVALID_ARGUMENT;
     return APSP_SUCCESS;
 }
 
@@ -2248,9 +2346,9 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out) {
         recs.swap(g_prof);
     }
     *out = apsp_profile_t{};
-    apsp_kernel_time_t *slot[8] = {&out->phase1,       &out->phase2,       &out->phase3,
-                                   &out->other,        &out->phase3_cross, &out->pred_product,
-                                   &out->phase1_blocked, &out->single_launch};
+    apsp_kernel_time_t *slot[9] = {&out->phase1,         &out->phase2,        &out->phase3,
+                                   &out->other,          &out->phase3_cross,  &out->pred_product,
+                                   &out->phase1_blocked, &out->single_launch, &out->phase1_flow};
     apsp_status_t st = APSP_SUCCESS;
     for (auto &r : recs) {
         float ms = 0.f;
@@ -2260,7 +2358,7 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out) {
             g_last_hip = (int)e;
             st = APSP_ERROR_HIP;
         }
-        for (int kind : {r.kind == kPhase1Blocked ? (int)kPhase1 : -1, r.kind}) {
+        for (int kind : {r.kind == kPhase1Blocked || r.kind == kPhase1Flow ? (int)kPhase1 : -1, r.kind}) {
             if (kind < 0) continue;
             apsp_kernel_time_t *k = slot[kind];
             k->launches += 1;
@@ -2447,6 +2545,17 @@ apsp_status_t apsp_release_workspace(void) {
     {
         std::lock_guard<std::mutex> lg(g_graph_mu);
         drop_graphs_locked(dev);  // graphs refer to the work memory freed below
+    }
+    {
+        std::lock_guard<std::mutex> lc(g_closure_mu);
+        for (auto it = g_closure.begin(); it != g_closure.end();) {
+            if (it->first.first == dev) {
+                if (it->second) APSP_HIP(hipFree(it->second));
+                it = g_closure.erase(it);
+            } else {
+                ++it;
+            }
+        }
     }
     std::lock_guard<std::mutex> lk(g_ws_mu);
     for (auto it = g_ws.begin(); it != g_ws.end();) {

@@ -76,8 +76,12 @@ def test_host_side_argument_errors():
     stp = ctypes.c_void_p()
     assert L.apsp_stepper_create(100, apsp.INT32, 0, ctypes.byref(single), ctypes.byref(stp)) == \
         apsp.INVALID_ARGUMENT
-    bad_phase1 = apsp.Options(0, 256, 0, 0, 0, 0, None, None, 3)
+    bad_phase1 = apsp.Options(0, 256, 0, 0, 0, 0, None, None, 4)
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_phase1) == apsp.INVALID_ARGUMENT
+    # the dataflow closure needs 128- or 256-wide blocks
+    for bs in (0, 64):
+        flow_bs = apsp.Options(0, bs, 0, 0, 0, 0, None, None, 3)
+        assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, flow_bs) == apsp.INVALID_ARGUMENT
     # the blocked diagonal closure needs 256-wide blocks
     blocked_bs128 = apsp.Options(0, 128, 0, 0, 0, 0, None, None, 2)
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, blocked_bs128) == apsp.INVALID_ARGUMENT

@@ -199,3 +199,98 @@ def test_split_negative_cycle_reported():
     for arith in (1, 2):
         _, _, st, _, _ = _solve_profiled(W, False, block_size=256, schedule=2, phase1=2, arith=arith)
         assert st == 3, arith
+
+
+# ------------------------------------------------------------------------
+# Phase 1 as the dataflow closure (phase1=3): the diagonal block solved by
+# the blocked schedule over 32-wide sub-blocks in one launch, on the exact
+# routes (int32 arithmetic; float32 arithmetic watched for exactness).
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("bs", [128, 256])
+@pytest.mark.parametrize("kind,arith", [("int", 1), ("int", 2), ("pot", 1), ("pot", 2), ("sparse", 2)])
+def test_dataflow_closure_distances(orc, n, bs, kind, arith):
+    describe(f"phase-1 closure: distances n={n} bs={bs} {kind} arith={arith}")
+    W, D0, _ = _expect(orc, kind, n)
+    R = (n + bs - 1) // bs
+    for schedule in (1, 2):
+        D, _, st, used, prof = _solve_profiled(W, False, block_size=bs, schedule=schedule, phase1=3, arith=arith)
+        assert st == 0
+        assert first_mismatch(D, D0) is None, (schedule, first_mismatch(D, D0))
+        assert prof["phase1_flow"]["launches"] == R, prof["phase1_flow"]
+        assert prof["phase1"]["launches"] == R
+        assert used == (1 if arith == 2 else 0)
+
+
+@pytest.mark.parametrize("n", [1000, 2048])
+@pytest.mark.parametrize("kind", ["int", "pot", "f32"])
+def test_dataflow_closure_float32_predecessor_route(orc, n, kind):
+    """The float32 route's distance rounds (watched float32) with the closure
+    and the two-stream split, then the key product."""
+    describe(f"phase-1 closure: float32 predecessor route n={n} {kind}")
+    W, D0, P0 = _expect(orc, kind, n)
+    D, P, st, used, prof = _solve_profiled(W, True, block_size=256, schedule=2, phase1=3, arith=2)
+    assert st == 0 and used == 1
+    assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+    assert first_mismatch(P, P0) is None, first_mismatch(P, P0)
+    assert prof["phase1_flow"]["launches"] == (n + 255) // 256
+
+
+def test_dataflow_closure_watch_fallback_and_cycles(orc):
+    """Operands reaching 2^23 inside the closure raise the watch, and the
+    int32 redo (closure too) is exact; negative cycles are reported."""
+    describe("phase-1 closure: watch fallback, negative cycle")
+    n = 900
+    rng = np.random.default_rng(11)
+    bound = (2 ** 28 - 1) // (n - 1)
+    W = pins.random_graph(rng, n, 0.002, bound // 2, bound)
+    for i in range(n - 1):
+        W[i, i + 1] = bound - (i % 7)
+    D0, _, st0 = orc.fw(W)
+    assert st0 == oracle.OK
+    D, _, st, used, prof = _solve_profiled(W, False, block_size=256, schedule=1, phase1=3, arith=2)
+    assert st == 0 and used == 0
+    assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+    assert prof["phase1_flow"]["launches"] >= (n + 255) // 256
+    Wc = synth.single_int32(800, p=0.05, seed=12)
+    Wc[10, 600], Wc[600, 10] = 5, -9
+    for arith in (1, 2):
+        _, _, st, _, _ = _solve_profiled(Wc, False, block_size=256, phase1=3, arith=arith)
+        assert st == 3, arith
+
+
+def test_dataflow_closure_not_for_inexact_float32(orc):
+    """Real-valued float32 weights are not an exact route: phase1=3 keeps the
+    stepwise closure there (so every schedule rounds alike)."""
+    describe("phase-1 closure: real float32 keeps the stepwise kernel")
+    n = 700
+    W = synth.single_f32real(n, p=0.05, lo=0.5, hi=100.0, seed=23)
+    D, _, st, _, prof = _solve_profiled(W, False, block_size=256, phase1=3)
+    assert st == 0
+    assert prof["phase1_flow"]["launches"] == 0
+    D1, _, _, _, _ = _solve_profiled(W, False, block_size=256, phase1=1)
+    assert np.array_equal(D.view(np.uint32), D1.view(np.uint32))
+
+
+def test_dataflow_closure_in_a_graph_replayed(orc):
+    """The closure recorded into a hipGraph (its scratch made beforehand),
+    replayed several times with eager work in between: every replay exact."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe("phase-1 closure: hipGraph replays")
+    n = 2100
+    W = _graph("int", n)
+    D0, _, _ = oracle_expect(orc, W)
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        d = torch.from_numpy(W).cuda()
+        st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        apsp.solve(d, status=st, stream=s, use_graph=True, block_size=256, phase1=3, arith=2)
+        s.synchronize()
+        junk = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        assert first_mismatch(d.cpu().numpy(), D0) is None, rep
