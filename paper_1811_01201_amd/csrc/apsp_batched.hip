@@ -1032,8 +1032,10 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
         plan_free(p);
         return APSP_ERROR_OUT_OF_MEMORY;
     }
+    // (the memset is on the null stream: wait for it, so a launch on a
+    // non-blocking stream cannot overtake it)
     if (hipMemcpy(p->dev_meta, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(p->counters, 0, 8 * sizeof(int32_t)) != hipSuccess) {
+        hipMemset(p->counters, 0, 8 * sizeof(int32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         plan_free(p);
         return APSP_ERROR_HIP;
     }

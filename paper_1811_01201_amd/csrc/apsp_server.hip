@@ -520,7 +520,8 @@ apsp_status_t apsp_server_create(const apsp_server_config_t *config, apsp_server
         const size_t bytes = (size_t)sv->batch_grid * sv->batch_scratch_elems * 8;
         if ((int64_t)bytes >= cfg.hbm_budget_bytes || hipMalloc(&sv->batch_scratch, bytes) != hipSuccess ||
             hipMalloc((void **)&sv->batch_counters, 32) != hipSuccess ||
-            hipMemset(sv->batch_counters, 0, 32) != hipSuccess)
+            hipMemset(sv->batch_counters, 0, 32) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)  // the null-stream memset done before any stream uses them
             return fail(APSP_ERROR_OUT_OF_MEMORY);
         sv->fixed_bytes = (int64_t)bytes;
     }

@@ -260,55 +260,30 @@ phase3_kernel(void *X, int64_t ld, int r, int per_xcd, int seq0, int seq_end, Ar
     }
 }
 
-// ------------------------------------------------ single-launch schedule
-// Small graphs: all rounds in one cooperative launch of co-resident
-// workgroups that meet at device-wide barriers, in place of three dependent
-// launches per round, whose dispatch gaps rather than their arithmetic set
-// the time of a solve below n of a few thousand.  64 x 64 blocks and tiles;
-// every product stages its whole A and B (64 k each) in one LDS DMA pass.
-// The blocked schedule is kept as it is -- round r's panels read the closed
-// block r, its remaining blocks read round r's panels, each product over the
-// same operands -- so the values are the multi-launch schedule's, bit for
-// bit.  Lookahead: workgroup 0 takes round r's tile (r+1, r+1) first and
-// closes it at once (phase 1 of round r+1) while the others finish round
-// r's phase 3, so a round costs two barriers:
-//   [P2(r) tiles] barrier [P3(r) tiles; WG 0: tile (r+1,r+1), P1(r+1)] barrier
+// --------------------------------------------- dataflow (task graph) solves
+// Below n of a few thousand a solve is a chain of dependent launches whose
+// dispatch gaps, not their arithmetic, set the time; and phase 1 of 128-
+// and 256-wide blocks is a chain of dependent steps on one compute unit.
+// Both are served by one kernel (flow_tasks_kernel below) that runs the
+// blocked schedule over small blocks as a graph of tasks inside a single
+// launch.
 //
 // Coherence without cache flushes: each XCD has its own L2, and a
 // device-scope release or acquire fence writes back or invalidates the
-// whole L2 -- one such operation per wavefront and barrier costs more than
-// the barrier itself once hundreds of workgroups take part.  Instead every
-// load and store of the matrix in this kernel is device-coherent (cache
-// policy sc1: stores write through, loads do not return lines another XCD
-// may have overwritten), so a barrier only waits for its own stores to
-// complete before arriving.
-//
-// Barrier words (all zeroed by single_init_kernel before the launch), each
-// barrier numbered b = 1, 2, ... within the launch:
-//   flags[w]      workgroup w arrived at barrier b (stores b; one word each,
-//                 so arrivals never contend on one address)
-//   release[x]    workgroup 0, having seen every flag at b, stores b into
-//                 all 8 copies (256 bytes apart); workgroup w polls copy w % 8
-//   fail          a wait ran out; every other wait then ends too
-constexpr int kSingleBS = 64;
+// whole L2 (measured on MI355X: one per wavefront made a 1024-workgroup
+// barrier cost 62 us).  Instead every load and store of the matrix in these
+// kernels is device-coherent (cache policy sc1: stores write through, loads
+// do not return lines another XCD may have overwritten), so a task only
+// waits for its own stores to complete before it marks its result ready.
+constexpr int kSingleBS = 64;         // the solve's block size the single launch belongs to
 constexpr int kSingleThreads = 256;
-constexpr int kSingleMaxGroups = 2048;
-constexpr int kReleaseWords = kSingleMaxGroups;  // 8 copies, 64 words apart
-constexpr int kFailWord = kReleaseWords + 8 * 64;
-constexpr int kSingleWords = kFailWord + 64;
-constexpr size_t kSingleWordBytes = (size_t)kSingleWords * 4;
 // element offsets within the matrix are 32-bit
 constexpr int64_t kSingleMaxN = 16384;
-// Spins of one barrier wait before it gives up (about a second or more;
-// the workgroups are co-resident, so a wait ends long before unless the
-// device is broken).  A failed wait sets the fail word, which ends every
-// other wait, and the solve reports APSP_ERROR_TIMEOUT.
+// Polls of one wait before it gives up (about a second or more; every wait
+// is for a task that running workgroups hold, so it ends long before unless
+// the device is broken).  A failed wait sets the fail word, which ends
+// every other wait, and the solve reports APSP_ERROR_TIMEOUT.
 constexpr uint32_t kBarrierSpins = 1u << 22;
-
-__global__ void single_init_kernel(uint32_t *words, int32_t *status) {
-    for (int i = threadIdx.x; i < kSingleWords; i += blockDim.x) words[i] = 0;
-    if (status && threadIdx.x == 0) *status = APSP_SUCCESS;
-}
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -318,52 +293,6 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
 }
 // this wavefront's loads and stores (device-coherent ones included) complete
 __device__ __forceinline__ void mem_done() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
-
-// Device-wide barrier number b; false if a wait ran out here or anywhere.
-// Data moves through device-coherent accesses only (see above), so arriving
-// needs no more than this workgroup's accesses completed.
-__device__ __forceinline__ bool grid_barrier(uint32_t *words, int groups, uint32_t b, int *ok_lds) {
-    mem_done();
-    __syncthreads();
-    const int w = (int)blockIdx.x;
-    if (threadIdx.x == 0) st_agent(&words[w], b);
-    if (w == 0) {
-        // every thread checks a share of the flags; the decision is block-wide
-        bool ok = true;
-        for (uint32_t spin = 0;; ++spin) {
-            bool mine = true;
-            for (int v = (int)threadIdx.x; v < groups; v += kSingleThreads) mine &= ld_agent(&words[v]) == b;
-            if (__syncthreads_and(mine)) break;
-            const bool failed = threadIdx.x == 0 && ld_agent(&words[kFailWord]) != 0;
-            if (__syncthreads_or(failed) || spin >= kBarrierSpins) {
-                ok = false;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (threadIdx.x == 0) {
-            if (ok) {
-#pragma unroll
-                for (int x = 0; x < 8; ++x) st_agent(&words[kReleaseWords + 64 * x], b);
-            } else {
-                st_agent(&words[kFailWord], 1u);
-            }
-        }
-    } else if (threadIdx.x == 0) {
-        const uint32_t *rel = &words[kReleaseWords + 64 * (w & 7)];
-        for (uint32_t spin = 0; ld_agent(rel) != b; ++spin) {
-            if (spin >= kBarrierSpins) {
-                st_agent(&words[kFailWord], 1u);
-                break;
-            }
-            if (ld_agent(&words[kFailWord]) != 0) break;
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    if (threadIdx.x == 0) *ok_lds = ld_agent(&words[kFailWord]) == 0;
-    __syncthreads();
-    return *ok_lds != 0;
-}
 
 // 16-byte device-coherent accesses (two 8-byte device-scope atomics, which
 // the compiler emits as dwordx2 loads and stores with sc1)
@@ -389,156 +318,8 @@ __device__ __forceinline__ void st16_dev(T *p, const T *in) {
     __hip_atomic_store(q + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <class Ar>
-__global__ void __launch_bounds__(kSingleThreads)
-rounds_single_kernel(void *Xv, int64_t ld, Ar ar, uint32_t *words, int32_t *status,
-                     const int32_t *__restrict__ skip) {
-    using T = typename Ar::T;
-    static_assert(sizeof(T) == 4, "4-byte elements");
-    using TP = TileProductDMA<Ar, kSingleBS, kSingleBS, kSingleBS, 4, 4, kCpolDevice>;
-    using PS = P1S<Ar, kSingleBS, 4>;
-    static_assert(TP::NTH == kSingleThreads && PS::NTH == kSingleThreads && PS::TM1 == 4 && PS::TN1 == 4,
-                  "one workgroup shape for products and closures");
-    if (skip && *skip != APSP_SUCCESS) return;
-    __shared__ alignas(16) T la[kSingleBS * kSingleBS];
-    __shared__ alignas(16) T lb[kSingleBS * kSingleBS];
-    __shared__ alignas(16) T p1c[4][kSingleBS];
-    __shared__ alignas(16) T p1r[4][kSingleBS];
-    __shared__ int ok_lds;
-    T *const D = (T *)Xv;
-    const uint32_t ldu = (uint32_t)ld;
-    const int R = (int)(ld / kSingleBS), m = R - 1;
-    const int G = (int)gridDim.x, w = (int)blockIdx.x;
-    const int tid = (int)threadIdx.x;
-    uint32_t bar = 0;  // barriers passed
-
-    // C <- min(C, A (x) B) on the tile at (crow, ccol), k-block at k0
-    auto product = [&](uint32_t crow, uint32_t ccol, uint32_t k0) __attribute__((always_inline)) {
-        const int tx = tid % TP::TX, ty = tid / TP::TX;
-        T *const c0 = D + ((crow + (uint32_t)ty) * ldu + ccol + (uint32_t)tx * TP::VW);
-        T c[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) ld16_dev(c0 + (uint32_t)(TP::TY * i) * ldu, c[i]);
-        __syncthreads();  // the previous tile's LDS reads are done
-        TP::copy_chunk(la, lb, D + (size_t)crow * ldu + k0, D + (size_t)k0 * ldu + ccol, ldu);
-        TP::copies_done(la, ar);
-        TP::compute(c, la, lb, tx, ty, ar);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) st16_dev(c0 + (uint32_t)(TP::TY * i) * ldu, c[i]);
-    };
-    // phase 1 on block r (the stepwise closure's register layout)
-    auto close = [&](uint32_t r0) __attribute__((always_inline)) {
-        mem_done();
-        __syncthreads();  // this workgroup's stores to the block are complete
-        const int tx = tid % PS::TX, ty = tid / PS::TX;
-        T *const c0 = D + ((r0 + (uint32_t)ty * 4) * ldu + r0 + (uint32_t)tx * 4);
-        T c[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) ld16_dev(c0 + (uint32_t)i * ldu, c[i]);
-        (void)phase1_steps<Ar, kSingleBS, false, 4>(c, kSingleBS, ar, p1c, p1r);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) st16_dev(c0 + (uint32_t)i * ldu, c[i]);
-    };
-
-    bool ok = true;
-    if (w == 0) close(0);
-    for (int r = 0; r < R && m > 0; ++r) {
-        const uint32_t r0 = (uint32_t)r * kSingleBS;
-        if (!(ok = grid_barrier(words, G, ++bar, &ok_lds))) break;
-        // phase 2: block row r (t < m), block column r (t >= m)
-        for (int t = w; t < 2 * m; t += G) {
-            int q = t < m ? t : t - m;
-            q += q >= r;
-            if (t < m)
-                product(r0, (uint32_t)q * kSingleBS, r0);
-            else
-                product((uint32_t)q * kSingleBS, r0, r0);
-        }
-        if (!(ok = grid_barrier(words, G, ++bar, &ok_lds))) break;
-        // phase 3 over the m x m blocks outside row and column r, numbered
-        // a = i' m + j' (i', j' skip r); tile (r+1, r+1) is a = r m + r
-        const int total = m * m;
-        const bool ahead = r + 1 < R;
-        const int lead = ahead ? r * m + r : -1;
-        auto p3 = [&](int a) __attribute__((always_inline)) {
-            int i = a / m, j = a - (a / m) * m;
-            i += i >= r;
-            j += j >= r;
-            product((uint32_t)i * kSingleBS, (uint32_t)j * kSingleBS, r0);
-        };
-        if (ahead && w == 0) {
-            p3(lead);
-            close(r0 + kSingleBS);
-        }
-        // the other tiles: over workgroups 1 .. G-1, or all on workgroup 0
-        const int first = (ahead && G > 1) ? 1 : 0, stride = G - first;
-        for (int t = w - first; w >= first && t < total - (ahead ? 1 : 0); t += stride)
-            p3(ahead && t >= lead ? t + 1 : t);
-    }
-    if (!ok && status && tid == 0) *status = APSP_ERROR_TIMEOUT;
-}
-
-// Dataflow form of the single launch, for padded orders whose R x R blocks
-// (R = ld / BS, BS = 32 or 64) fit one workgroup each on the device at
-// once.  Workgroup
-// w = i R + j owns block (i, j) for the whole solve and keeps it in
-// registers (the stepwise closure's layout: thread (tx, ty) holds rows
-// 4 ty .. 4 ty + 3, columns 4 tx .. 4 tx + 3).  Per round r it does its one
-// task of the blocked schedule and then the next round's, waiting only for
-// the operands it reads:
-//   block (r, j), j != r   phase 2: waits for diag(r); B is its own block
-//   block (i, r), i != r   phase 2: waits for diag(r); A is its own block
-//   other blocks           phase 3: waits for panels (i, r) and (r, j)
-//   block (r+1, r+1)       after its phase 3, at once phase 1 of round r+1
-//                          (in registers), then publishes diag(r+1)
-// Panels and closed diagonal blocks are published, each exactly once, to
-// separate matrices (block row panels and diagonal blocks to P_row, block
-// column panels to P_col) with device-coherent stores, then a ready word
-// per published block is set; readers copy them with device-coherent LDS
-// DMA.  A block read by others is never written again in place, so no
-// reader can see a later round's value.  The operands of every product are
-// those of the multi-launch schedule, so the values are too, bit for bit.
-// Ready words: row(r, j) at r R + j, col(i, r) at R^2 + i R + r, diag(r) at
-// 2 R^2 + r, the fail word at flow_fail_word(R), a count of finished
-// workgroups 32 words after it.  All are zero before a launch; the last
-// workgroup to finish zeroes them again, so a launch leaves them ready for
-// the next one.
-__host__ __device__ constexpr int flow_fail_word(int R) { return 2 * R * R + R; }
-__host__ __device__ constexpr int flow_done_word(int R) { return flow_fail_word(R) + 32; }
-__host__ __device__ constexpr size_t flow_word_bytes(int R) { return ((size_t)flow_fail_word(R) + 64) * 4; }
-
-__global__ void flow_init_kernel(uint32_t *words, int count, int32_t *status) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) words[i] = 0;
-    if (status && blockIdx.x == 0 && threadIdx.x == 0) *status = APSP_SUCCESS;
-}
-
-// Waits until every nonzero-addressed word in w0, w1 reads nonzero (thread
-// 0 polls; the workgroup leaves together).  False if the wait ran out or
-// another wait did (the fail word).
-__device__ __forceinline__ bool flow_wait(const uint32_t *w0, const uint32_t *w1, uint32_t *fail, int *ok_lds) {
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        for (uint32_t spin = 0; ld_agent(w0) == 0 || (w1 && ld_agent(w1) == 0); ++spin) {
-            if (spin >= kBarrierSpins) {
-                st_agent(fail, 1u);
-                ok = 0;
-                break;
-            }
-            if (ld_agent(fail) != 0) {
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        *ok_lds = ok;
-    }
-    __syncthreads();
-    return *ok_lds != 0;
-}
-
 // 256 threads per block: BS = 64 with 4 x 4 elements per thread, BS = 32
-// with 2 x 2.  At most 4 workgroups per CU (see coop_capacity): 1024 blocks
-// on MI355X, so BS = 32 up to a padded order of 1024, BS = 64 up to 2048.
+// with 2 x 2.
 template <int BS>
 constexpr int flow_tile() {
     return BS == 32 ? 2 : 4;
@@ -601,47 +382,113 @@ __device__ __forceinline__ void flow_copy(T *__restrict__ lds, const T *__restri
     }
 }
 
+__global__ void flow_init_kernel(uint32_t *words, int count, int32_t *status) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) words[i] = 0;
+    if (status && blockIdx.x == 0 && threadIdx.x == 0) *status = APSP_SUCCESS;
+}
+
+// Dataflow solve as a ticketed task graph (the phase-1 closure of 128- and
+// 256-wide blocks): the tasks of the blocked schedule over BS-wide
+// sub-blocks are numbered in an order where every task's operands come
+// from tasks with smaller numbers --
+//   0                              phase 1 of sub-round 0 on block (0, 0)
+//   then per round r, m = R - 1:   2m panel products (block row r, then
+//                                  block column r), then m^2 products of
+//                                  the remaining blocks, block (r+1, r+1)
+//                                  first, closed at once (phase 1 of r+1)
+// -- and a workgroup takes the next number from a counter, waits for the
+// operands it reads and does the task, over and over.  A task only waits
+// for smaller numbers, which running workgroups hold, so the launch makes
+// progress however few of its workgroups are resident and whatever else
+// runs on the device.  Block states live in X (device-coherent loads and
+// stores); panels and closed diagonal blocks are also published once each
+// to P_row / P_col, so a reader never sees a later round's value.
+// words: ver(i, j) at i R + j = rounds applied to block (i, j) (its panel
+// or closed block is published once ver passes that round), then the fail
+// word, the task counter and the finished-workgroup count; zero before a
+// launch, zeroed again by the last workgroup to finish.
+__host__ __device__ constexpr int task_fail_word(int R) { return R * R + 32; }
+__host__ __device__ constexpr int task_next_word(int R) { return R * R + 64; }
+__host__ __device__ constexpr int task_done_word(int R) { return R * R + 96; }
+__host__ __device__ constexpr size_t task_word_bytes(int R) { return ((size_t)R * R + 128) * 4; }
+__host__ __device__ constexpr int64_t task_count(int R) {
+    return 1 + (int64_t)R * (R - 1) * (R + 1);  // R rounds of m (m + 2) tasks, m = R - 1
+}
+
+// Waits (thread 0 polling) until *w0 >= v0 and, if w1, *w1 >= v1; the
+// workgroup leaves together.  False if the wait ran out or another did.
+__device__ __forceinline__ bool task_wait(const uint32_t *w0, uint32_t v0, const uint32_t *w1, uint32_t v1,
+                                          uint32_t *fail, int *ok_lds) {
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        for (uint32_t spin = 0; ld_agent(w0) < v0 || (w1 && ld_agent(w1) < v1); ++spin) {
+            if (spin >= kBarrierSpins) {
+                st_agent(fail, 1u);
+                ok = 0;
+                break;
+            }
+            if (ld_agent(fail) != 0) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        *ok_lds = ok;
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+template <int TT, class T>
+__device__ __forceinline__ void ld_tt_dev(const T *p, T *out) {
+    if constexpr (TT == 4) {
+        ld16_dev(p, out);
+    } else {
+        const uint64_t v = __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        out[0] = __builtin_bit_cast(T, (uint32_t)v);
+        out[1] = __builtin_bit_cast(T, (uint32_t)(v >> 32));
+    }
+}
+
 template <class Ar, int BS>
 __global__ void __launch_bounds__(kSingleThreads) __attribute__((amdgpu_waves_per_eu(4)))
-rounds_flow_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *words, void *prow_v, void *pcol_v,
-                   int32_t *status, const int32_t *__restrict__ skip) {
+flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *words, void *prow_v, void *pcol_v,
+                  int32_t *status, const int32_t *__restrict__ skip) {
     using T = typename Ar::T;
     static_assert(sizeof(T) == 4, "4-byte elements");
     constexpr int TT = flow_tile<BS>();
     using PS = P1S<Ar, BS, TT>;
     static_assert(PS::NTH == kSingleThreads && PS::TM1 == TT && PS::TN1 == TT, "TT x TT per thread");
     if (skip && *skip != APSP_SUCCESS) return;
-    __shared__ alignas(16) T la[BS * BS];  // A operand
-    __shared__ alignas(16) T lb[BS * BS];  // B operand
+    __shared__ alignas(16) T la[BS * BS];
+    __shared__ alignas(16) T lb[BS * BS];
     __shared__ alignas(16) T p1c[4][BS];
     __shared__ alignas(16) T p1r[4][BS];
     __shared__ int ok_lds;
+    __shared__ uint32_t ticket_lds;
     T *const X = (T *)Xv;
     T *const Prow = (T *)prow_v;
     T *const Pcol = (T *)pcol_v;
     const uint32_t ordu = (uint32_t)order, stru = (uint32_t)stride;
-    const int R = (int)(order / BS);
-    const int bi = (int)blockIdx.x / R, bj = (int)blockIdx.x % R;
+    const int R = (int)(order / BS), m = R - 1;
     const int tid = (int)threadIdx.x, tx = tid % PS::TX, ty = tid / PS::TX;
-    uint32_t *const fail = words + flow_fail_word(R);
-    // block (p, q) of a matrix with row stride ld (X: stride; the published
-    // matrices: order), and this thread's TT x TT piece of it
+    uint32_t *const ver = words;
+    uint32_t *const fail = words + task_fail_word(R);
+    const uint32_t total = (uint32_t)task_count(R), per_round = (uint32_t)(m * (m + 2));
     auto blk = [&](T *M, uint32_t ld, int p, int q) __attribute__((always_inline)) {
         return M + ((uint32_t)p * BS * ld + (uint32_t)q * BS);
     };
     auto at = [&](T *M, uint32_t ld, int p, int q) __attribute__((always_inline)) {
         return blk(M, ld, p, q) + ((uint32_t)ty * TT * ld + (uint32_t)tx * TT);
     };
-    bool big = false;  // a watching policy saw an unsafe operand or result
     T c[TT][TT];
-    {
-        T *const src = at(X, stru, bi, bj);
+    bool big = false;
+    auto load = [&](int i, int j) __attribute__((always_inline)) {
+        T *const src = at(X, stru, i, j);
 #pragma unroll
-        for (int m = 0; m < TT; ++m) ld_tt<TT>(src + (uint32_t)m * stru, c[m]);
+        for (int q = 0; q < TT; ++q) ld_tt_dev<TT>(src + (uint32_t)q * stru, c[q]);
         big |= any_big(ar, c);
-    }
-    // c <- min(c, A (x) B), A in la, B in lb, once both are complete
-    // (unrolled by two, so the LDS reads of the next k run ahead of the arithmetic)
+    };
     auto multiply = [&]() __attribute__((always_inline)) {
         __builtin_amdgcn_s_waitcnt(0x0F70);  // this wavefront's copies: vmcnt(0)
         __syncthreads();
@@ -649,9 +496,9 @@ rounds_flow_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *wor
         for (int kg = 0; kg < BS; kg += 4) {
             T a[TT][4];
 #pragma unroll
-            for (int m = 0; m < TT; ++m) {
-                const int row = ty * TT + m;
-                ld16(&la[row * BS + (((kg >> 2) ^ flow_swz<BS>(row)) << 2)], a[m]);
+            for (int q = 0; q < TT; ++q) {
+                const int row = ty * TT + q;
+                ld16(&la[row * BS + (((kg >> 2) ^ flow_swz<BS>(row)) << 2)], a[q]);
             }
 #pragma unroll
             for (int kk = 0; kk < 4; kk += 2) {
@@ -659,87 +506,111 @@ rounds_flow_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *wor
                 ld_tt<TT>(&lb[(kg + kk) * BS + tx * TT], b0);
                 ld_tt<TT>(&lb[(kg + kk + 1) * BS + tx * TT], b1);
 #pragma unroll
-                for (int m = 0; m < TT; ++m)
+                for (int q = 0; q < TT; ++q)
 #pragma unroll
-                    for (int n = 0; n < TT; ++n) c[m][n] = ar.relax2(c[m][n], a[m][kk], b0[n], a[m][kk + 1], b1[n]);
+                    for (int n = 0; n < TT; ++n) c[q][n] = ar.relax2(c[q][n], a[q][kk], b0[n], a[q][kk + 1], b1[n]);
             }
         }
     };
-    // stores this thread's piece into block (p, q) of M, then (once every
-    // wavefront's stores are complete) sets the ready word
-    auto publish = [&](T *M, int p, int q, uint32_t *ready) __attribute__((always_inline)) {
+    // stores the block state (and its publication, if any), then, once every
+    // wavefront's stores are complete, advances ver(i, j) to v
+    auto finish = [&](int i, int j, T *pub, uint32_t v) __attribute__((always_inline)) {
         big |= any_big(ar, c);
-        T *const dst = at(M, ordu, p, q);
+        T *const dst = at(X, stru, i, j);
 #pragma unroll
-        for (int m = 0; m < TT; ++m) st_tt_dev<TT>(dst + (uint32_t)m * ordu, c[m]);
+        for (int q = 0; q < TT; ++q) st_tt_dev<TT>(dst + (uint32_t)q * stru, c[q]);
+        if (pub) {
+            T *const pd = at(pub, ordu, i, j);
+#pragma unroll
+            for (int q = 0; q < TT; ++q) st_tt_dev<TT>(pd + (uint32_t)q * ordu, c[q]);
+        }
         mem_done();
         __syncthreads();
-        if (tid == 0) st_agent(ready, 1u);
+        if (tid == 0) st_agent(&ver[i * R + j], v);
     };
     auto close = [&]() __attribute__((always_inline)) {
         big |= phase1_steps<Ar, BS, false, TT>(c, BS, ar, p1c, p1r);
     };
-    uint32_t *const row_ready = words, *const col_ready = words + R * R, *const diag_ready = words + 2 * R * R;
 
     bool ok = true;
-    if (bi == 0 && bj == 0) {
-        close();
-        publish(Prow, 0, 0, &diag_ready[0]);
-    }
-    for (int r = 0; r < R && ok; ++r) {
-        if (bi == r && bj == r) continue;  // closed one round earlier
-        if (bi == r) {
-            // block row r: c <- min(c, D(r,r)* (x) c)
-            if (!(ok = flow_wait(&diag_ready[r], nullptr, fail, &ok_lds))) break;
-            flow_copy<BS, kSingleThreads, true>(la, blk(Prow, ordu, r, r), ordu);
+    for (;;) {
+        __syncthreads();  // LDS (operands, ticket) free for the next task
+        if (tid == 0)
+            ticket_lds = __hip_atomic_fetch_add(&words[task_next_word(R)], 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t t = ticket_lds;
+        if (t >= total) break;
+        if (!ok) continue;  // after a failed wait: drain the counter, do nothing
+        if (t == 0) {
+            load(0, 0);
+            close();
+            finish(0, 0, Prow, 1u);
+            continue;
+        }
+        const int r = (int)((t - 1) / per_round);
+        const int u = (int)((t - 1) % per_round);
+        if (u < 2 * m) {
+            const bool row = u < m;
+            int q = row ? u : u - m;
+            q += q >= r;
+            const int i = row ? r : q, j = row ? q : r;
+            // its own round r - 1 and the closed block r
+            if (!(ok = task_wait(&ver[i * R + j], (uint32_t)r, &ver[r * R + r], (uint32_t)r + 1, fail, &ok_lds)))
+                continue;
+            load(i, j);
+            if (row) {  // c <- min(c, D(r,r)* (x) c)
+                flow_copy<BS, kSingleThreads, true>(la, blk(Prow, ordu, r, r), ordu);
 #pragma unroll
-            for (int m = 0; m < TT; ++m) st_tt<TT>(&lb[(ty * TT + m) * BS + tx * TT], c[m]);
-            multiply();
-            publish(Prow, r, bj, &row_ready[r * R + bj]);
-        } else if (bj == r) {
-            // block column r: c <- min(c, c (x) D(r,r)*)
-            if (!(ok = flow_wait(&diag_ready[r], nullptr, fail, &ok_lds))) break;
-            flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, r), ordu);
+                for (int q2 = 0; q2 < TT; ++q2) st_tt<TT>(&lb[(ty * TT + q2) * BS + tx * TT], c[q2]);
+            } else {  // c <- min(c, c (x) D(r,r)*)
+                flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, r), ordu);
 #pragma unroll
-            for (int m = 0; m < TT; ++m) {
-                const int row = ty * TT + m, col = tx * TT;
-                st_tt<TT>(&la[row * BS + (((col >> 2) ^ flow_swz<BS>(row)) << 2) + (col & 3)], c[m]);
+                for (int q2 = 0; q2 < TT; ++q2) {
+                    const int rw = ty * TT + q2, col = tx * TT;
+                    st_tt<TT>(&la[rw * BS + (((col >> 2) ^ flow_swz<BS>(rw)) << 2) + (col & 3)], c[q2]);
+                }
             }
             multiply();
-            publish(Pcol, bi, r, &col_ready[bi * R + r]);
+            finish(i, j, row ? Prow : Pcol, (uint32_t)r + 1);
+            continue;
+        }
+        // the remaining blocks, block (r+1, r+1) first
+        int a = u - 2 * m;
+        const bool ahead = r + 1 < R;
+        if (ahead) {
+            const int lead = r * m + r;
+            a = a == 0 ? lead : (a - 1 >= lead ? a : a - 1);
+        }
+        int i = a / m, j = a - (a / m) * m;
+        i += i >= r;
+        j += j >= r;
+        if (!(ok = task_wait(&ver[i * R + j], (uint32_t)r, nullptr, 0u, fail, &ok_lds))) continue;
+        if (!(ok = task_wait(&ver[i * R + r], (uint32_t)r + 1, &ver[r * R + j], (uint32_t)r + 1, fail, &ok_lds)))
+            continue;
+        load(i, j);
+        flow_copy<BS, kSingleThreads, true>(la, blk(Pcol, ordu, i, r), ordu);
+        flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, j), ordu);
+        multiply();
+        if (ahead && i == r + 1 && j == r + 1) {
+            close();
+            finish(i, j, Prow, (uint32_t)r + 2);
         } else {
-            // the remaining blocks: c <- min(c, P_col(i, r) (x) P_row(r, j))
-            if (!(ok = flow_wait(&col_ready[bi * R + r], &row_ready[r * R + bj], fail, &ok_lds))) break;
-            flow_copy<BS, kSingleThreads, true>(la, blk(Pcol, ordu, bi, r), ordu);
-            flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, bj), ordu);
-            multiply();
-            if (bi == r + 1 && bj == r + 1) {
-                close();
-                publish(Prow, r + 1, r + 1, &diag_ready[r + 1]);
-            }
+            finish(i, j, nullptr, (uint32_t)r + 1);
         }
-        __syncthreads();  // LDS free for the next round's operands
     }
-    if (ok) {
-        T *const dst = at(X, stru, bi, bj);
-#pragma unroll
-        for (int m = 0; m < TT; ++m) st_tt<TT>(dst + (uint32_t)m * stru, c[m]);
-        if constexpr (Ar::kWatch) {
-            if (big || any_big(ar, c)) ar.raise();
-        }
-    } else if (status && tid == 0) {
-        *status = APSP_ERROR_TIMEOUT;
+    if constexpr (Ar::kWatch) {
+        if (big && tid == 0) ar.raise();
     }
-    // the last workgroup to get here clears the words for the next launch
-    // (every other workgroup has finished all its waits)
+    if (!ok && status && tid == 0) *status = APSP_ERROR_TIMEOUT;
+    // the last workgroup to finish clears the words for the next launch
     __syncthreads();
-    if (tid == 0) {
-        uint32_t *const done = words + flow_done_word(R);
-        ok_lds = __hip_atomic_fetch_add(done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)(R * R) - 1;
-    }
+    if (tid == 0)
+        ok_lds = __hip_atomic_fetch_add(&words[task_done_word(R)], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+                 gridDim.x - 1;
     __syncthreads();
     if (ok_lds)
-        for (int i = tid; i < flow_fail_word(R) + 64; i += kSingleThreads) st_agent(&words[i], 0u);
+        for (int k = tid; k < R * R + 128; k += kSingleThreads) st_agent(&words[k], 0u);
 }
 
 // ------------------------------------------------------ set-up / wrap-up
@@ -1481,37 +1352,46 @@ struct Sched {
 
 // Phase 1 of 128- and 256-wide blocks as a dataflow closure: the diagonal
 // block is solved by the blocked schedule itself, over 32-wide sub-blocks,
-// in one launch of (BS/32)^2 workgroups (rounds_flow_kernel on the block in
+// in one launch of (BS/32)^2 workgroups (flow_tasks_kernel on the block in
 // place: its order is BS, its row stride ld).  In exact arithmetic (int32,
 // and float32 watched for exactness) its values are those of BS single
-// steps.  An ordinary launch: its few workgroups start as soon as compute
-// units free up, and every workgroup that another one waits for does start
-// (the others' kernels never wait on it), so no co-residency is required;
-// the waits are bounded all the same.  Per (device, stream) scratch: the
-// two 256 x 256 published matrices and the ready words, zeroed once at
-// allocation (each launch leaves its words zeroed again).
+// steps.  An ordinary launch: its tasks are taken in dependency order, so
+// it completes however many of its workgroups are resident beside other
+// work (several solves on several streams included).  Per (device, stream)
+// scratch: the two 256 x 256 published matrices and the task words, zeroed
+// once at allocation (each launch leaves its words zeroed again).
 template <class Ar, int BS, class Alt>
 constexpr bool kFlowP1 = (BS == 128 || BS == 256) && std::is_same_v<Alt, NoAlt> &&
                          (std::is_same_v<Ar, ArI32> || std::is_same_v<Ar, ArF32W>);
 constexpr int kClosureBS = 32, kClosureMax = 256;
 constexpr size_t kClosurePub = (size_t)kClosureMax * kClosureMax * 4;
-constexpr size_t kClosureBytes = 2 * kClosurePub + flow_word_bytes(kClosureMax / kClosureBS);
+constexpr size_t kClosureBytes = 2 * kClosurePub + task_word_bytes(kClosureMax / kClosureBS);
 std::mutex g_closure_mu;
 std::map<std::pair<int, hipStream_t>, void *> g_closure;
 
 // The calling stream's closure scratch; allocates it unless `create` is
-// false (then *out is null where none exists yet).
+// false (then *out is null where none exists yet).  Its words are zeroed
+// by a kernel on that stream, so the zeros precede every launch that uses
+// them (a memset on the null stream would not be ordered before work on a
+// non-blocking stream).
 apsp_status_t closure_scratch(int dev, hipStream_t s, bool create, void **out) {
     std::lock_guard<std::mutex> lk(g_closure_mu);
     void *&p = g_closure[{dev, s}];
     if (!p && create) {
         void *q = nullptr;
         hipError_t e = hipMalloc(&q, kClosureBytes);
-        if (e == hipSuccess) e = hipMemset(q, 0, kClosureBytes);
         if (e != hipSuccess) {
             g_last_hip = (int)e;
-            if (q) (void)hipFree(q);
             return APSP_ERROR_OUT_OF_MEMORY;
+        }
+        const int words = (int)((kClosureBytes - 2 * kClosurePub) / 4);
+        hipLaunchKernelGGL(flow_init_kernel, dim3(1), dim3(256), 0, s, (uint32_t *)((char *)q + 2 * kClosurePub),
+                           words, (int32_t *)nullptr);
+        e = hipGetLastError();
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            (void)hipFree(q);
+            return APSP_ERROR_HIP;
         }
         p = q;
     }
@@ -1577,7 +1457,7 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
             if (closure) {
                 constexpr int RC = BS / kClosureBS;
                 char *const c = (char *)closure;
-                enq((rounds_flow_kernel<Ar, kClosureBS>), dim3(RC * RC), dim3(kSingleThreads), s,
+                enq((flow_tasks_kernel<Ar, kClosureBS>), dim3(RC * RC), dim3(kSingleThreads), s,
                     (void *)((typename Ar::T *)X + (int64_t)r * BS * ld + (int64_t)r * BS), (int64_t)BS, ld, ar,
                     (uint32_t *)(c + 2 * kClosurePub), (void *)c, (void *)(c + kClosurePub), t_status, skip);
                 return;
@@ -1758,40 +1638,18 @@ size_t work_bytes(int64_t n, bool with_pred, int opt_bs, bool aligned, apsp_dtyp
 
 // Single-launch schedule: distances only, 64-wide blocks with 4 x 4 thread
 // tiles, 4-byte arithmetic without a watch (int32 in int32, float32),
-// issued directly (not while a graph or a stepper records, nor without
-// allocations); automatic up to a padded order of kSingleMaxLd.  The launch
-// is cooperative (every workgroup resident at once).  Where one workgroup
-// per 64 x 64 block fits on the device, the dataflow kernel
-// (rounds_flow_kernel); otherwise the barrier-phased one
-// (rounds_single_kernel), whose workgroup count is the blocks of one
-// phase 3, capped at what the device holds.  (Measured on MI355X, int32
-// distances, ms per solve, rounds in order / dataflow / barrier-phased:
-// n = 1024: 0.435 / 0.383 / 0.438; 2048: 1.171 / 0.896 / 0.929; 3072:
-// 2.44 / - / 1.89; 4096: 4.49 / - / 3.95.)
+// issued directly (not while a graph or a stepper records, nor into
+// caller-provided or static work memory); automatic up to a padded order of
+// kSingleMaxLd.  One ordinary launch of flow_tasks_kernel over the whole
+// matrix: int32 up to a padded order of 768 in 32-wide blocks (twice the
+// rounds of 64-wide ones, each round's chain much shorter; above that the
+// task count makes the shared task counter the bottleneck), else 64-wide
+// blocks -- float32 always, the blocking of the per-phase launches, so the
+// rounding is theirs too.  (Measured on MI355X, int32 distances, ms per
+// solve, per-phase launches / 32-wide tasks / 64-wide tasks: n = 256 0.111
+// / 0.082 / 0.107; 512 0.217 / 0.155 / 0.204; 1024 0.440 / 0.465 / 0.398;
+// 2048 1.180 / 3.03 / 0.838; 3072 2.45 / - / 1.78; 4032 4.43 / - / 3.46.)
 constexpr int64_t kSingleMaxLd = 4096;
-
-// Workgroups of `kernel` taken as resident at once (0 without cooperative
-// launches), looked up once per device: the occupancy the runtime reports,
-// but at most 4 workgroups per CU.  (A dataflow solve of 1600 workgroups,
-// 6.25 per CU and within the reported occupancy of 7, ended in a barrier
-// timeout on MI355X, as if not all of them had been resident; every
-// configuration of at most 4 per CU completes.)
-constexpr int kCoopMaxPerCU = 4;
-apsp_status_t coop_capacity(const void *kernel, int dev, int threads, int *out) {
-    static std::mutex mu;
-    static std::map<std::pair<const void *, int>, int> cache;
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find({kernel, dev});
-    if (it == cache.end()) {
-        int coop = 0, cus = 0, per_cu = 0;
-        APSP_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-        APSP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        APSP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
-        it = cache.emplace(std::make_pair(kernel, dev), coop ? std::min(per_cu, kCoopMaxPerCU) * cus : 0).first;
-    }
-    *out = it->second;
-    return APSP_SUCCESS;
-}
 
 inline bool single_applies(int64_t ld, int bs, int tt, bool with_pred, bool f32w, int schedule, bool ext_ws) {
     if (with_pred || f32w || bs != kSingleBS || tt != 4 || ext_ws || t_capturing || t_rec || t_noalloc)
@@ -1799,80 +1657,43 @@ inline bool single_applies(int64_t ld, int bs, int tt, bool with_pred, bool f32w
     return schedule == 3 || (schedule == 0 && ld <= kSingleMaxLd);
 }
 
-// Which single-launch kernel serves padded order ld (groups 0: none fits).
-// int32 takes 32-wide blocks in the dataflow kernel where they fit (twice
-// the rounds, but each round's chain of closure, panel product and
-// next-diagonal product is about 2.6x shorter: measured on MI355X, n = 1024,
-// 0.307 ms against 0.383 ms with 64-wide blocks); float32 keeps 64-wide
-// blocks, the blocking of the per-phase launches, so its rounding is theirs.
+// The single launch's shape for padded order ld.
 struct SinglePlan {
-    int flow_bs = 0;  // 32 or 64: the dataflow kernel; 0: the barrier-phased one
-    int groups = 0;
-    size_t word_bytes = 0;  // ready or barrier words
-    size_t pub_bytes = 0;   // the dataflow kernel's two publication matrices
+    int bs = 0;             // 32 or 64
+    int groups = 0;         // workgroups taking tasks
+    size_t word_bytes = 0;  // task words
+    size_t pub_bytes = 0;   // the two publication matrices
 };
-template <class Ar>
-apsp_status_t single_plan(int dev, int64_t ld, SinglePlan *out) {
-    SinglePlan p;
-    auto try_flow = [&](auto bs_tag) -> apsp_status_t {
-        constexpr int bs = decltype(bs_tag)::value;
-        int cap = 0;
-        apsp_status_t st = coop_capacity(reinterpret_cast<const void *>(&rounds_flow_kernel<Ar, bs>), dev,
-                                         kSingleThreads, &cap);
-        const int64_t R = ld / bs;
-        if (st == APSP_SUCCESS && !p.flow_bs && R * R <= cap) {
-            p.flow_bs = bs;
-            p.groups = (int)(R * R);
-            p.word_bytes = flow_word_bytes((int)R);
-            p.pub_bytes = 2 * (size_t)(ld * ld) * 4;
-        }
-        return st;
-    };
-    apsp_status_t st = APSP_SUCCESS;
-#ifndef APSP_SINGLE_PHASED_ONLY
-    if constexpr (std::is_same_v<Ar, ArI32>) st = try_flow(std::integral_constant<int, 32>{});
-    if (st == APSP_SUCCESS) st = try_flow(std::integral_constant<int, 64>{});
-    if (st != APSP_SUCCESS) return st;
+#ifndef APSP_TASK32_MAX_LD
+#define APSP_TASK32_MAX_LD 768
 #endif
-    if (!p.flow_bs) {
-        int cap = 0;
-        st = coop_capacity(reinterpret_cast<const void *>(&rounds_single_kernel<Ar>), dev, kSingleThreads, &cap);
-        if (st != APSP_SUCCESS) return st;
-        if (cap > 0) {
-            const int64_t m = ld / kSingleBS - 1;
-            const int64_t want = std::max<int64_t>(1, std::max(m * m, 2 * m));
-            p.groups = (int)std::min<int64_t>(std::min<int64_t>(want, cap), kSingleMaxGroups);
-            p.word_bytes = kSingleWordBytes;
-        }
-    }
-    *out = p;
-    return APSP_SUCCESS;
+template <class Ar>
+SinglePlan single_plan(int cus, int64_t ld) {
+    SinglePlan p;
+    p.bs = std::is_same_v<Ar, ArI32> && ld <= APSP_TASK32_MAX_LD ? 32 : 64;
+    const int64_t R = ld / p.bs, m = R - 1;
+    // workgroups: one per task of a round's phase 3, at most 4 per CU
+    p.groups = (int)std::max<int64_t>(1, std::min<int64_t>(m * m, 4 * (int64_t)cus));
+    p.word_bytes = task_word_bytes((int)R);
+    p.pub_bytes = 2 * (size_t)(ld * ld) * 4;
+    return p;
 }
 
 template <class Ar>
-apsp_status_t run_single(void *X, int64_t ld, const Ar &ar, const SinglePlan &plan, void *ws, int32_t *status,
-                         const int32_t *skip, hipStream_t s) {
+void run_single(void *X, int64_t ld, const Ar &ar, const SinglePlan &plan, void *ws, int32_t *status,
+                const int32_t *skip, hipStream_t s) {
     ProfScope ps(kSingle, (double)ld * (double)ld * (double)ld, s);
-    void *x = X;
-    int64_t l = ld;
-    Ar a = ar;
-    int32_t *stt = status;
-    const int32_t *sk = skip;
-    if (plan.flow_bs) {
-        uint32_t *wd = (uint32_t *)((char *)ws + plan.pub_bytes);
-        void *prow = ws, *pcol = (char *)ws + plan.pub_bytes / 2;
-        void *args[] = {&x, &l, &l, &a, &wd, &prow, &pcol, &stt, &sk};
-        const void *k = reinterpret_cast<const void *>(&rounds_flow_kernel<Ar, 64>);
-        if constexpr (std::is_same_v<Ar, ArI32>)
-            if (plan.flow_bs == 32) k = reinterpret_cast<const void *>(&rounds_flow_kernel<Ar, 32>);
-        APSP_HIP(hipLaunchCooperativeKernel(k, dim3(plan.groups), dim3(kSingleThreads), args, 0, s));
-    } else {
-        uint32_t *wd = (uint32_t *)ws;
-        void *args[] = {&x, &l, &a, &wd, &stt, &sk};
-        APSP_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&rounds_single_kernel<Ar>),
-                                            dim3(plan.groups), dim3(kSingleThreads), args, 0, s));
+    uint32_t *words = (uint32_t *)((char *)ws + plan.pub_bytes);
+    void *prow = ws, *pcol = (char *)ws + plan.pub_bytes / 2;
+    if constexpr (std::is_same_v<Ar, ArI32>) {
+        if (plan.bs == 32) {
+            enq((flow_tasks_kernel<Ar, 32>), dim3(plan.groups), dim3(kSingleThreads), s, X, ld, ld, ar, words, prow,
+                pcol, status, skip);
+            return;
+        }
     }
-    return APSP_SUCCESS;
+    enq((flow_tasks_kernel<Ar, 64>), dim3(plan.groups), dim3(kSingleThreads), s, X, ld, ld, ar, words, prow, pcol,
+        status, skip);
 }
 
 template <class T>
@@ -1903,30 +1724,24 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
     const int32_t *skip = nullptr;
     const bool f32w = std::is_same_v<T, int32_t> && use_f32w(n, APSP_INT32, with_pred, opt.arith);
     using ArPlain = std::conditional_t<std::is_same_v<T, int32_t>, ArI32, ArF32>;
-    bool single = single_applies(ld, bs, tt, with_pred, f32w, opt.schedule, ext_ws != nullptr);
+    const bool single = single_applies(ld, bs, tt, with_pred, f32w, opt.schedule, ext_ws != nullptr);
     SinglePlan plan;
     if (single) {
-        apsp_status_t st = single_plan<ArPlain>(dev, ld, &plan);
-        if (st != APSP_SUCCESS) return st;
-        if (plan.groups <= 0) {
-            if (opt.schedule == 3) return APSP_ERROR_INVALID_ARGUMENT;
-            single = false;
-        }
+        int cus = 0;
+        APSP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        plan = single_plan<ArPlain>(cus, ld);
     }
-    // single-launch schedule: [work matrix if padded][publication matrices][words]
+    // single-launch schedule: [work matrix if padded][publication matrices][task words]
     void *single_ws = nullptr, *single_aux = nullptr;
     const size_t single_mat = (ld == n && (uintptr_t)dist % 16 == 0) ? 0 : (size_t)(ld * ld) * sizeof(T);
     if (single) {
         apsp_status_t st = workspace(dev, s, single_mat + plan.pub_bytes + plan.word_bytes, &single_ws);
         if (st != APSP_SUCCESS) return st;
         single_aux = (char *)single_ws + single_mat;
+        // (the work memory is shared with other solves on this stream: its words are cleared per solve)
         uint32_t *words = (uint32_t *)((char *)single_aux + plan.pub_bytes);
-        if (plan.flow_bs) {
-            const int count = (int)(plan.word_bytes / 4);
-            enq(flow_init_kernel, dim3(std::min(64, (count + 255) / 256)), dim3(256), s, words, count, status);
-        } else {
-            enq(single_init_kernel, dim3(1), dim3(256), s, words, status);
-        }
+        const int count = (int)(plan.word_bytes / 4);
+        enq(flow_init_kernel, dim3(std::min(64, (count + 255) / 256)), dim3(256), s, words, count, status);
     } else if (status) {
         enq(status_init_kernel, dim3(1), dim3(1), s, status);
     }
@@ -2045,9 +1860,10 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
                                ld, inf, skip);
         }
         apsp_status_t st;
-        if (single)
-            st = run_single<ArPlain>(X, ld, ArPlain{}, plan, single_aux, status, skip, s);
-        else
+        if (single) {
+            run_single<ArPlain>(X, ld, ArPlain{}, plan, single_aux, status, skip, s);
+            st = APSP_SUCCESS;
+        } else
             st = run_rounds_bs<ArPlain>(bs, tt, lookahead, X, ld, ArPlain{}, s, skip);
         if (st != APSP_SUCCESS) return st;
         // (a failed single-launch wait leaves APSP_ERROR_TIMEOUT in status: no wrap-up then)
