@@ -387,17 +387,21 @@ __global__ void flow_init_kernel(uint32_t *words, int count, int32_t *status) {
     if (status && blockIdx.x == 0 && threadIdx.x == 0) *status = APSP_SUCCESS;
 }
 
-// Dataflow solve as a ticketed task graph (the phase-1 closure of 128- and
-// 256-wide blocks): the tasks of the blocked schedule over BS-wide
-// sub-blocks are numbered in an order where every task's operands come
-// from tasks with smaller numbers --
-//   0                              phase 1 of sub-round 0 on block (0, 0)
-//   then per round r, m = R - 1:   2m panel products (block row r, then
-//                                  block column r), then m^2 products of
-//                                  the remaining blocks, block (r+1, r+1)
-//                                  first, closed at once (phase 1 of r+1)
+// Dataflow solve as a ticketed task graph: the tasks of the blocked
+// schedule over BS-wide blocks are numbered in an order where every task's
+// operands come from tasks with smaller numbers --
+//   0                         phase 1 of round 0 on block (0, 0)
+//   then per round r < R-1:   2m panel products (block row r, then block
+//                             column r; m = R - 1), block (r+1, r+1)
+//                             (phase 3, then at once its phase 1 of round
+//                             r+1), the other blocks of block row and
+//                             column r+1 (the next round's panels), then
+//                             the remaining (m-1)^2 blocks in chunks of K
+//   last round:               2m panel products, m^2 blocks in chunks of K
 // -- and a workgroup takes the next number from a counter, waits for the
-// operands it reads and does the task, over and over.  A task only waits
+// operands it reads and does the task (or chunk), over and over.  The
+// next round's chain (its panels, its diagonal block) comes first in each
+// round; chunks keep the counter's traffic low.  A task only waits
 // for smaller numbers, which running workgroups hold, so the launch makes
 // progress however few of its workgroups are resident and whatever else
 // runs on the device.  Block states live in X (device-coherent loads and
@@ -411,8 +415,15 @@ __host__ __device__ constexpr int task_fail_word(int R) { return R * R + 32; }
 __host__ __device__ constexpr int task_next_word(int R) { return R * R + 64; }
 __host__ __device__ constexpr int task_done_word(int R) { return R * R + 96; }
 __host__ __device__ constexpr size_t task_word_bytes(int R) { return ((size_t)R * R + 128) * 4; }
-__host__ __device__ constexpr int64_t task_count(int R) {
-    return 1 + (int64_t)R * (R - 1) * (R + 1);  // R rounds of m (m + 2) tasks, m = R - 1
+// numbers per round r < R - 1, and in the last round (chunks of K)
+__host__ __device__ constexpr int64_t task_round(int R, int K) {
+    return 2 * (R - 1) + 1 + 2 * (R - 2) + ((int64_t)(R - 2) * (R - 2) + K - 1) / K;
+}
+__host__ __device__ constexpr int64_t task_last(int R, int K) {
+    return 2 * (R - 1) + ((int64_t)(R - 1) * (R - 1) + K - 1) / K;
+}
+__host__ __device__ constexpr int64_t task_count(int R, int K) {
+    return R == 1 ? 1 : 1 + (int64_t)(R - 1) * task_round(R, K) + task_last(R, K);
 }
 
 // Waits (thread 0 polling) until *w0 >= v0 and, if w1, *w1 >= v1; the
@@ -453,7 +464,7 @@ __device__ __forceinline__ void ld_tt_dev(const T *p, T *out) {
 template <class Ar, int BS>
 __global__ void __launch_bounds__(kSingleThreads) __attribute__((amdgpu_waves_per_eu(4)))
 flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *words, void *prow_v, void *pcol_v,
-                  int32_t *status, const int32_t *__restrict__ skip) {
+                  int32_t *status, const int32_t *__restrict__ skip, int K) {
     using T = typename Ar::T;
     static_assert(sizeof(T) == 4, "4-byte elements");
     constexpr int TT = flow_tile<BS>();
@@ -474,7 +485,7 @@ flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *word
     const int tid = (int)threadIdx.x, tx = tid % PS::TX, ty = tid / PS::TX;
     uint32_t *const ver = words;
     uint32_t *const fail = words + task_fail_word(R);
-    const uint32_t total = (uint32_t)task_count(R), per_round = (uint32_t)(m * (m + 2));
+    const uint32_t total = (uint32_t)task_count(R, K), per_round = R > 1 ? (uint32_t)task_round(R, K) : 1u;
     auto blk = [&](T *M, uint32_t ld, int p, int q) __attribute__((always_inline)) {
         return M + ((uint32_t)p * BS * ld + (uint32_t)q * BS);
     };
@@ -548,8 +559,10 @@ flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *word
             finish(0, 0, Prow, 1u);
             continue;
         }
-        const int r = (int)((t - 1) / per_round);
-        const int u = (int)((t - 1) % per_round);
+        const uint32_t t1 = t - 1;
+        const bool ahead = t1 < (uint32_t)(R - 1) * per_round;
+        const int r = ahead ? (int)(t1 / per_round) : R - 1;
+        int u = ahead ? (int)(t1 % per_round) : (int)(t1 - (uint32_t)(R - 1) * per_round);
         if (u < 2 * m) {
             const bool row = u < m;
             int q = row ? u : u - m;
@@ -575,28 +588,46 @@ flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *word
             finish(i, j, row ? Prow : Pcol, (uint32_t)r + 1);
             continue;
         }
-        // the remaining blocks, block (r+1, r+1) first
-        int a = u - 2 * m;
-        const bool ahead = r + 1 < R;
+        u -= 2 * m;
+        // one phase-3 block (i, j) of round r: c <- min(c, P_col(i, r) (x) P_row(r, j))
+        auto p3 = [&](int i, int j) __attribute__((always_inline)) {
+            if (!(ok = task_wait(&ver[i * R + j], (uint32_t)r, nullptr, 0u, fail, &ok_lds))) return;
+            if (!(ok = task_wait(&ver[i * R + r], (uint32_t)r + 1, &ver[r * R + j], (uint32_t)r + 1, fail, &ok_lds)))
+                return;
+            load(i, j);
+            flow_copy<BS, kSingleThreads, true>(la, blk(Pcol, ordu, i, r), ordu);
+            flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, j), ordu);
+            multiply();
+            if (i == r + 1 && j == r + 1) {
+                close();
+                finish(i, j, Prow, (uint32_t)r + 2);
+            } else {
+                finish(i, j, nullptr, (uint32_t)r + 1);
+            }
+        };
         if (ahead) {
-            const int lead = r * m + r;
-            a = a == 0 ? lead : (a - 1 >= lead ? a : a - 1);
-        }
-        int i = a / m, j = a - (a / m) * m;
-        i += i >= r;
-        j += j >= r;
-        if (!(ok = task_wait(&ver[i * R + j], (uint32_t)r, nullptr, 0u, fail, &ok_lds))) continue;
-        if (!(ok = task_wait(&ver[i * R + r], (uint32_t)r + 1, &ver[r * R + j], (uint32_t)r + 1, fail, &ok_lds)))
-            continue;
-        load(i, j);
-        flow_copy<BS, kSingleThreads, true>(la, blk(Pcol, ordu, i, r), ordu);
-        flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, j), ordu);
-        multiply();
-        if (ahead && i == r + 1 && j == r + 1) {
-            close();
-            finish(i, j, Prow, (uint32_t)r + 2);
+            const int w = m - 1;  // indices outside {r, r+1}: q -> q + (q >= r ? 2 : 0)
+            if (u == 0) {
+                p3(r + 1, r + 1);
+            } else if (u - 1 < 2 * w) {
+                const int q = (u - 1) % w, x = q + (q >= r ? 2 : 0);
+                if (u - 1 < w)
+                    p3(r + 1, x);
+                else
+                    p3(x, r + 1);
+            } else {
+                const int c0 = (u - 1 - 2 * w) * K, c1 = min(c0 + K, w * w);
+                for (int a = c0; a < c1 && ok; ++a) {
+                    const int qi = a / w, qj = a - (a / w) * w;
+                    p3(qi + (qi >= r ? 2 : 0), qj + (qj >= r ? 2 : 0));
+                }
+            }
         } else {
-            finish(i, j, nullptr, (uint32_t)r + 1);
+            const int c0 = u * K, c1 = min(c0 + K, m * m);
+            for (int a = c0; a < c1 && ok; ++a) {
+                const int qi = a / m, qj = a - (a / m) * m;
+                p3(qi + (qi >= r), qj + (qj >= r));
+            }
         }
     }
     if constexpr (Ar::kWatch) {
@@ -1459,7 +1490,7 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
                 char *const c = (char *)closure;
                 enq((flow_tasks_kernel<Ar, kClosureBS>), dim3(RC * RC), dim3(kSingleThreads), s,
                     (void *)((typename Ar::T *)X + (int64_t)r * BS * ld + (int64_t)r * BS), (int64_t)BS, ld, ar,
-                    (uint32_t *)(c + 2 * kClosurePub), (void *)c, (void *)(c + kClosurePub), t_status, skip);
+                    (uint32_t *)(c + 2 * kClosurePub), (void *)c, (void *)(c + kClosurePub), t_status, skip, 1);
                 return;
             }
         }
@@ -1660,6 +1691,7 @@ inline bool single_applies(int64_t ld, int bs, int tt, bool with_pred, bool f32w
 // The single launch's shape for padded order ld.
 struct SinglePlan {
     int bs = 0;             // 32 or 64
+    int chunk = 1;          // remaining phase-3 blocks per task number
     int groups = 0;         // workgroups taking tasks
     size_t word_bytes = 0;  // task words
     size_t pub_bytes = 0;   // the two publication matrices
@@ -1667,10 +1699,20 @@ struct SinglePlan {
 #ifndef APSP_TASK32_MAX_LD
 #define APSP_TASK32_MAX_LD 768
 #endif
+// (chunks of more than one remaining block were slower at every size
+// measured: n = 256 0.100 ms with chunks of 4 against 0.082 with single
+// blocks; n = 1024 0.407 with chunks of 2 against 0.397)
+#ifndef APSP_TASK32_CHUNK
+#define APSP_TASK32_CHUNK 1
+#endif
+#ifndef APSP_TASK64_CHUNK
+#define APSP_TASK64_CHUNK 1
+#endif
 template <class Ar>
 SinglePlan single_plan(int cus, int64_t ld) {
     SinglePlan p;
     p.bs = std::is_same_v<Ar, ArI32> && ld <= APSP_TASK32_MAX_LD ? 32 : 64;
+    p.chunk = p.bs == 32 ? APSP_TASK32_CHUNK : APSP_TASK64_CHUNK;
     const int64_t R = ld / p.bs, m = R - 1;
     // workgroups: one per task of a round's phase 3, at most 4 per CU
     p.groups = (int)std::max<int64_t>(1, std::min<int64_t>(m * m, 4 * (int64_t)cus));
@@ -1688,12 +1730,12 @@ void run_single(void *X, int64_t ld, const Ar &ar, const SinglePlan &plan, void 
     if constexpr (std::is_same_v<Ar, ArI32>) {
         if (plan.bs == 32) {
             enq((flow_tasks_kernel<Ar, 32>), dim3(plan.groups), dim3(kSingleThreads), s, X, ld, ld, ar, words, prow,
-                pcol, status, skip);
+                pcol, status, skip, plan.chunk);
             return;
         }
     }
     enq((flow_tasks_kernel<Ar, 64>), dim3(plan.groups), dim3(kSingleThreads), s, X, ld, ld, ar, words, prow, pcol,
-        status, skip);
+        status, skip, plan.chunk);
 }
 
 template <class T>
