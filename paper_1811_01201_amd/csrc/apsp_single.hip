@@ -411,10 +411,13 @@ __global__ void flow_init_kernel(uint32_t *words, int count, int32_t *status) {
 // or closed block is published once ver passes that round), then the fail
 // word, the task counter and the finished-workgroup count; zero before a
 // launch, zeroed again by the last workgroup to finish.
-__host__ __device__ constexpr int task_fail_word(int R) { return R * R + 32; }
-__host__ __device__ constexpr int task_next_word(int R) { return R * R + 64; }
-__host__ __device__ constexpr int task_done_word(int R) { return R * R + 96; }
-__host__ __device__ constexpr size_t task_word_bytes(int R) { return ((size_t)R * R + 128) * 4; }
+// (the fail word, the counter and the count 1 KiB apart: every waiting
+// workgroup reads the fail word, every task bumps the counter)
+__host__ __device__ constexpr int task_fail_word(int R) { return R * R + 256; }
+__host__ __device__ constexpr int task_next_word(int R) { return R * R + 512; }
+__host__ __device__ constexpr int task_done_word(int R) { return R * R + 768; }
+__host__ __device__ constexpr int task_words(int R) { return R * R + 1024; }
+__host__ __device__ constexpr size_t task_word_bytes(int R) { return (size_t)task_words(R) * 4; }
 // numbers per round r < R - 1, and in the last round (chunks of K)
 __host__ __device__ constexpr int64_t task_round(int R, int K) {
     return 2 * (R - 1) + 1 + 2 * (R - 2) + ((int64_t)(R - 2) * (R - 2) + K - 1) / K;
@@ -438,7 +441,7 @@ __device__ __forceinline__ bool task_wait(const uint32_t *w0, uint32_t v0, const
                 ok = 0;
                 break;
             }
-            if (ld_agent(fail) != 0) {
+            if ((spin & 31) == 31 && ld_agent(fail) != 0) {  // (now and then: one word all waiters share)
                 ok = 0;
                 break;
             }
@@ -568,10 +571,10 @@ flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *word
             int q = row ? u : u - m;
             q += q >= r;
             const int i = row ? r : q, j = row ? q : r;
-            // its own round r - 1 and the closed block r
-            if (!(ok = task_wait(&ver[i * R + j], (uint32_t)r, &ver[r * R + r], (uint32_t)r + 1, fail, &ok_lds)))
-                continue;
+            // its own round r - 1 (loaded while the closed block r is awaited)
+            if (!(ok = task_wait(&ver[i * R + j], (uint32_t)r, nullptr, 0u, fail, &ok_lds))) continue;
             load(i, j);
+            if (!(ok = task_wait(&ver[r * R + r], (uint32_t)r + 1, nullptr, 0u, fail, &ok_lds))) continue;
             if (row) {  // c <- min(c, D(r,r)* (x) c)
                 flow_copy<BS, kSingleThreads, true>(la, blk(Prow, ordu, r, r), ordu);
 #pragma unroll
@@ -592,9 +595,9 @@ flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *word
         // one phase-3 block (i, j) of round r: c <- min(c, P_col(i, r) (x) P_row(r, j))
         auto p3 = [&](int i, int j) __attribute__((always_inline)) {
             if (!(ok = task_wait(&ver[i * R + j], (uint32_t)r, nullptr, 0u, fail, &ok_lds))) return;
+            load(i, j);  // (in flight while the panels are awaited)
             if (!(ok = task_wait(&ver[i * R + r], (uint32_t)r + 1, &ver[r * R + j], (uint32_t)r + 1, fail, &ok_lds)))
                 return;
-            load(i, j);
             flow_copy<BS, kSingleThreads, true>(la, blk(Pcol, ordu, i, r), ordu);
             flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, j), ordu);
             multiply();
@@ -641,7 +644,7 @@ flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *word
                  gridDim.x - 1;
     __syncthreads();
     if (ok_lds)
-        for (int k = tid; k < R * R + 128; k += kSingleThreads) st_agent(&words[k], 0u);
+        for (int k = tid; k < task_words(R); k += kSingleThreads) st_agent(&words[k], 0u);
 }
 
 // ------------------------------------------------------ set-up / wrap-up
