@@ -129,10 +129,11 @@ typedef struct {
                               second stream; 1 = one stream, rounds in order; 2 = the
                               two-stream split at any size with at least three rounds
                               (the device-gated fallback passes always run in order);
-                              3 = every round in one cooperative launch whose workgroups
-                              (all resident at once) meet at device-wide barriers, two per
-                              round, or, where one workgroup per 64 x 64 block fits,
-                              waiting per block only for the panels it reads --
+                              3 = every round in one launch: the blocked schedule over
+                              small blocks (32-wide for int32 up to a padded order of 768,
+                              else 64-wide) as a graph of tasks that workgroups take in
+                              dependency order, each waiting only for the blocks it reads
+                              (no co-residency needed, so concurrent solves are fine) --
                               automatic (0) for distance solves up to a padded
                               order of 4096 issued directly (not under use_graph, a
                               stepper or apsp_solve_noalloc).  3 requires distances only,
@@ -160,10 +161,11 @@ typedef struct {
                               the original weights instead.  The results are the same. */
     int32_t *d_status;     /* device int32 or NULL: receives APSP_SUCCESS,
                               APSP_ERROR_INVALID_VALUE or APSP_ERROR_NEGATIVE_CYCLE, or
-                              APSP_ERROR_TIMEOUT if a barrier wait of the single-launch
-                              schedule ran out (about a second; its workgroups are
-                              resident together, so only a faulty device gets there;
-                              dist is then partly updated) */
+                              APSP_ERROR_TIMEOUT if a wait inside a dataflow kernel (the
+                              single launch, the phase-1 closure) ran out (a second or
+                              more; every wait is for work that running workgroups hold,
+                              so only a faulty device gets there; dist is then partly
+                              updated) */
     int32_t *d_arith;      /* device int32 or NULL: receives 1 if the result came from float32
                               arithmetic (with predecessors: the float32 route held), 0 if
                               from int32 arithmetic (the recurrence) */
