@@ -135,9 +135,9 @@ typedef struct {
                               dependency order, each waiting only for the blocks it reads
                               (no co-residency needed, so concurrent solves are fine) --
                               automatic (0) for distance solves up to a padded
-                              order of 4096 issued directly (not under use_graph, a
+                              order of 4096 (directly or under use_graph; not in a
                               stepper or apsp_solve_noalloc).  3 requires distances only,
-                              n <= 16384, block_size 0 or 64, thread_tile 0 or 4, use_graph 0 and, for
+                              n <= 16384, block_size 0 or 64, thread_tile 0 or 4 and, for
                               int32 weights, arith 0 or 1 (int32 arithmetic), else
                               APSP_ERROR_INVALID_ARGUMENT; the values equal those of the
                               other schedules bit for bit */

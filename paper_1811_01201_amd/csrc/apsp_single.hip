@@ -1672,7 +1672,7 @@ size_t work_bytes(int64_t n, bool with_pred, int opt_bs, bool aligned, apsp_dtyp
 
 // Single-launch schedule: distances only, 64-wide blocks with 4 x 4 thread
 // tiles, 4-byte arithmetic without a watch (int32 in int32, float32),
-// issued directly (not while a graph or a stepper records, nor into
+// issued directly or into a hipGraph (not while a stepper records, nor into
 // caller-provided or static work memory); automatic up to a padded order of
 // kSingleMaxLd.  One ordinary launch of flow_tasks_kernel over the whole
 // matrix: int32 up to a padded order of 768 in 32-wide blocks (twice the
@@ -1686,8 +1686,7 @@ size_t work_bytes(int64_t n, bool with_pred, int opt_bs, bool aligned, apsp_dtyp
 constexpr int64_t kSingleMaxLd = 4096;
 
 inline bool single_applies(int64_t ld, int bs, int tt, bool with_pred, bool f32w, int schedule, bool ext_ws) {
-    if (with_pred || f32w || bs != kSingleBS || tt != 4 || ext_ws || t_capturing || t_rec || t_noalloc)
-        return false;
+    if (with_pred || f32w || bs != kSingleBS || tt != 4 || ext_ws || t_rec || t_noalloc) return false;
     return schedule == 3 || (schedule == 0 && ld <= kSingleMaxLd);
 }
 
@@ -1739,6 +1738,19 @@ void run_single(void *X, int64_t ld, const Ar &ar, const SinglePlan &plan, void 
     }
     enq((flow_tasks_kernel<Ar, 64>), dim3(plan.groups), dim3(kSingleThreads), s, X, ld, ld, ar, words, prow, pcol,
         status, skip, plan.chunk);
+}
+
+// Work memory of a single-launch solve (0 if the options do not take one):
+// made before a graph capture, which cannot allocate.
+size_t single_work_bytes(int64_t n, apsp_dtype_t dtype, bool with_pred, bool aligned, const apsp_options_t &opt) {
+    const int bs = opt.block_size ? opt.block_size : auto_block(n, with_pred);
+    const int tt = opt.thread_tile ? opt.thread_tile : auto_tile(n, bs);
+    const int64_t ld = (n + bs - 1) / bs * bs;
+    const bool f32w = dtype == APSP_INT32 && use_f32w(n, APSP_INT32, with_pred, opt.arith);
+    if (!single_applies(ld, bs, tt, with_pred, f32w, opt.schedule, false)) return 0;
+    const SinglePlan p = dtype == APSP_INT32 ? single_plan<ArI32>(256, ld) : single_plan<ArF32>(256, ld);
+    const size_t mat = (ld == n && aligned) ? 0 : (size_t)(ld * ld) * 4;
+    return mat + p.pub_bytes + p.word_bytes;
 }
 
 template <class T>
@@ -2001,7 +2013,17 @@ apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dty
     const int tt = opt.thread_tile ? opt.thread_tile : auto_tile(n, bs);
     // the work memory must exist (at its final address) before recording
     void *w = ws;
-    const size_t need = work_bytes(n, with_pred, opt.block_size, ((uintptr_t)dist % 16) == 0, dtype, opt.arith);
+    const bool aligned = ((uintptr_t)dist % 16) == 0;
+    size_t need = work_bytes(n, with_pred, opt.block_size, aligned, dtype, opt.arith);
+    if (!ws) {
+        apsp_options_t o = opt;  // the single launch's configuration, as solve_direct sets it
+        if (o.schedule == 3) {
+            o.block_size = 64;
+            o.thread_tile = 4;
+            if (dtype == APSP_INT32) o.arith = 1;
+        }
+        need = std::max(need, single_work_bytes(n, dtype, with_pred, aligned, o));
+    }
     if (!w && need > 0) {
         apsp_status_t st = cached_workspace(dev, s, need, &w);
         if (st != APSP_SUCCESS) return st;
@@ -2067,10 +2089,10 @@ apsp_status_t check_options(int64_t n, apsp_dtype_t dtype, bool with_pred, const
     if (opt.validate && !opt.d_status) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.schedule < 0 || opt.schedule > 3) return APSP_ERROR_INVALID_ARGUMENT;
     // the single-launch schedule: distances on 64-wide blocks with 4 x 4 thread
-    // tiles, int32 weights in int32 arithmetic, issued directly
+    // tiles, int32 weights in int32 arithmetic
     if (opt.schedule == 3 &&
         (with_pred || n > kSingleMaxN || (opt.block_size != 0 && opt.block_size != 64) ||
-         (opt.thread_tile != 0 && opt.thread_tile != 4) || opt.use_graph || (dtype == APSP_INT32 && opt.arith == 2)))
+         (opt.thread_tile != 0 && opt.thread_tile != 4) || (dtype == APSP_INT32 && opt.arith == 2)))
         return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.phase1 < 0 || opt.phase1 > 3) return APSP_ERROR_INVALID_ARGUMENT;
     if (opt.phase1 == 2 && opt.block_size != 256) return APSP_ERROR_INVALID_ARGUMENT;

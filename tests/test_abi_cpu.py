@@ -62,8 +62,8 @@ def test_host_side_argument_errors():
     bad_schedule = apsp.Options(0, 0, 0, 4, 0, 0, None)
     assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, bad_schedule) == apsp.INVALID_ARGUMENT
     # the single-launch schedule (3): distances, 64-wide blocks, 4 x 4 thread
-    # tiles, int32 arithmetic for int32 weights, issued directly
-    for kw in (dict(block_size=128), dict(thread_tile=8), dict(use_graph=1), dict(arith=2)):
+    # tiles, int32 arithmetic for int32 weights
+    for kw in (dict(block_size=128), dict(thread_tile=8), dict(arith=2)):
         o = apsp.Options(0, kw.get("block_size", 0), kw.get("thread_tile", 0), 3, kw.get("use_graph", 0),
                          kw.get("arith", 0), None)
         assert apsp.solve_raw(fake, None, 10, apsp.INT32, None, o) == apsp.INVALID_ARGUMENT, kw

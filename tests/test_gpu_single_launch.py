@@ -168,8 +168,36 @@ def test_single_launch_rejected_where_it_does_not_apply():
     describe("single launch: option checks")
     d = torch.zeros((100, 100), dtype=torch.int32, device="cuda")
     p = torch.zeros((100, 100), dtype=torch.int32, device="cuda")
-    bad = [dict(schedule=3, block_size=128), dict(schedule=3, thread_tile=8), dict(schedule=3, use_graph=True),
-           dict(schedule=3, arith=2), dict(schedule=4)]
+    bad = [dict(schedule=3, block_size=128), dict(schedule=3, thread_tile=8), dict(schedule=3, arith=2),
+           dict(schedule=4)]
     for kw in bad:
         assert apsp.solve(d, check=False, **kw) == apsp.INVALID_ARGUMENT, kw
     assert apsp.solve(d, p, check=False, schedule=3) == apsp.INVALID_ARGUMENT
+
+
+@pytest.mark.parametrize("n,schedule,dtype", [(1024, 0, "int"), (300, 3, "int"), (1000, 3, "f32"), (2500, 3, "int")])
+def test_single_launch_in_a_graph_replayed(orc, n, schedule, dtype):
+    """The single launch recorded into a hipGraph (its work memory made before
+    the capture) and replayed several times, with other work on the device
+    between the replays: every replay exact."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe(f"single launch: hipGraph replays n={n} schedule={schedule} {dtype}")
+    W = _graph(dtype, n)
+    D0, _, _ = oracle_expect(orc, W)
+    s = torch.cuda.Stream()
+    w = torch.from_numpy(W).cuda()
+    d = torch.empty_like(w)  # one buffer set: the first call captures, the others replay
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    for rep in range(3):
+        d.copy_(w)
+        st.fill_(-1)
+        torch.cuda.synchronize()
+        apsp.solve(d, status=st, stream=s, use_graph=True, schedule=schedule)
+        s.synchronize()
+        junk = torch.randn(256, 256, device="cuda") @ torch.randn(256, 256, device="cuda")
+        torch.cuda.synchronize()
+        del junk
+        assert int(st.item()) == 0, rep
+        assert first_mismatch(d.cpu().numpy(), D0) is None, rep
