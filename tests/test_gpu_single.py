@@ -263,9 +263,9 @@ def test_full_size_n32768_potential_sampled_rows(orc, half):
     """The n=32768 int32 potential-weight workload (negative weights, no
     negative cycle) in the launch configuration the benchmark times
     (automatic block size 256, two-stream schedule, phase 1 as the dataflow
-    closure over 32-wide sub-blocks, one kRest launch per round): one row
+    closure over 32-wide sub-blocks, one kRest launch per round): two rows
     in every other block row (the two halves together cover all 128 block
-    rows, at varying offsets inside the block) against the row oracle
+    rows with 256 rows, at varying offsets inside the block) against the row oracle
     exactly, and properties that hold at any size checked on every element:
     zero diagonal, D <= W, and D(i,j) <= D(i,k) + D(k,j) for 32 values of k
     spread over the block rows."""
@@ -285,7 +285,7 @@ def test_full_size_n32768_potential_sampled_rows(orc, half):
     assert int(st.item()) == 0
     assert int(used.item()) == 1  # the float32 arithmetic held (exact)
     assert prof["phase1_flow"]["launches"] == n // 256 and prof["phase3_cross"]["launches"] == n // 256 - 1
-    srcs = [256 * r + (37 * r + 11 * half) % 256 for r in range(half, n // 256, 2)]
+    srcs = [256 * r + (37 * r + 11 * half + 128 * e) % 256 for r in range(half, n // 256, 2) for e in (0, 1)]
     got = d[torch.tensor(srcs, device="cuda")].cpu().numpy()
     for src, g, (dr, _, s) in zip(srcs, got, orc.rows(W, srcs)):
         assert s == 0
