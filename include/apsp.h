@@ -169,7 +169,7 @@ typedef struct {
     int32_t *d_arith;      /* device int32 or NULL: receives 1 if the result came from float32
                               arithmetic (with predecessors: the float32 route held), 0 if
                               from int32 arithmetic (the recurrence) */
-    int32_t phase1;        /* 0 = automatic: the dataflow closure (3) on the exact routes
+    int32_t phase1;        /* 0 = automatic: the dataflow closure (3) for 4-byte distances
                               with 128- or 256-wide blocks; elsewhere, with 256-wide blocks
                               from a padded order of 10240, phase 1 is a blocked closure of
                               the diagonal block
@@ -182,10 +182,13 @@ typedef struct {
                               3 = the dataflow closure: the diagonal block solved by the
                               blocked schedule over 32-wide sub-blocks, one workgroup per
                               sub-block in one launch (requires block_size 128 or 256;
-                              applies to the exact routes -- int32 arithmetic and float32
-                              arithmetic on integer data -- and is their automatic choice
-                              for 128- and 256-wide blocks, where the two-stream split then
-                              issues the rest of phase 3 as one launch per round) */
+                              applies to the rounds on 4-byte distances, the fp64-key
+                              recurrence keeps the stepwise kernel, and is their automatic
+                              choice for 128- and 256-wide blocks, where the two-stream
+                              split then issues the rest of phase 3 as one launch per
+                              round; with real-valued float32 weights it rounds otherwise
+                              than the stepwise kernel, within float32 rounding, and every
+                              path -- direct, hipGraph, stepper, noalloc -- takes it alike) */
 } apsp_options_t;
 
 /* apsp_solve with options (NULL options = defaults = apsp_solve). */

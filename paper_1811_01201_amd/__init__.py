@@ -188,8 +188,8 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
              for int32; automatic for distance solves up to n = 4096).
     phase1 : 0 automatic, 1 the stepwise diagonal kernel, 2 the blocked
              closure of the diagonal block (block_size=256), 3 the dataflow
-             closure over 32-wide sub-blocks (block_size 128 or 256; exact
-             routes only, the stepwise kernel elsewhere).
+             closure over 32-wide sub-blocks (block_size 128 or 256; 4-byte
+             distance rounds, the stepwise kernel for the fp64-key recurrence).
     Returns the host status of the enqueue (raises APSPError unless check=False).
     """
     assert dist.dim() == 2 and dist.shape[0] == dist.shape[1], "dist must be square"

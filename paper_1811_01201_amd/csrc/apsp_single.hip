@@ -1389,14 +1389,17 @@ struct Sched {
 // in one launch of (BS/32)^2 workgroups (flow_tasks_kernel on the block in
 // place: its order is BS, its row stride ld).  In exact arithmetic (int32,
 // and float32 watched for exactness) its values are those of BS single
-// steps.  An ordinary launch: its tasks are taken in dependency order, so
+// steps (real-valued float32: those of the blocked schedule, rounded
+// otherwise than the stepwise kernel, within float32 rounding; every way of
+// issuing a solve -- direct, hipGraph, stepper, apsp_solve_noalloc -- makes
+// the same choice, so they agree bit for bit).  An ordinary launch: its tasks are taken in dependency order, so
 // it completes however many of its workgroups are resident beside other
 // work (several solves on several streams included).  Per (device, stream)
 // scratch: the two 256 x 256 published matrices and the task words, zeroed
 // once at allocation (each launch leaves its words zeroed again).
 template <class Ar, int BS, class Alt>
 constexpr bool kFlowP1 = (BS == 128 || BS == 256) && std::is_same_v<Alt, NoAlt> &&
-                         (std::is_same_v<Ar, ArI32> || std::is_same_v<Ar, ArF32W>);
+                         (std::is_same_v<Ar, ArI32> || std::is_same_v<Ar, ArF32W> || std::is_same_v<Ar, ArF32>);
 constexpr int kClosureBS = 32, kClosureMax = 256;
 constexpr size_t kClosurePub = (size_t)kClosureMax * kClosureMax * 4;
 constexpr size_t kClosureBytes = 2 * kClosurePub + task_word_bytes(kClosureMax / kClosureBS);
@@ -1434,6 +1437,10 @@ apsp_status_t closure_scratch(int dev, hipStream_t s, bool create, void **out) {
 }
 
 thread_local int32_t *t_status = nullptr;  // the solve's status word (timeouts of the closure)
+// closure scratch of a stepper's recording (its own work memory; the words
+// are zeroed inside the recorded sequence) or of apsp_solve_noalloc (a
+// slice of the static array, zero from load and left zeroed by each launch)
+thread_local void *t_closure = nullptr;
 
 template <class Ar, class Alt, int BS, int TT>
 apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, const int32_t *mode,
@@ -1467,20 +1474,25 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
     // n = 10240 ... 12288, -3 % at 16384, -0.4 % at 32768; +7 % at 9216 and
     // +23 % at 8192)
     constexpr bool kBlockedP1 = BS == 256 && sizeof(typename Ar::T) == 4 && std::is_same_v<Alt, NoAlt>;
-    // The dataflow closure (phase1 3, and the automatic choice on the exact
-    // routes: measured on MI355X, int32 distances, ms per solve against the
+    // The dataflow closure (phase1 3, and the automatic choice for 4-byte
+    // distances: measured on MI355X, int32 distances, ms per solve against the
     // stepwise kernel / the blocked closure: n = 6144 8.68 / 9.39; 8192
     // 15.77 / 17.36; 10240 29.16 / 31.36 / 29.67; 16384 111.2 / 113.8 /
-    // 112.0; 32768 882.0 / - / 886.1), where its scratch exists or may be
-    // created: not for apsp_solve_noalloc or a stepper's recording (whose
-    // operations outlive apsp_release_workspace), nor inside a graph capture
-    // that found none -- the other kernels give the same values there
-    // (exact arithmetic).
+    // 112.0; 32768 882.0 / - / 886.1).  Its scratch: a stepper's or
+    // apsp_solve_noalloc's own (t_closure), else the stream's (made before
+    // any graph capture that may need it).
     void *closure = nullptr;
     if constexpr (kFlowP1<Ar, BS, Alt>) {
-        if (!t_noalloc && !t_rec && (sc.phase1 == 3 || sc.phase1 == 0)) {
-            apsp_status_t st = closure_scratch(dev, s, !t_capturing, &closure);
-            if (st != APSP_SUCCESS) return st;
+        if (sc.phase1 == 3 || sc.phase1 == 0) {
+            if (t_closure) {
+                closure = t_closure;
+                if (t_rec)  // a stepper's recording: zero the words at the start of this pass
+                    enq(flow_init_kernel, dim3(1), dim3(256), s, (uint32_t *)((char *)closure + 2 * kClosurePub),
+                        (int)((kClosureBytes - 2 * kClosurePub) / 4), (int32_t *)nullptr);
+            } else if (!t_noalloc && !t_rec) {
+                apsp_status_t st = closure_scratch(dev, s, !t_capturing, &closure);
+                if (st != APSP_SUCCESS) return st;
+            }
         }
     }
     // (phase1 2 forces it wherever it applies, 1 keeps the stepwise kernel)
@@ -1956,8 +1968,16 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
 
 }  // namespace
 
+// Closure scratch a stepper or a lent work area must carry (the rounds of
+// 128- or 256-wide blocks take the dataflow closure; a predecessor solve's
+// distance rounds take the distance block size).
+size_t closure_bytes(int64_t n, bool with_pred, int opt_bs) {
+    const int bs = opt_bs ? opt_bs : std::max(auto_block(n, with_pred), auto_block(n, false));
+    return bs >= 128 ? kClosureBytes : 0;
+}
+
 size_t solve_work_bytes(int64_t n, apsp_dtype_t dtype, bool with_pred) {
-    return work_bytes(n, with_pred, 0, true, dtype, 0);
+    return work_bytes(n, with_pred, 0, true, dtype, 0) + closure_bytes(n, with_pred, 0);
 }
 
 namespace {
@@ -2033,7 +2053,8 @@ apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dty
         apsp_status_t st = aux_stream(dev, s, &aux);
         if (st != APSP_SUCCESS) return st;
     }
-    if (opt.phase1 != 1 && opt.phase1 != 2 && n > 2048) {  // and the phase-1 closure's scratch
+    if ((opt.phase1 == 0 || opt.phase1 == 3) && closure_bytes(n, with_pred, opt.block_size) > 0) {
+        // and the phase-1 closure's scratch
         void *c = nullptr;
         apsp_status_t st = closure_scratch(dev, s, true, &c);
         if (st != APSP_SUCCESS) return st;
@@ -2102,10 +2123,13 @@ apsp_status_t check_options(int64_t n, apsp_dtype_t dtype, bool with_pred, const
 
 // Static work memory of apsp_solve_noalloc: the largest work matrix any
 // solve of n <= 2048 needs (2048^2 8-byte keys, or two 2048^2 float32
-// matrices, plus the route's status words).  One copy per device, held
-// until the process ends; in host code the name only stands for the
-// symbol, so kernels get the device address found by hipGetSymbolAddress.
-constexpr size_t kScratchBytes = (size_t)2048 * 2048 * 8 + 4096;
+// matrices, plus the route's status words), then the phase-1 closure's
+// scratch (zero from load; each closure launch leaves its words zeroed).
+// One copy per device, held until the process ends; in host code the name
+// only stands for the symbol, so kernels get the device address found by
+// hipGetSymbolAddress.
+constexpr size_t kScratchWork = (size_t)2048 * 2048 * 8 + 4096;
+constexpr size_t kScratchBytes = kScratchWork + kClosureBytes;  // [work][closure scratch]
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 constexpr int kMaxDevices = 64;
@@ -2197,14 +2221,16 @@ apsp_status_t apsp_solve_noalloc(void *dist, int32_t *pred, int64_t n, apsp_dtyp
     if (!dist || ((uintptr_t)dist % 4) != 0 || ((uintptr_t)pred % 4) != 0) return APSP_ERROR_INVALID_ARGUMENT;
     const size_t need =
         work_bytes(n, pred != nullptr, opt.block_size, ((uintptr_t)dist % 16) == 0, dtype, opt.arith);
-    if (need > kScratchBytes) return APSP_ERROR_INVALID_ARGUMENT;  // beyond the static scratch
+    if (need > kScratchWork) return APSP_ERROR_INVALID_ARGUMENT;  // beyond the static scratch
     void *ws = nullptr;
-    if (need > 0) {
+    {
         const apsp_status_t st = scratch_ptr(&ws);
         if (st != APSP_SUCCESS) return st;
     }
     t_noalloc = true;
-    const apsp_status_t st = solve_direct(dist, pred, n, dtype, stream, opt, ws, kScratchBytes);
+    t_closure = (char *)ws + kScratchWork;
+    const apsp_status_t st = solve_direct(dist, pred, n, dtype, stream, opt, need > 0 ? ws : nullptr, kScratchWork);
+    t_closure = nullptr;
     t_noalloc = false;
     return st;
 }
@@ -2269,6 +2295,7 @@ struct apsp_stepper {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     bool owns_ws = true;  // false: work memory lent by the server
+    size_t closure_bytes = 0;  // closure scratch at the end of ws
     AuxStream aux{};
     Recorder rec;
     hipStream_t stream = nullptr;
@@ -2279,13 +2306,15 @@ struct apsp_stepper {
 namespace {
 
 struct RecordScope {
-    RecordScope(Recorder *r, AuxStream *a) {
+    RecordScope(Recorder *r, AuxStream *a, void *closure) {
         t_rec = r;
         t_aux = a;
+        t_closure = closure;
     }
     ~RecordScope() {
         t_rec = nullptr;
         t_aux = nullptr;
+        t_closure = nullptr;
     }
 };
 
@@ -2319,7 +2348,9 @@ apsp_status_t stepper_create(int64_t n, apsp_dtype_t dtype, bool want_pred, cons
     p->opt = opt;
     hipError_t e = hipGetDevice(&p->device);
     // work memory for any alignment of the caller's matrix
-    const size_t need = n ? work_bytes(n, p->want_pred, opt.block_size, lend, dtype, opt.arith) : 0;
+    // [work memory][closure scratch, if its rounds take the closure]
+    p->closure_bytes = n ? closure_bytes(n, p->want_pred, opt.block_size) : 0;
+    const size_t need = n ? work_bytes(n, p->want_pred, opt.block_size, lend, dtype, opt.arith) + p->closure_bytes : 0;
     if (lend) {
         if (ws_bytes < need) {
             delete p;
@@ -2382,8 +2413,11 @@ apsp_status_t apsp_stepper_begin(apsp_stepper_t *p, void *dist, int32_t *pred, h
         int dev = 0;
         APSP_HIP(hipGetDevice(&dev));
         if (dev != p->device) return APSP_ERROR_INVALID_ARGUMENT;
-        RecordScope rs(&p->rec, &p->aux);
-        apsp_status_t st = solve_direct(dist, pred, p->n, p->dtype, stream, p->opt, p->ws, p->ws_bytes);
+        // [work memory][closure scratch]
+        RecordScope rs(&p->rec, &p->aux,
+                       p->closure_bytes ? (char *)p->ws + (p->ws_bytes - p->closure_bytes) : nullptr);
+        apsp_status_t st =
+            solve_direct(dist, pred, p->n, p->dtype, stream, p->opt, p->ws, p->ws_bytes - p->closure_bytes);
         if (st != APSP_SUCCESS) {
             p->rec.ops.clear();
             p->rec.marks.clear();

@@ -260,17 +260,51 @@ def test_dataflow_closure_watch_fallback_and_cycles(orc):
         assert st == 3, arith
 
 
-def test_dataflow_closure_not_for_inexact_float32(orc):
-    """Real-valued float32 weights are not an exact route: phase1=3 keeps the
-    stepwise closure there (so every schedule rounds alike)."""
-    describe("phase-1 closure: real float32 keeps the stepwise kernel")
+def test_dataflow_closure_real_float32_every_path_agrees(orc):
+    """Real-valued float32 weights: the closure rounds otherwise than the
+    stepwise kernel (within float32 rounding of the oracle), and every way of
+    issuing the solve -- direct, a hipGraph replay, a stepper in slices, the
+    no-allocation entry point -- makes the same choice, bit for bit."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe("phase-1 closure: real float32, every path")
     n = 700
     W = synth.single_f32real(n, p=0.05, lo=0.5, hi=100.0, seed=23)
-    D, _, st, _, prof = _solve_profiled(W, False, block_size=256, phase1=3)
+    D, _, st, _, prof = _solve_profiled(W, False, block_size=256)
     assert st == 0
-    assert prof["phase1_flow"]["launches"] == 0
-    D1, _, _, _, _ = _solve_profiled(W, False, block_size=256, phase1=1)
-    assert np.array_equal(D.view(np.uint32), D1.view(np.uint32))
+    assert prof["phase1_flow"]["launches"] == (n + 255) // 256
+    D0, _, _ = orc.fw(W)
+    fin = np.isfinite(D0)
+    assert np.array_equal(np.isfinite(D), fin)
+    rel = np.abs(D[fin].astype(np.float64) - D0[fin]) / np.maximum(1.0, np.abs(D0[fin]))
+    assert rel.max() <= 1e-6, rel.max()
+    s = torch.cuda.Stream()
+    w = torch.from_numpy(W).cuda()
+    # hipGraph (captured, then replayed)
+    d = torch.empty_like(w)
+    for _ in range(2):
+        d.copy_(w)
+        torch.cuda.synchronize()
+        apsp.solve(d, stream=s, use_graph=True, block_size=256)
+        s.synchronize()
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), D.view(np.uint32))
+    # stepper, two rounds per slice
+    st_ = apsp.Stepper(n, "float32", block_size=256)
+    d = w.clone()
+    torch.cuda.synchronize()
+    st_.begin(d, stream=s)
+    while not st_.step(2):
+        pass
+    s.synchronize()
+    st_.destroy()
+    assert np.array_equal(d.cpu().numpy().view(np.uint32), D.view(np.uint32))
+    # no allocation
+    d = w.clone()
+    torch.cuda.synchronize()
+    apsp.solve_noalloc(d, stream=s, block_size=256)
+    s.synchronize()
+    assert np.array_equal(d.cpu().numpy().view(np.uint32), D.view(np.uint32))
 
 
 def test_dataflow_closure_in_a_graph_replayed(orc):
