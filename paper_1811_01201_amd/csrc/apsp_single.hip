@@ -1606,16 +1606,27 @@ apsp_status_t run_rounds_bs(int bs, int tt, Sched sc, void *X, int64_t ld, const
     }
 }
 
-// Block size by n (measured on MI355X, int32 distances in float32
-// arithmetic, ms per solve for BS = 64 / 128 / 256): 5120: 6.52 / 7.78 /
-// 8.61; 5632: 8.14 / 8.74 / 9.57; 6144: 9.87 / 9.67 / 10.85; 6656: 11.93 /
-// 11.67 / 11.87; 7168: 14.24 / 13.90 / 13.59; 8192: 19.79 / 19.58 / 17.77.
-// Small blocks keep the phase-1 chain short while phase 3 is short too.
-// The fp64-key recurrence (the product route's fallback there) keeps
-// BS = 128 above n = 4096.
+// Block size by n for distance rounds (measured on MI355X, int32
+// distances in float32 arithmetic with the phase-1 closure, ms per solve
+// for BS = 64 / 128 / 256): 4608: 5.09 / 5.95 / 5.40; 5120: 6.41 / 6.94 /
+// 6.25; 5632: 7.90 / 7.95 / 7.40; 6144: 9.65 / 8.75 / 8.38; 6656: 11.62 /
+// 9.72 / 9.24; 8192: 19.88 / 16.92 / 15.66; 12288: 66.1 / 52.3 / 48.4.
+// With the closure, phase 1 of a 256-wide block no longer sets the pace,
+// and the larger blocks' fewer rounds win from n of about 5000.  The
+// fp64-key recurrence (the product route's fallback there) keeps BS = 128
+// above n = 4096.
 int auto_block(int64_t n, bool pred) {
     if (n <= 4096) return 64;
     if (pred) return 128;
+    if (n <= 4864) return 64;
+    return 256;
+}
+
+// The float32 predecessor route's distance rounds (measured with the
+// closure, ms per solve at BS = 64 / 128 / 256, the key product included):
+// 5120: 10.42 / 11.11 / 10.45; 6144: 15.65 / 14.94 / 14.77; 7168: 23.70 /
+// 21.77 / 21.10; 8192: 33.08 / 30.55 / 29.48.
+int auto_block_pp(int64_t n) {
     if (n <= 5888) return 64;
     if (n < 7168) return 128;
     return 256;
@@ -1660,7 +1671,7 @@ struct PPShape {
 };
 PPShape pp_shape(int64_t n, int opt_bs) {
     PPShape p;
-    p.bsd = opt_bs ? opt_bs : auto_block(n, false);
+    p.bsd = opt_bs ? opt_bs : auto_block_pp(n);
     p.bsf = opt_bs ? std::min(opt_bs, 128) : auto_block(n, true);
     const int64_t m = std::max(p.bsd, 128);
     p.ld = (n + m - 1) / m * m;
