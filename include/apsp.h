@@ -144,7 +144,8 @@ typedef struct {
     int32_t use_graph;     /* nonzero: capture the launch sequence once per shape into a
                               hipGraph and replay it (fewer launch gaps for small n) */
     int32_t arith;         /* Distances only, int32 weights (ignored for float32 weights):
-                              0 = automatic (float32 arithmetic from n = 4096), 1 = int32
+                              0 = automatic (float32 arithmetic above n = 4096, and at
+                              4096 where the single launch does not apply), 1 = int32
                               arithmetic, 2 = float32 arithmetic at any n.  float32
                               arithmetic holds the integers exactly while every operand
                               stays below 2^23 in magnitude, which the kernels check; if one

@@ -1769,8 +1769,7 @@ size_t single_work_bytes(int64_t n, apsp_dtype_t dtype, bool with_pred, bool ali
     const int bs = opt.block_size ? opt.block_size : auto_block(n, with_pred);
     const int tt = opt.thread_tile ? opt.thread_tile : auto_tile(n, bs);
     const int64_t ld = (n + bs - 1) / bs * bs;
-    const bool f32w = dtype == APSP_INT32 && use_f32w(n, APSP_INT32, with_pred, opt.arith);
-    if (!single_applies(ld, bs, tt, with_pred, f32w, opt.schedule, false)) return 0;
+    if (!single_applies(ld, bs, tt, with_pred, dtype == APSP_INT32 && opt.arith == 2, opt.schedule, false)) return 0;
     const SinglePlan p = dtype == APSP_INT32 ? single_plan<ArI32>(256, ld) : single_plan<ArF32>(256, ld);
     const size_t mat = (ld == n && aligned) ? 0 : (size_t)(ld * ld) * 4;
     return mat + p.pub_bytes + p.word_bytes;
@@ -1802,9 +1801,13 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
     int32_t *status = opt.d_status;
     t_status = status;
     const int32_t *skip = nullptr;
-    const bool f32w = std::is_same_v<T, int32_t> && use_f32w(n, APSP_INT32, with_pred, opt.arith);
+    // the single launch (int32 in int32 arithmetic) where it applies, before
+    // the automatic float32 route for int32 (at n = 4096 both apply: 3.5
+    // against 4.2 ms)
     using ArPlain = std::conditional_t<std::is_same_v<T, int32_t>, ArI32, ArF32>;
-    const bool single = single_applies(ld, bs, tt, with_pred, f32w, opt.schedule, ext_ws != nullptr);
+    const bool single = single_applies(ld, bs, tt, with_pred, std::is_same_v<T, int32_t> && opt.arith == 2,
+                                       opt.schedule, ext_ws != nullptr);
+    const bool f32w = !single && std::is_same_v<T, int32_t> && use_f32w(n, APSP_INT32, with_pred, opt.arith);
     SinglePlan plan;
     if (single) {
         int cus = 0;
