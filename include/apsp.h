@@ -250,6 +250,8 @@ apsp_status_t apsp_stepper_begin(apsp_stepper_t *stepper, void *dist, int32_t *p
 apsp_status_t apsp_stepper_step(apsp_stepper_t *stepper, int32_t rounds, int32_t *done);
 /* Rounds in the recorded solve (-1 for NULL; 0 before begin). */
 int64_t apsp_stepper_rounds(const apsp_stepper_t *stepper);
+/* Waits for the stepper's streams, then frees it (always, also on an error:
+ * APSP_ERROR_HIP if a wait or the release of its memory failed). */
 apsp_status_t apsp_stepper_destroy(apsp_stepper_t *stepper);
 
 /* ---------------------------------------------------------------- profiling

@@ -764,7 +764,7 @@ apsp_status_t retire(apsp_batch_plan_t *p, hipStream_t s) {
     hipEvent_t ev;
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
         hipEventRecord(ev, s) != hipSuccess) {
-        hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);  // (the plan is freed once its work is done either way)
         plan_free(p);
         return APSP_SUCCESS;
     }
@@ -984,9 +984,9 @@ void batch_meta(const int32_t *ns, const int64_t *offsets, int32_t B, apsp_dtype
 void sweep_retired(bool wait) {
     std::lock_guard<std::mutex> lk(g_retired_mu);
     for (auto it = g_retired.begin(); it != g_retired.end();) {
-        if (wait) hipEventSynchronize(it->second);
+        if (wait) (void)hipEventSynchronize(it->second);
         if (hipEventQuery(it->second) == hipSuccess) {
-            hipEventDestroy(it->second);
+            (void)hipEventDestroy(it->second);
             plan_free(it->first);
             it = g_retired.erase(it);
         } else {
@@ -1020,7 +1020,7 @@ apsp_status_t apsp_batch_plan_create_ex(const int32_t *ns, const int64_t *offset
         return APSP_ERROR_HIP;
     }
     int cus = 256;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) cus = 256;
     std::vector<char> host;
     batch_meta(ns, offsets, batch, dtype, p->want_pred, team_config, host, p->n_team, p->scratch_elems, p->lean);
     p->grid = std::max(1, batched_blocks_per_cu(dtype, p->lean) * cus);
@@ -1111,18 +1111,20 @@ apsp_status_t autotune_on(const std::vector<int32_t> &sizes, apsp_dtype_t dtype,
     }
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return APSP_ERROR_HIP;
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     void *dist = nullptr, *pred = nullptr, *meta = nullptr;
     apsp_status_t result = APSP_SUCCESS;
-    if (hipMalloc(&dist, (size_t)total * 4) != hipSuccess ||
-        (want_pred && hipMalloc(&pred, (size_t)total * 4) != hipSuccess) ||
-        hipMalloc(&meta, (size_t)B * 12) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) result = APSP_ERROR_HIP;
+    if (result == APSP_SUCCESS &&
+        (hipMalloc(&dist, (size_t)total * 4) != hipSuccess ||
+         (want_pred && hipMalloc(&pred, (size_t)total * 4) != hipSuccess) ||
+         hipMalloc(&meta, (size_t)B * 12) != hipSuccess))
         result = APSP_ERROR_OUT_OF_MEMORY;
+    if (result == APSP_SUCCESS &&
+        (hipMemcpy(meta, offs.data(), (size_t)B * 8, hipMemcpyHostToDevice) != hipSuccess ||
+         hipMemcpy((char *)meta + (size_t)B * 8, ns.data(), (size_t)B * 4, hipMemcpyHostToDevice) != hipSuccess))
+        result = APSP_ERROR_HIP;
     if (result == APSP_SUCCESS) {
-        hipMemcpy(meta, offs.data(), (size_t)B * 8, hipMemcpyHostToDevice);
-        hipMemcpy((char *)meta + (size_t)B * 8, ns.data(), (size_t)B * 4, hipMemcpyHostToDevice);
         const int32_t *dns = (const int32_t *)((char *)meta + (size_t)B * 8);
         if (dtype == APSP_INT32)
             hipLaunchKernelGGL(tune_fill_kernel<int32_t>, dim3(std::min(B, 4096)), dim3(256), 0, s,
@@ -1144,12 +1146,13 @@ apsp_status_t autotune_on(const std::vector<int32_t> &sizes, apsp_dtype_t dtype,
             apsp_batch_plan_create_ex(ns.data(), offs.data(), B, dtype, want_pred, forced.data(), &plan);
         if (st != APSP_SUCCESS) return st;
         st = apsp_batch_plan_execute(plan, dist, (int32_t *)pred, nullptr, s);  // warm-up
-        hipEventRecord(e0, s);
+        if (st == APSP_SUCCESS && hipEventRecord(e0, s) != hipSuccess) st = APSP_ERROR_HIP;
         for (int r = 0; r < R && st == APSP_SUCCESS; ++r)
             st = apsp_batch_plan_execute(plan, dist, (int32_t *)pred, nullptr, s);
-        hipEventRecord(e1, s);
         float ms = 0.f;
-        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        if (st == APSP_SUCCESS &&
+            (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
             st = APSP_ERROR_HIP;
         plan_free(plan);
         ms_per = (double)ms / R;
@@ -1180,12 +1183,13 @@ apsp_status_t autotune_on(const std::vector<int32_t> &sizes, apsp_dtype_t dtype,
         std::lock_guard<std::mutex> lk(g_tune_mu);
         std::memcpy(g_tune[d][m], choice, sizeof choice);
     }
-    hipFree(dist);
-    hipFree(pred);
-    hipFree(meta);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipStreamDestroy(s);
+    if (hipStreamSynchronize(s) != hipSuccess && result == APSP_SUCCESS) result = APSP_ERROR_HIP;
+    (void)hipFree(dist);
+    (void)hipFree(pred);
+    (void)hipFree(meta);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
     return result;
 }
 
@@ -1199,7 +1203,7 @@ apsp_status_t apsp_batch_autotune(apsp_dtype_t dtype, int32_t want_pred, int32_t
     if (graphs_per_class < 0 || reps < 0) return APSP_ERROR_INVALID_ARGUMENT;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess) return APSP_ERROR_HIP;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
     const int32_t per = graphs_per_class ? graphs_per_class : cus;
     // `per` graphs spread evenly over every size class
     std::vector<int32_t> sizes;

@@ -389,20 +389,18 @@ __global__ void flow_init_kernel(uint32_t *words, int count, int32_t *status) {
 
 // Dataflow solve as a ticketed task graph: the tasks of the blocked
 // schedule over BS-wide blocks are numbered in an order where every task's
-// operands come from tasks with smaller numbers --
+// operands come from tasks with smaller numbers (task_decode) --
 //   0                         phase 1 of round 0 on block (0, 0)
-//   then per round r < R-1:   2m panel products (block row r, then block
-//                             column r; m = R - 1), block (r+1, r+1)
-//                             (phase 3, then at once its phase 1 of round
-//                             r+1), the other blocks of block row and
-//                             column r+1 (the next round's panels), then
-//                             the remaining (m-1)^2 blocks in chunks of K
-//   last round:               2m panel products, m^2 blocks in chunks of K
+//   then per round r:         2m panel products (block row r, then block
+//                             column r; m = R - 1), then the m^2 remaining
+//                             blocks: block (r+1, r+1) first (phase 3, then
+//                             at once its phase 1 of round r+1), then the
+//                             other blocks of block row and column r+1 (the
+//                             next round's panels), then the rest
 // -- and a workgroup takes the next number from a counter, waits for the
-// operands it reads and does the task (or chunk), over and over.  The
-// next round's chain (its panels, its diagonal block) comes first in each
-// round; chunks keep the counter's traffic low.  A task only waits
-// for smaller numbers, which running workgroups hold, so the launch makes
+// operands it reads and does the task, over and over.  The next round's
+// chain (its panels, its diagonal block) comes first in each round.  A
+// task only waits for smaller numbers, which running workgroups hold, so the launch makes
 // progress however few of its workgroups are resident and whatever else
 // runs on the device.  Block states live in X (device-coherent loads and
 // stores); panels and closed diagonal blocks are also published once each
@@ -418,15 +416,58 @@ __host__ __device__ constexpr int task_next_word(int R) { return R * R + 512; }
 __host__ __device__ constexpr int task_done_word(int R) { return R * R + 768; }
 __host__ __device__ constexpr int task_words(int R) { return R * R + 1024; }
 __host__ __device__ constexpr size_t task_word_bytes(int R) { return (size_t)task_words(R) * 4; }
-// numbers per round r < R - 1, and in the last round (chunks of K)
-__host__ __device__ constexpr int64_t task_round(int R, int K) {
-    return 2 * (R - 1) + 1 + 2 * (R - 2) + ((int64_t)(R - 2) * (R - 2) + K - 1) / K;
-}
-__host__ __device__ constexpr int64_t task_last(int R, int K) {
-    return 2 * (R - 1) + ((int64_t)(R - 1) * (R - 1) + K - 1) / K;
-}
-__host__ __device__ constexpr int64_t task_count(int R, int K) {
-    return R == 1 ? 1 : 1 + (int64_t)(R - 1) * task_round(R, K) + task_last(R, K);
+// numbers per round: m (m + 2), m = R - 1 (every round: 2m panels, m^2
+// remaining blocks); in all 1 + R m (m + 2)
+__host__ __device__ constexpr int64_t task_round(int R) { return (int64_t)(R - 1) * (R + 1); }
+__host__ __device__ constexpr int64_t task_count(int R) { return 1 + (int64_t)R * task_round(R); }
+
+// The task with number t: kind 0 the closure of block (0, 0); 1 the
+// block-row panel (r, j); 2 the block-column panel (i, r); 3 the product of
+// remaining block (i, j) in round r (block (r+1, r+1) closes itself after).
+// Within round r < R - 1 the remaining blocks come as (r+1, r+1), then the
+// rest of block row and column r+1, then all others (row-major); in the
+// last round row-major.
+struct FlowTask {
+    int kind, r, i, j;
+};
+__device__ __forceinline__ FlowTask task_decode(uint32_t t, int R) {
+    FlowTask k{0, 0, 0, 0};
+    if (t == 0) return k;
+    const int m = R - 1;
+    const uint32_t t1 = t - 1, per = (uint32_t)task_round(R);
+    k.r = (int)(t1 / per);
+    int u = (int)(t1 - (uint32_t)k.r * per);
+    const int r = k.r;
+    if (u < 2 * m) {
+        const bool row = u < m;
+        int q = row ? u : u - m;
+        q += q >= r;
+        k.kind = row ? 1 : 2;
+        k.i = row ? r : q;
+        k.j = row ? q : r;
+        return k;
+    }
+    u -= 2 * m;
+    k.kind = 3;
+    if (r + 1 < R) {
+        const int w = m - 1;  // indices outside {r, r+1}: q -> q + (q >= r ? 2 : 0)
+        if (u == 0) {
+            k.i = k.j = r + 1;
+        } else if (u - 1 < 2 * w) {
+            const int q = (u - 1) % w, x = q + (q >= r ? 2 : 0);
+            k.i = u - 1 < w ? r + 1 : x;
+            k.j = u - 1 < w ? x : r + 1;
+        } else {
+            const int a = u - 1 - 2 * w, qi = a / w, qj = a - (a / w) * w;
+            k.i = qi + (qi >= r ? 2 : 0);
+            k.j = qj + (qj >= r ? 2 : 0);
+        }
+    } else {
+        const int qi = u / m, qj = u - (u / m) * m;
+        k.i = qi + (qi >= r);
+        k.j = qj + (qj >= r);
+    }
+    return k;
 }
 
 // Waits (thread 0 polling) until *w0 >= v0 and, if w1, *w1 >= v1; the
@@ -467,7 +508,7 @@ __device__ __forceinline__ void ld_tt_dev(const T *p, T *out) {
 template <class Ar, int BS>
 __global__ void __launch_bounds__(kSingleThreads) __attribute__((amdgpu_waves_per_eu(4)))
 flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *words, void *prow_v, void *pcol_v,
-                  int32_t *status, const int32_t *__restrict__ skip, int K) {
+                  int32_t *status, const int32_t *__restrict__ skip) {
     using T = typename Ar::T;
     static_assert(sizeof(T) == 4, "4-byte elements");
     constexpr int TT = flow_tile<BS>();
@@ -484,11 +525,11 @@ flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *word
     T *const Prow = (T *)prow_v;
     T *const Pcol = (T *)pcol_v;
     const uint32_t ordu = (uint32_t)order, stru = (uint32_t)stride;
-    const int R = (int)(order / BS), m = R - 1;
+    const int R = (int)(order / BS);
     const int tid = (int)threadIdx.x, tx = tid % PS::TX, ty = tid / PS::TX;
     uint32_t *const ver = words;
     uint32_t *const fail = words + task_fail_word(R);
-    const uint32_t total = (uint32_t)task_count(R, K), per_round = R > 1 ? (uint32_t)task_round(R, K) : 1u;
+    const uint32_t total = (uint32_t)task_count(R);
     auto blk = [&](T *M, uint32_t ld, int p, int q) __attribute__((always_inline)) {
         return M + ((uint32_t)p * BS * ld + (uint32_t)q * BS);
     };
@@ -556,26 +597,21 @@ flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *word
         const uint32_t t = ticket_lds;
         if (t >= total) break;
         if (!ok) continue;  // after a failed wait: drain the counter, do nothing
-        if (t == 0) {
+        const FlowTask k = task_decode(t, R);
+        const int r = k.r, i = k.i, j = k.j;
+        if (k.kind == 0) {
             load(0, 0);
             close();
             finish(0, 0, Prow, 1u);
             continue;
         }
-        const uint32_t t1 = t - 1;
-        const bool ahead = t1 < (uint32_t)(R - 1) * per_round;
-        const int r = ahead ? (int)(t1 / per_round) : R - 1;
-        int u = ahead ? (int)(t1 % per_round) : (int)(t1 - (uint32_t)(R - 1) * per_round);
-        if (u < 2 * m) {
-            const bool row = u < m;
-            int q = row ? u : u - m;
-            q += q >= r;
-            const int i = row ? r : q, j = row ? q : r;
-            // its own round r - 1 (loaded while the closed block r is awaited)
-            if (!(ok = task_wait(&ver[i * R + j], (uint32_t)r, nullptr, 0u, fail, &ok_lds))) continue;
-            load(i, j);
+        // its own round r - 1 (loaded while the operands are awaited)
+        if (!(ok = task_wait(&ver[i * R + j], (uint32_t)r, nullptr, 0u, fail, &ok_lds))) continue;
+        load(i, j);
+        if (k.kind != 3) {
+            // a panel: the closed block r
             if (!(ok = task_wait(&ver[r * R + r], (uint32_t)r + 1, nullptr, 0u, fail, &ok_lds))) continue;
-            if (row) {  // c <- min(c, D(r,r)* (x) c)
+            if (k.kind == 1) {  // c <- min(c, D(r,r)* (x) c)
                 flow_copy<BS, kSingleThreads, true>(la, blk(Prow, ordu, r, r), ordu);
 #pragma unroll
                 for (int q2 = 0; q2 < TT; ++q2) st_tt<TT>(&lb[(ty * TT + q2) * BS + tx * TT], c[q2]);
@@ -588,49 +624,20 @@ flow_tasks_kernel(void *Xv, int64_t order, int64_t stride, Ar ar, uint32_t *word
                 }
             }
             multiply();
-            finish(i, j, row ? Prow : Pcol, (uint32_t)r + 1);
+            finish(i, j, k.kind == 1 ? Prow : Pcol, (uint32_t)r + 1);
             continue;
         }
-        u -= 2 * m;
-        // one phase-3 block (i, j) of round r: c <- min(c, P_col(i, r) (x) P_row(r, j))
-        auto p3 = [&](int i, int j) __attribute__((always_inline)) {
-            if (!(ok = task_wait(&ver[i * R + j], (uint32_t)r, nullptr, 0u, fail, &ok_lds))) return;
-            load(i, j);  // (in flight while the panels are awaited)
-            if (!(ok = task_wait(&ver[i * R + r], (uint32_t)r + 1, &ver[r * R + j], (uint32_t)r + 1, fail, &ok_lds)))
-                return;
-            flow_copy<BS, kSingleThreads, true>(la, blk(Pcol, ordu, i, r), ordu);
-            flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, j), ordu);
-            multiply();
-            if (i == r + 1 && j == r + 1) {
-                close();
-                finish(i, j, Prow, (uint32_t)r + 2);
-            } else {
-                finish(i, j, nullptr, (uint32_t)r + 1);
-            }
-        };
-        if (ahead) {
-            const int w = m - 1;  // indices outside {r, r+1}: q -> q + (q >= r ? 2 : 0)
-            if (u == 0) {
-                p3(r + 1, r + 1);
-            } else if (u - 1 < 2 * w) {
-                const int q = (u - 1) % w, x = q + (q >= r ? 2 : 0);
-                if (u - 1 < w)
-                    p3(r + 1, x);
-                else
-                    p3(x, r + 1);
-            } else {
-                const int c0 = (u - 1 - 2 * w) * K, c1 = min(c0 + K, w * w);
-                for (int a = c0; a < c1 && ok; ++a) {
-                    const int qi = a / w, qj = a - (a / w) * w;
-                    p3(qi + (qi >= r ? 2 : 0), qj + (qj >= r ? 2 : 0));
-                }
-            }
+        // a remaining block: c <- min(c, P_col(i, r) (x) P_row(r, j))
+        if (!(ok = task_wait(&ver[i * R + r], (uint32_t)r + 1, &ver[r * R + j], (uint32_t)r + 1, fail, &ok_lds)))
+            continue;
+        flow_copy<BS, kSingleThreads, true>(la, blk(Pcol, ordu, i, r), ordu);
+        flow_copy<BS, kSingleThreads, false>(lb, blk(Prow, ordu, r, j), ordu);
+        multiply();
+        if (i == r + 1 && j == r + 1) {
+            close();
+            finish(i, j, Prow, (uint32_t)r + 2);
         } else {
-            const int c0 = u * K, c1 = min(c0 + K, m * m);
-            for (int a = c0; a < c1 && ok; ++a) {
-                const int qi = a / m, qj = a - (a / m) * m;
-                p3(qi + (qi >= r), qj + (qj >= r));
-            }
+            finish(i, j, nullptr, (uint32_t)r + 1);
         }
     }
     if constexpr (Ar::kWatch) {
@@ -1279,11 +1286,11 @@ struct ProfScope {
             on = false;
             return;
         }
-        hipEventRecord(rec.start, s);
+        (void)hipEventRecord(rec.start, s);
     }
     ~ProfScope() {
         if (!on) return;
-        hipEventRecord(rec.stop, s);
+        (void)hipEventRecord(rec.stop, s);
         std::lock_guard<std::mutex> lk(g_prof_mu);
         g_prof.push_back(rec);
     }
@@ -1505,7 +1512,7 @@ apsp_status_t run_rounds(void *X, int64_t ld, const Ar &ar, const Alt &alt, cons
                 char *const c = (char *)closure;
                 enq((flow_tasks_kernel<Ar, kClosureBS>), dim3(RC * RC), dim3(kSingleThreads), s,
                     (void *)((typename Ar::T *)X + (int64_t)r * BS * ld + (int64_t)r * BS), (int64_t)BS, ld, ar,
-                    (uint32_t *)(c + 2 * kClosurePub), (void *)c, (void *)(c + kClosurePub), t_status, skip, 1);
+                    (uint32_t *)(c + 2 * kClosurePub), (void *)c, (void *)(c + kClosurePub), t_status, skip);
                 return;
             }
         }
@@ -1716,7 +1723,6 @@ inline bool single_applies(int64_t ld, int bs, int tt, bool with_pred, bool f32w
 // The single launch's shape for padded order ld.
 struct SinglePlan {
     int bs = 0;             // 32 or 64
-    int chunk = 1;          // remaining phase-3 blocks per task number
     int groups = 0;         // workgroups taking tasks
     size_t word_bytes = 0;  // task words
     size_t pub_bytes = 0;   // the two publication matrices
@@ -1724,20 +1730,10 @@ struct SinglePlan {
 #ifndef APSP_TASK32_MAX_LD
 #define APSP_TASK32_MAX_LD 768
 #endif
-// (chunks of more than one remaining block were slower at every size
-// measured: n = 256 0.100 ms with chunks of 4 against 0.082 with single
-// blocks; n = 1024 0.407 with chunks of 2 against 0.397)
-#ifndef APSP_TASK32_CHUNK
-#define APSP_TASK32_CHUNK 1
-#endif
-#ifndef APSP_TASK64_CHUNK
-#define APSP_TASK64_CHUNK 1
-#endif
 template <class Ar>
 SinglePlan single_plan(int cus, int64_t ld) {
     SinglePlan p;
     p.bs = std::is_same_v<Ar, ArI32> && ld <= APSP_TASK32_MAX_LD ? 32 : 64;
-    p.chunk = p.bs == 32 ? APSP_TASK32_CHUNK : APSP_TASK64_CHUNK;
     const int64_t R = ld / p.bs, m = R - 1;
     // workgroups: one per task of a round's phase 3, at most 4 per CU
     p.groups = (int)std::max<int64_t>(1, std::min<int64_t>(m * m, 4 * (int64_t)cus));
@@ -1755,12 +1751,12 @@ void run_single(void *X, int64_t ld, const Ar &ar, const SinglePlan &plan, void 
     if constexpr (std::is_same_v<Ar, ArI32>) {
         if (plan.bs == 32) {
             enq((flow_tasks_kernel<Ar, 32>), dim3(plan.groups), dim3(kSingleThreads), s, X, ld, ld, ar, words, prow,
-                pcol, status, skip, plan.chunk);
+                pcol, status, skip);
             return;
         }
     }
     enq((flow_tasks_kernel<Ar, 64>), dim3(plan.groups), dim3(kSingleThreads), s, X, ld, ld, ar, words, prow, pcol,
-        status, skip, plan.chunk);
+        status, skip);
 }
 
 // Work memory of a single-launch solve (0 if the options do not take one):
@@ -2030,7 +2026,7 @@ constexpr size_t kMaxGraphs = 64;
 void drop_graphs_locked(int dev) {
     for (auto it = g_graphs.begin(); it != g_graphs.end();) {
         if (dev < 0 || it->first.dev == dev) {
-            hipGraphExecDestroy(it->second);
+            (void)hipGraphExecDestroy(it->second);
             it = g_graphs.erase(it);
         } else {
             ++it;
@@ -2086,7 +2082,7 @@ apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dty
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(s, &graph);
         if (st != APSP_SUCCESS) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return st;
         }
         if (e != hipSuccess) {
@@ -2095,7 +2091,7 @@ apsp_status_t solve_graph(void *dist, int32_t *pred, int64_t n, apsp_dtype_t dty
         }
         hipGraphExec_t exec = nullptr;
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) {
             g_last_hip = (int)e;
             return APSP_ERROR_HIP;
@@ -2252,8 +2248,8 @@ apsp_status_t apsp_solve_noalloc(void *dist, int32_t *pred, int64_t n, apsp_dtyp
 apsp_status_t apsp_profile_begin(void) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto &r : g_prof) {
-        hipEventDestroy(r.start);
-        hipEventDestroy(r.stop);
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
     }
     g_prof.clear();
     g_prof_on = true;
@@ -2289,8 +2285,8 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out) {
             k->max_ms = std::max(k->max_ms, (double)ms);
             k->updates += r.updates;
         }
-        hipEventDestroy(r.start);
-        hipEventDestroy(r.stop);
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
     }
     return st;
 }
@@ -2394,14 +2390,15 @@ apsp_status_t stepper_create(int64_t n, apsp_dtype_t dtype, bool want_pred, cons
 // other work of a shared stream).
 apsp_status_t stepper_destroy(apsp_stepper_t *p, bool sync) {
     if (!p) return APSP_ERROR_INVALID_ARGUMENT;
-    if (sync && p->begun) hipStreamSynchronize(p->stream);
-    if (sync && p->aux.s) hipStreamSynchronize(p->aux.s);
-    if (p->ws && p->owns_ws) hipFree(p->ws);
-    if (p->aux.panels) hipEventDestroy(p->aux.panels);
-    if (p->aux.rest) hipEventDestroy(p->aux.rest);
-    if (p->aux.s) hipStreamDestroy(p->aux.s);
+    bool ok = true;
+    if (sync && p->begun) ok &= hipStreamSynchronize(p->stream) == hipSuccess;
+    if (sync && p->aux.s) ok &= hipStreamSynchronize(p->aux.s) == hipSuccess;
+    if (p->ws && p->owns_ws) ok &= hipFree(p->ws) == hipSuccess;
+    if (p->aux.panels) (void)hipEventDestroy(p->aux.panels);
+    if (p->aux.rest) (void)hipEventDestroy(p->aux.rest);
+    if (p->aux.s) (void)hipStreamDestroy(p->aux.s);
     delete p;
-    return APSP_SUCCESS;
+    return ok ? APSP_SUCCESS : APSP_ERROR_HIP;
 }
 
 }  // namespace apsp

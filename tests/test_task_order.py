@@ -1,5 +1,5 @@
 """The task numbering of the dataflow solves (flow_tasks_kernel), restated
-here: for every block count R and chunk size K, each task of the blocked
+here: for every block count R, each task of the blocked
 schedule (Section "Data Locality": per round, the diagonal block, its block
 row and column, then the remaining blocks) appears exactly once, and every
 task's operands -- its own block's previous round, the closed diagonal
@@ -8,20 +8,19 @@ That order is what lets a launch complete however few of its workgroups
 are resident: a workgroup only ever waits for numbers that running
 workgroups hold.  (A model of the numbering, checked on the CPU; the GPU
 parity tests run the kernel itself.)"""
-import math
-
 import pytest
 
 
-def decode(R, K):
+def decode(R):
     """[(number, task)] with task ('P1',) for round 0's closure of block
     (0, 0), else (r, i, j): round r's product on block (i, j) (block (r+1,
     r+1) includes its closure for round r+1)."""
     m = R - 1
     if R == 1:
         return [(0, ("P1",))]
-    per_round = 2 * (R - 1) + 1 + 2 * (R - 2) + math.ceil((R - 2) ** 2 / K)
-    last = 2 * (R - 1) + math.ceil((R - 1) ** 2 / K)
+    per_round = 2 * (R - 1) + 1 + 2 * (R - 2) + (R - 2) ** 2
+    last = 2 * (R - 1) + (R - 1) ** 2
+    assert per_round == last == (R - 1) * (R + 1)  # the kernel's count per round
     total = 1 + (R - 1) * per_round + last
     out = [(0, ("P1",))]
     for t in range(1, total):
@@ -45,26 +44,23 @@ def decode(R, K):
                 x = skip2((u - 1) % w)
                 out.append((t, (r, r + 1, x) if u - 1 < w else (r, x, r + 1)))
             else:
-                c0 = (u - 1 - 2 * w) * K
-                for a in range(c0, min(c0 + K, w * w)):
-                    out.append((t, (r, skip2(a // w), skip2(a % w))))
+                a = u - 1 - 2 * w
+                out.append((t, (r, skip2(a // w), skip2(a % w))))
         else:
-            c0 = u * K
-            for a in range(c0, min(c0 + K, m * m)):
-                out.append((t, (r, a // m + (a // m >= r), a % m + (a % m >= r))))
+            out.append((t, (r, u // m + (u // m >= r), u % m + (u % m >= r))))
     return out
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8])
-def test_task_numbering_complete_and_ordered(K):
-    for R in list(range(1, 34)) + [48, 64]:
+def test_task_numbering_complete_and_ordered():
+    for R in list(range(1, 34)) + [48, 64, 96]:
         seen = {}
-        for t, task in decode(R, K):
-            assert task not in seen, (R, K, task)
+        for t, task in decode(R):
+            assert t == len(seen), (R, t)  # numbers 0, 1, 2, ... one task each
+            assert task not in seen, (R, task)
             seen[task] = t
         expect = {("P1",)} | {(r, i, j) for r in range(R) for i in range(R) for j in range(R)
                                if not (i == r and j == r)}
-        assert set(seen) == expect, (R, K)
+        assert set(seen) == expect, R
 
         def number(r, i, j):
             if i == r and j == r:  # closed block r: round r-1's block (r, r), or the first task
@@ -80,4 +76,4 @@ def test_task_numbering_complete_and_ordered(K):
                 deps.append(number(r, r, r))
             else:
                 deps += [number(r, i, r), number(r, r, j)]
-            assert all(d < t for d in deps), (R, K, task, t, deps)
+            assert all(d < t for d in deps), (R, task, t, deps)
