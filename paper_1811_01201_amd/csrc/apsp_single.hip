@@ -724,6 +724,17 @@ __global__ void finalize_kernel(const T *__restrict__ X, int64_t ld, T *__restri
     if (neg && status) *status = APSP_ERROR_NEGATIVE_CYCLE;
 }
 
+// The same for float32 distances solved in the caller's buffer: nothing to
+// map or copy, so only the diagonal is read.
+__global__ void finalize_diag_kernel(const float *__restrict__ X, int64_t ld, int64_t n, int32_t *__restrict__ status,
+                                     const int32_t *__restrict__ skip) {
+    if (skip && *skip != APSP_SUCCESS) return;
+    bool neg = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (X[i * ld + i] < 0.0f) neg = true;
+    if (neg && status) *status = APSP_ERROR_NEGATIVE_CYCLE;
+}
+
 // int32 distance solves in float32 arithmetic (policy ArF32W).  words[0]:
 // set when a watched value reached 2^23 (the float32 result may then be
 // inexact and is discarded); words[1]: gate of the int32 pass that follows
@@ -1946,8 +1957,16 @@ apsp_status_t solve_typed(T *dist, int32_t *pred, int64_t n, hipStream_t s,
             st = run_rounds_bs<ArPlain>(bs, tt, lookahead, X, ld, ArPlain{}, s, skip);
         if (st != APSP_SUCCESS) return st;
         // (a failed single-launch wait leaves APSP_ERROR_TIMEOUT in status: no wrap-up then)
-        enq((finalize_kernel<T>), dim3(grid_for(n * n)), dim3(256), s, X, ld, dist, n,
-                           status, single && status ? (const int32_t *)status : skip);
+        const int32_t *fskip = single && status ? (const int32_t *)status : skip;
+        if constexpr (std::is_same_v<T, float>) {
+            if (X == dist) {
+                enq(finalize_diag_kernel, dim3((unsigned)std::min<int64_t>(64, (n + 255) / 256)), dim3(256), s,
+                    (const float *)X, ld, n, status, fskip);
+                APSP_HIP(hipGetLastError());
+                return APSP_SUCCESS;
+            }
+        }
+        enq((finalize_kernel<T>), dim3(grid_for(n * n)), dim3(256), s, X, ld, dist, n, status, fskip);
     } else {
         // ld^2 8-byte elements, then one int32 mode word
         void *w = nullptr;

@@ -135,6 +135,32 @@ def test_negative_cycle_reported(orc, pred, dtype):
     assert st == 3
 
 
+@pytest.mark.parametrize("n", [256, 1024, 4160, 5120])
+def test_float32_in_place_negative_cycle_and_clean_diagonal(orc, n):
+    """Float32 distances solved in the caller's own buffer (n a multiple of
+    the block size) are checked on the diagonal only: a negative cycle
+    through two vertices is reported, a graph without one ends with status 0
+    and a zero diagonal (and, where the oracle is quick, every distance)."""
+    describe(f"float32 in place: negative cycle n={n}")
+    W = synth.single_f32int(n, p=0.05, seed=31 + n)
+    _, _, st = gpu_solve(W)
+    assert st == 0
+    a, b = 7, n - 3
+    Wn = W.copy()
+    Wn[a, b], Wn[b, a] = 5.0, -9.0
+    D, _, st = gpu_solve(Wn)
+    assert st == 3
+    assert D[a, a] < 0 and D[b, b] < 0
+    if n <= 1024:
+        D0, _, st0 = orc.fw(W)
+        D, _, st = gpu_solve(W)
+        assert st == 0 and st0 == oracle.OK
+        assert np.array_equal(D, D0.astype(np.float32))
+    else:
+        D, _, st = gpu_solve(W)
+        assert st == 0 and np.all(np.diag(D) == 0.0)
+
+
 def _deep_negative(n):
     """Every off-diagonal weight at minus the bound: negative cycles deep
     enough that plain 32-bit sums wrap long before the solve ends."""
