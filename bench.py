@@ -471,7 +471,7 @@ def single_leg(args, n):
     roofline = {
         "bound": "alu",
         "kernel": "phase3_kernel kRest (remaining-block min-plus products, 128x128 tiles, one launch per round "
-                  "from n=10240, two below)",
+                  "beside the next round's closure and panels)",
         "achieved": round(achieved, 3),
         "peak": round(PEAK_F32_VECTOR / 1e12, 1),
         "unit": "TFLOP/s-equivalent: 2 ops per (i,j,k) relaxation (one add, one min), as an FMA counts 2 flops",

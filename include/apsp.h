@@ -171,15 +171,14 @@ typedef struct {
                               arithmetic (with predecessors: the float32 route held), 0 if
                               from int32 arithmetic (the recurrence) */
     int32_t phase1;        /* 0 = automatic: the dataflow closure (3) for 4-byte distances
-                              with 128- or 256-wide blocks; elsewhere, with 256-wide blocks
-                              from a padded order of 10240, phase 1 is a blocked closure of
-                              the diagonal block
-                              inside one 256-thread workgroup (four 64-wide sub-rounds),
-                              and the two-stream split then issues the rest of phase 3 as
-                              one launch per round instead of two; 1 = always the
-                              one-step-per-barrier kernel; 2 = always the blocked closure
-                              (requires block_size 256; applies to the rounds on 4-byte
-                              distances, the fp64-key recurrence keeps the stepwise kernel);
+                              with 128- or 256-wide blocks, the one-step-per-barrier kernel
+                              elsewhere; 1 = always the one-step-per-barrier kernel;
+                              2 = always the blocked closure of the diagonal block inside
+                              one 256-thread workgroup (four 64-wide sub-rounds; requires
+                              block_size 256; applies to the rounds on 4-byte distances,
+                              the fp64-key recurrence keeps the stepwise kernel); with 2
+                              or 3 the two-stream split issues the rest of phase 3 as one
+                              launch per round instead of two;
                               3 = the dataflow closure: the diagonal block solved by the
                               blocked schedule over 32-wide sub-blocks, one workgroup per
                               sub-block in one launch (requires block_size 128 or 256;

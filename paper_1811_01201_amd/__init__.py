@@ -184,9 +184,12 @@ def solve(dist, pred=None, *, validate=False, block_size=0, use_graph=False, sta
              else 0.
     schedule : 0 automatic, 1 rounds in order on one stream, 2 the two-stream
              split at any size with three rounds or more, 3 all rounds in one
-             cooperative launch (distances, 64-wide blocks, int32 arithmetic
-             for int32; automatic for distance solves up to n = 4096).
-    phase1 : 0 automatic, 1 the stepwise diagonal kernel, 2 the blocked
+             task-graph launch (distances; 32- or 64-wide blocks; int32 in
+             int32 arithmetic, or float32; automatic for distance solves up
+             to a padded order of 4096).
+    phase1 : 0 automatic (the dataflow closure for 4-byte distances in 128-
+             and 256-wide blocks, else the stepwise kernel), 1 the stepwise
+             diagonal kernel, 2 the blocked
              closure of the diagonal block (block_size=256), 3 the dataflow
              closure over 32-wide sub-blocks (block_size 128 or 256; 4-byte
              distance rounds, the stepwise kernel for the fp64-key recurrence).

@@ -4,9 +4,10 @@ whole.
 The automatic configuration uses the two-stream split (phase 3 of round r
 as the next round's panels plus the rest, the rest on a second stream beside
 phases 1-2 of round r+1) only from a padded order of 4096 (3072 for the
-fp64-key recurrence), and the blocked closure of the diagonal block with one
-launch of the remaining phase-3 tiles per round only from 10240.  The
-options schedule=2 and phase1=2 force both at any size, so the exact
+fp64-key recurrence), and phase 1 as the dataflow closure of the diagonal
+block (4-byte distances in 128- and 256-wide blocks) with one launch of the
+remaining phase-3 tiles per round.  The options schedule=2 and phase1=2/3
+force the split and either closure at any size, so the exact
 launch sequence the headline runs is compared here element by element with
 the oracle, for every arithmetic (int32, float32 watched with its int32
 redo, float32 weights, the float32 predecessor route and the fp64-key
@@ -150,7 +151,8 @@ def test_split_fp64_key_recurrence(orc, n, kind):
 @pytest.mark.parametrize("kind", ["int", "f32", "sparse"])
 def test_split_two_launch_rest(orc, n, bs, tt, kind):
     """The split with the stepwise diagonal kernel and kRest in two launches
-    per round (the automatic schedule from 4096 to 10240)."""
+    per round (the schedule wherever phase 1 is the stepwise kernel: the
+    fp64-key recurrence, 64-wide blocks, or phase1=1)."""
     describe(f"schedule forced: split two-launch rest n={n} bs={bs} tt={tt} {kind}")
     W, D0, _ = _expect(orc, kind, n)
     kw = dict(block_size=bs, thread_tile=tt, schedule=2, phase1=1)

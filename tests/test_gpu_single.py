@@ -371,10 +371,11 @@ def test_paper_configuration_float32_pred_large_sampled_rows(orc, n, rows):
 def test_auto_configuration_mid_sizes(orc, n, kind, pred, alt_bs):
     """Sizes around the automatic configuration's switches: the fp64-key
     recurrence on two streams from ld = 3072, predecessors
-    by the float32 key product from n = 4096, 64-wide blocks
-    with 4 x 4 register blocks up to n = 5888, 128-wide below 7168, 256-wide
-    above, and from ld = 10240 phase 1 as the blocked closure of the diagonal
-    block (n = 10300 pads to ld = 10496).  The automatic route against an
+    by the float32 key product from n = 4096, distance rounds in 64-wide
+    blocks with 4 x 4 register blocks up to n = 4864 and 256-wide above (the
+    float32 predecessor route: 64-wide to 5888, 128-wide below 7168, 256-wide
+    above), phase 1 as the dataflow closure of 128- and 256-wide diagonal
+    blocks (n = 10300 pads to ld = 10496).  The automatic route against an
     independent configuration (another block size, int32 or fp64-key
     arithmetic, rounds in order) on every element, and sampled rows against
     the row oracle."""
