@@ -1,18 +1,17 @@
 """The single-launch schedule (all rounds of the blocked algorithm in one
-cooperative launch, two device-wide barriers per round) against the full
-oracle.
+ordinary launch of the task-graph kernel) against the full oracle.
 
 Section "Data Locality" orders each round as the diagonal block, then its
-block row and column, then the remaining blocks; the single launch keeps
-that order with barriers instead of launch boundaries, and closes the next
-round's diagonal block as soon as its own phase-3 tile is done.  Every size
-here runs with schedule=3 (forced) and is compared element by element with
-the oracle; the library's profile confirms that exactly one launch did the
-rounds.  Sizes span one round (n <= 64), ragged last blocks, and padded
-orders beyond the dataflow limit; up to n = 2048 the dataflow kernel runs
-(one workgroup per block, panels published once with ready words; int32 in
-32 x 32 blocks up to n = 1024, else 64 x 64), above it the barrier-phased
-kernel (two device-wide barriers per round).
+block row and column, then the remaining blocks; the single launch numbers
+those tasks so that every task's operands come from smaller numbers, lets
+workgroups claim numbers from a counter and wait on per-block round
+counters instead of launch boundaries, and closes the next round's diagonal
+block as soon as its own phase-3 product is done.  Every size here runs
+with schedule=3 (forced) and is compared element by element with the
+oracle; the library's profile confirms that exactly one launch did the
+rounds.  Sizes span one round (n <= 64), ragged last blocks and padded
+orders up to 3000 (int32 in 32 x 32 blocks up to a padded order of 768,
+else 64 x 64).
 Real-valued float32 weights are compared
 with the multi-launch schedule bit for bit (the same products over the same
 operands) and with the oracle within float32 rounding."""
@@ -94,9 +93,8 @@ def test_single_launch_real_weights_bitwise(orc, n):
 
 
 def test_single_launch_is_automatic_for_small_graphs(orc):
-    """Default options: the single launch up to a padded order of 4096 (the
-    dataflow kernel to n = 2048, the barrier-phased one above), the per-phase
-    launches beyond it."""
+    """Default options: the single launch up to a padded order of 4096, the
+    per-phase launches beyond it."""
     for n, single in ((1024, True), (2048, True), (2049, True), (4100, False)):
         describe(f"single launch: automatic choice n={n}")
         W = _graph("int", n)
@@ -114,7 +112,7 @@ def test_single_launch_is_automatic_for_small_graphs(orc):
 
 def test_single_launch_back_to_back_and_on_a_stream(orc):
     """Consecutive solves of different sizes on one stream reuse one set of
-    barrier words (cleared before each launch): every result stays exact."""
+    task words (cleared before each launch): every result stays exact."""
     import torch
 
     import paper_1811_01201_amd as apsp
