@@ -93,9 +93,10 @@ def test_single_launch_real_weights_bitwise(orc, n):
 
 
 def test_single_launch_is_automatic_for_small_graphs(orc):
-    """Default options: the single launch up to a padded order of 4096, the
-    per-phase launches beyond it."""
-    for n, single in ((1024, True), (2048, True), (2049, True), (4100, False)):
+    """Default options: the single launch up to a padded order of 4096 (int32
+    at 4096 itself too, ahead of the float32 route), the per-phase launches
+    beyond it."""
+    for n, single in ((1024, True), (2048, True), (2049, True), (4096, True), (4100, False)):
         describe(f"single launch: automatic choice n={n}")
         W = _graph("int", n)
         D, st, prof = _run(W)
@@ -103,6 +104,13 @@ def test_single_launch_is_automatic_for_small_graphs(orc):
         if n < 4096:  # (the per-phase launches have parity tests of their own)
             D0, _, _ = oracle_expect(orc, W)
             assert first_mismatch(D, D0) is None, first_mismatch(D, D0)
+        elif single:  # the per-phase rounds in float32 arithmetic, element by element
+            D1, st1, _ = _run(W, profile=False, schedule=1)
+            assert st1 == 0
+            assert first_mismatch(D, D1) is None, first_mismatch(D, D1)
+            for src in (0, n // 2 + 1, n - 1):
+                dr, _, s_ = orc.row(W, src)
+                assert s_ == 0 and np.array_equal(D[src], dr.astype(D.dtype)), src
         if single:
             _assert_one_launch(prof)
         else:
