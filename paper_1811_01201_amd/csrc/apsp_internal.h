@@ -448,11 +448,13 @@ struct TileProductDMA {
 #pragma unroll
             for (int g = 0; g < GN; ++g)
                 ld16(Cbase + (coff + (uint32_t)(TY * m) * ld + g * GSTRIDE), &c[m][g * VW]);
-        bool big = false;
-        if constexpr (WATCH) big = any_big(ar, c);
+        // (the inputs' check raises at once: nothing live across the products)
+        if constexpr (WATCH && Ar::kWatch) {
+            if (any_big(ar, c)) ar.raise();
+        }
         accumulate(sm, c, Abase, Bbase, ld, kcount, tx, ty, ar);
         if constexpr (WATCH && Ar::kWatch) {
-            if (big || any_big(ar, c)) ar.raise();
+            if (any_big(ar, c)) ar.raise();
         }
 #pragma unroll
         for (int m = 0; m < TM; ++m)

@@ -21,10 +21,16 @@
 #include "apsp_internal.h"
 
 // Launch tuning (measured on MI355X): phase-3 waves per SIMD for 4-byte
-// elements on 128 x 128 tiles (163 VGPRs) and for 8-byte keys; kRest
-// launches per round under the two-stream schedule.
+// elements on 128 x 128 tiles (157 VGPRs) and for 8-byte keys; phase-2
+// waves per SIMD for 4-byte elements (at most 168 VGPRs, so a phase-2
+// workgroup fits on a compute unit beside two phase-3 workgroups and starts
+// while a remaining-block launch runs: at n = 16384 the next round's panels
+// then finish mid-launch instead of 33 us after it, 110.3 vs 110.6 ms; at
+// 32768 848.2 vs 851.6 ms); kRest launches per round under the two-stream
+// schedule.
 constexpr int kP3Waves4 = 3;
 constexpr int kP3Waves8 = 2;
+constexpr int kP2Waves4 = 3;
 constexpr int kRestChunks = 2;
 
 namespace apsp {
@@ -148,7 +154,7 @@ constexpr int elem_size<char>() {
 
 template <class Ar, class Alt, int BS, int P2W, int TT>
 __global__ void __launch_bounds__((BS / TT) * (P2W / TT))
-__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? 2 : 1)))
+__attribute__((amdgpu_waves_per_eu(sizeof(typename Ar::T) == 4 ? kP2Waves4 : 1)))
 phase2_kernel(void *X, int64_t ld, int64_t r0, int nt, Ar ar, Alt alt,
               const int32_t *__restrict__ mode, const int32_t *__restrict__ skip) {
     if (skip && *skip != APSP_SUCCESS) return;
