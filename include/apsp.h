@@ -39,8 +39,10 @@
  *              for short-hop paths.
  *   Memory     Pointers named dist/pred/packed_* are DEVICE pointers owned by
  *              the caller.  The library may allocate internal device
- *              workspace (kept per device and reused; released by
- *              apsp_release_workspace).
+ *              workspace (kept per device and stream and reused -- the work
+ *              matrix, a second stream and its events, and about 0.5 MiB of
+ *              phase-1 closure scratch per stream that solves run on;
+ *              released by apsp_release_workspace).
  *   Streams    apsp_solve* and apsp_batch_plan_execute enqueue work on the
  *              given hipStream_t (NULL = the legacy default stream) and
  *              return without waiting.  Argument errors are detected on the
@@ -300,8 +302,10 @@ apsp_status_t apsp_profile_end(apsp_profile_t *out);
  * device; allocates 16 bytes of device memory for the duration of the call. */
 apsp_status_t apsp_probe_valu(int32_t kind, double *lane_instr_per_s, double *elapsed_ms);
 
-/* Release the calling device's internal workspace and cached graphs.
- * Must not overlap with solves in flight on that device. */
+/* Release the calling device's internal workspace, cached graphs and
+ * per-stream helpers (second streams and their events, closure scratch);
+ * later solves make them again.  Must not overlap with solves in flight
+ * on that device. */
 apsp_status_t apsp_release_workspace(void);
 
 /* ------------------------------------------------------------------ paths

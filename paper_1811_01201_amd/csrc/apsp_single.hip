@@ -1342,13 +1342,27 @@ struct AuxStream {
 std::mutex g_aux_mu;
 std::map<std::pair<int, hipStream_t>, AuxStream> g_aux;
 
+void aux_destroy(AuxStream &a) {
+    if (a.panels) (void)hipEventDestroy(a.panels);
+    if (a.rest) (void)hipEventDestroy(a.rest);
+    if (a.s) (void)hipStreamDestroy(a.s);
+    a = AuxStream{};
+}
+
 apsp_status_t aux_stream(int dev, hipStream_t s, AuxStream **out) {
     std::lock_guard<std::mutex> lk(g_aux_mu);
     AuxStream &a = g_aux[{dev, s}];
     if (!a.s) {
-        APSP_HIP(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
-        APSP_HIP(hipEventCreateWithFlags(&a.panels, hipEventDisableTiming));
-        APSP_HIP(hipEventCreateWithFlags(&a.rest, hipEventDisableTiming));
+        AuxStream n;  // all three or none
+        hipError_t e = hipStreamCreateWithFlags(&n.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n.panels, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&n.rest, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            aux_destroy(n);
+            return APSP_ERROR_HIP;
+        }
+        a = n;
     }
     *out = &a;
     return APSP_SUCCESS;
@@ -2498,6 +2512,17 @@ apsp_status_t apsp_release_workspace(void) {
     {
         std::lock_guard<std::mutex> lg(g_graph_mu);
         drop_graphs_locked(dev);  // graphs refer to the work memory freed below
+    }
+    {
+        std::lock_guard<std::mutex> la(g_aux_mu);
+        for (auto it = g_aux.begin(); it != g_aux.end();) {
+            if (it->first.first == dev) {
+                aux_destroy(it->second);
+                it = g_aux.erase(it);
+            } else {
+                ++it;
+            }
+        }
     }
     {
         std::lock_guard<std::mutex> lc(g_closure_mu);

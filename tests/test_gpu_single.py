@@ -494,6 +494,40 @@ def test_lookahead_schedule_matches_in_order(orc, n, bs, kind, pred):
         assert first_mismatch(Pa, P0) is None and first_mismatch(Pb, P0) is None
 
 
+def test_release_workspace_then_solve_again(orc):
+    """apsp_release_workspace frees the work matrices, cached graphs, second
+    streams and closure scratch; solves after it make them again and give
+    the same result (two-stream split with the closure at n = 5000, on a
+    side stream, the default stream and replayed from a captured graph)."""
+    import torch
+
+    import paper_1811_01201_amd as apsp
+    describe("release_workspace, then solve again")
+    n = 5000
+    W = _graph("int", n, seed=5000)
+    w = torch.from_numpy(W).cuda()
+    s = torch.cuda.Stream()
+
+    def solve(stream, **kw):
+        d = w.clone()
+        st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        apsp.solve(d, status=st, stream=stream, **kw)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        return d.cpu().numpy()
+
+    D1 = solve(s)
+    apsp.release_workspace()
+    for D in (solve(s), solve(None), solve(s, use_graph=True), solve(s, use_graph=True)):
+        assert first_mismatch(D, D1) is None, first_mismatch(D, D1)
+    apsp.release_workspace()
+    assert first_mismatch(solve(s), D1) is None
+    for src in (0, n // 2, n - 1):
+        dr, _, st = orc.row(W, src)
+        assert st == 0 and np.array_equal(D1[src], dr.astype(D1.dtype)), src
+
+
 def test_concurrent_solves_on_streams(orc):
     """Solves enqueued on different streams at once (each with its own
     auxiliary stream and work memory) all match the oracle."""
